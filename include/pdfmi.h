@@ -1,0 +1,176 @@
+/*
+ * pdfmi.h -- C ABI of libpdfmi.so: parton-distribution and alpha_s
+ * interpolation on AMD MI355X (gfx950).
+ *
+ * The operations are those of Carrazza, Cruz-Martinez, Rossi, "PDFFlow: parton
+ * distribution functions on GPU": evaluate x*f(x,Q^2) for arrays of points and
+ * a set of flavours (section 2.1, the xfxQ2 / xfxQ2_allpid methods of figure 1)
+ * by log-bicubic interpolation on knot grids split into Q^2 sub-grids at
+ * flavour thresholds, with extrapolation outside the grid (section 2.2, figure
+ * 1 INTERPOLATE / EXTRAPOLATE), and alpha_s(Q^2) by log-cubic interpolation
+ * with constant extrapolation (section 2.3).
+ *
+ * Interpolation rule (the paper defers to LHAPDF6 and prints no formula; this
+ * library's reading): cubic Hermite in ln x, then in ln Q^2, with slopes from
+ * finite differences (mean of the two adjacent secants inside a sub-grid, the
+ * single secant at a sub-grid edge).  Knot search compares raw FP64 values.  A
+ * Q^2 equal to a threshold knot belongs to the upper sub-grid.  Below x_min the
+ * value is continued in ln x from the first two x knots; above Q^2_max in
+ * ln Q^2 from the last two Q^2 knots; below Q^2_min by an anomalous-dimension
+ * power law; corners take x first.
+ *
+ * Conventions
+ *   - Return value: PDF_OK (0) or a negative pdf_status.  pdf_last_error()
+ *     gives a message for the last failure on the calling thread.
+ *   - Load inputs are host memory and are copied; the caller may free them on
+ *     return.  Query inputs and outputs are device pointers owned by the caller
+ *     that must stay valid until the work queued on `stream` has completed.
+ *   - Query calls are asynchronous on `stream` (a hipStream_t; NULL = the
+ *     default stream).  Argument errors are detected before anything is queued
+ *     and nothing is written then.
+ *   - Per-point domain errors (x <= 0, x > x_max, Q^2 <= 0, NaN/inf) are not
+ *     API errors: those points get NaN in every requested column and add one
+ *     to a device-side counter read with pdf_error_count().
+ *   - Flavours are PDG ids: -6..-1, 1..6 quarks, 21 gluon; 0 is accepted as
+ *     the gluon.  A valid flavour that the grid does not store evaluates to 0.
+ *   - Loading/unloading must not race with queries that use the same member
+ *     (single writer).  All calls use the HIP device current on the calling
+ *     thread when the library initialises (device 0 by default).
+ */
+#ifndef PDFMI_H
+#define PDFMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PDF_OK = 0,
+    PDF_ERR_ARG = -1,     /* bad argument (null pointer, negative size, ...) */
+    PDF_ERR_GRID = -2,    /* malformed grid passed to a load call */
+    PDF_ERR_MEMBER = -3,  /* unknown member id */
+    PDF_ERR_PID = -4,     /* flavour id outside {-6..6, 21} or duplicated in a load */
+    PDF_ERR_NOMEM = -5,   /* device or host allocation failed */
+    PDF_ERR_DEVICE = -6,  /* HIP runtime / launch failure, or no usable GPU */
+    PDF_ERR_STATE = -7    /* call not valid in the current state (e.g. no alpha_s table) */
+} pdf_status;
+
+/* hipStream_t, passed as an opaque pointer so this header needs no HIP include */
+typedef void* pdf_stream_t;
+
+/*
+ * Load one member's grid (section 2.2 data: LHAPDF-style sub-grids).
+ *   n_subgrids     K >= 1 sub-grids in increasing Q^2 order
+ *   subgrid_shape  [K][2] = {nx, nq}, each >= 2
+ *   n_pids, pids   the stored flavour columns, in column order (no duplicates)
+ *   knots          for each sub-grid: nx x knots then nq Q^2 knots, all strictly
+ *                  increasing; x knots in (0, 1]; every sub-grid has the same
+ *                  first and last x knot; the last Q^2 knot of sub-grid k equals
+ *                  the first of sub-grid k+1 (the threshold is repeated)
+ *   values         for each sub-grid: x*f as [ix][iq][column] (column fastest),
+ *                  finite, concatenated over sub-grids
+ *   member_out     receives the member id (>= 0)
+ * Errors: PDF_ERR_ARG (null pointers), PDF_ERR_GRID (shape/knots/values),
+ * PDF_ERR_PID, PDF_ERR_NOMEM, PDF_ERR_DEVICE.  Synchronous: the grid is
+ * resident on the device when the call returns.
+ */
+int pdf_load_grid(int32_t n_subgrids, const int32_t* subgrid_shape,
+                  int32_t n_pids, const int32_t* pids,
+                  const double* knots, const double* values,
+                  int32_t* member_out);
+
+/* Release a member's device memory.  PDF_ERR_MEMBER if unknown. */
+int pdf_unload(int32_t member);
+
+/*
+ * Load the alpha_s table (section 2.3: nodes from the set's metadata).
+ * q2_knots non-decreasing, > 0; a value repeated once starts a new segment
+ * (flavour threshold) and a Q^2 equal to it uses the upper segment; every
+ * segment has >= 2 knots.  alphas finite.  Replaces any previous table.
+ */
+int pdf_load_alphas(int32_t n_knots, const double* q2_knots, const double* alphas);
+
+/*
+ * x*f for n points and n_pids flavours, FP64 arithmetic (sections 2.1-2.2).
+ *   member        id from pdf_load_grid
+ *   pids, n_pids  HOST array of requested flavours (copied into the launch);
+ *                 pids == NULL requests every stored column in load order
+ *                 (n_pids is then ignored)
+ *   x, q2         DEVICE arrays of n doubles (momentum fraction, Q^2 in GeV^2)
+ *   out           DEVICE array of n * P doubles, point-major:
+ *                 out[i * P + j] = x f_{pid j}(x[i], q2[i]), P = number of
+ *                 requested flavours
+ * n == 0 is a no-op.  Errors: PDF_ERR_MEMBER, PDF_ERR_PID, PDF_ERR_ARG,
+ * PDF_ERR_DEVICE.
+ */
+int pdf_xfxq2(int32_t member, const int32_t* pids, int32_t n_pids,
+              const double* x, const double* q2, int64_t n,
+              double* out, pdf_stream_t stream);
+
+/*
+ * As pdf_xfxq2 with FP32 bulk arithmetic: validation, sub-grid choice, knot
+ * search and the log transforms in FP64; Hermite weights, grid values (rounded
+ * to FP32 at load) and the accumulation in FP32; extrapolation combined in
+ * FP64 from the FP32 anchor values; FP32 output.
+ */
+int pdf_xfxq2_f32(int32_t member, const int32_t* pids, int32_t n_pids,
+                  const double* x, const double* q2, int64_t n,
+                  float* out, pdf_stream_t stream);
+
+/*
+ * alpha_s(Q^2) for n points (section 2.3): cubic Hermite in ln Q^2 inside a
+ * segment, constant below the first and above the last knot; NaN (and the
+ * error counter) for Q^2 <= 0 or non-finite.  q2 and out are DEVICE arrays of
+ * n doubles.  PDF_ERR_STATE if no table is loaded.
+ */
+int pdf_alphas_q2(const double* q2, int64_t n, double* out, pdf_stream_t stream);
+
+/*
+ * Location of each point in a member's grid, as used by pdf_xfxq2: sub-grid k
+ * (the largest whose first Q^2 knot is <= q2, clamped), x cell ix and Q^2 cell
+ * iq (largest i <= n-2 with knot_i <= value, clamped to the grid), and region
+ * bits (1 x < x_min, 2 Q^2 < Q^2_min, 4 Q^2 > Q^2_max, 8 invalid; an invalid
+ * point gets k = ix = iq = -1).  All four outputs are DEVICE arrays of n.
+ */
+int pdf_locate(int32_t member, const double* x, const double* q2, int64_t n,
+               int32_t* subgrid, int32_t* ix, int32_t* iq, int8_t* region,
+               pdf_stream_t stream);
+
+/*
+ * Number of invalid query points seen since the last reset (all query entry
+ * points add to it).  Synchronises `stream` first.  reset != 0 zeroes it.
+ */
+int pdf_error_count(int64_t* count_out, int32_t reset, pdf_stream_t stream);
+
+/*
+ * Host-only checks run by pdf_load_grid / pdf_load_alphas before any device
+ * work (same arguments, same error codes); they touch no GPU state and can be
+ * called on a machine without a GPU.
+ */
+int pdf_validate_grid(int32_t n_subgrids, const int32_t* subgrid_shape,
+                      int32_t n_pids, const int32_t* pids,
+                      const double* knots, const double* values);
+int pdf_validate_alphas(int32_t n_knots, const double* q2_knots, const double* alphas);
+
+/*
+ * Tuning: whether pdf_xfxq2 / pdf_xfxq2_f32 stage a member's whole grid in
+ * each workgroup's LDS (160 KB per CU on gfx950) when it fits.
+ *   0 = automatic (stage when it fits and the call has enough points to pay
+ *       for one grid copy per workgroup), 1 = never, 2 = whenever it fits.
+ * Results are identical under every policy.
+ */
+int pdf_set_lds_policy(int32_t policy);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* pdf_last_error(void);
+
+/* Release every member, the alpha_s table and library state. */
+int pdf_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDFMI_H */

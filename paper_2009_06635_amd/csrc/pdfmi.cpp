@@ -1,0 +1,491 @@
+// Host runtime of libpdfmi.so: argument and grid validation, member registry,
+// per-cell Hermite coefficients, device packing/upload, flavour->column tables,
+// error state and kernel launches.  Implements include/pdfmi.h.
+#include "pdfmi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pdfmi_dev.h"
+
+namespace pdfmi {
+size_t xfxq2_record_bytes(bool f32);
+hipError_t launch_xfxq2_f64(const MemberDev&, const ReqCols&, const double*, const double*, int64_t, double*,
+                            unsigned long long*, int, double, int, hipStream_t);
+hipError_t launch_xfxq2_f32(const MemberDev&, const ReqCols&, const double*, const double*, int64_t, float*,
+                            unsigned long long*, int, double, int, hipStream_t);
+hipError_t launch_locate(const MemberDev&, const double*, const double*, int64_t, int32_t*, int32_t*, int32_t*,
+                         int8_t*, int, hipStream_t);
+hipError_t launch_alphas(const AlphasDev&, const double*, int64_t, double*, unsigned long long*, int, hipStream_t);
+}  // namespace pdfmi
+
+using namespace pdfmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? PDF_ERR_NOMEM : PDF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct Member {
+  bool used = false;
+  MemberDev dev{};
+  void* dmem = nullptr;
+  std::vector<int> pids;   // stored column -> pid (0 normalised to 21)
+  int64_t grid_elems = 0;  // padded value elements
+  double invL01 = 0.0;
+};
+
+std::mutex g_mu;
+std::vector<Member> g_members;
+bool g_init = false;
+int g_ncu = 0;
+unsigned long long* g_nerr = nullptr;
+bool g_has_alphas = false;
+AlphasDev g_alphas{};
+void* g_alphas_mem = nullptr;
+int g_lds_policy = 0;  // 0 auto, 1 never stage the grid in LDS, 2 whenever it fits
+constexpr size_t kLdsBytes = 160 * 1024;
+
+int ensure_init() {
+  if (g_init) return PDF_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  e = hipDeviceGetAttribute(&g_ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute");
+  e = hipMalloc(&g_nerr, sizeof(unsigned long long));
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc(error counter)");
+  e = hipMemset(g_nerr, 0, sizeof(unsigned long long));
+  if (e != hipSuccess) return fail_hip(e, "hipMemset(error counter)");
+  g_init = true;
+  return PDF_OK;
+}
+
+bool valid_pid(int p) { return (p >= -6 && p <= 6) || p == 21; }
+int norm_pid(int p) { return p == 0 ? 21 : p; }
+
+// Hermite coefficients of every cell of a strictly increasing 1D table
+// (see CellCoef); edge flags within [lo, hi].
+void cell_coefs(const double* t, int n, CellCoef* out) {
+  std::vector<double> D(n - 1);
+  for (int i = 0; i + 1 < n; ++i) D[i] = std::log(t[i + 1] / t[i]);
+  for (int i = 0; i + 1 < n; ++i) {
+    CellCoef c{};
+    c.t0 = t[i];
+    c.t1 = t[i + 1];
+    c.inv_t0 = 1.0 / t[i];
+    c.invD = 1.0 / D[i];
+    const bool L = i > 0, R = i + 1 < n - 1;
+    if (L) {
+      const double rl = D[i] / D[i - 1];
+      c.am1 = -0.5 * rl;
+      c.a0 = 0.5 * rl - 0.5;
+      c.a1 = 0.5;
+    } else {
+      c.am1 = 0.0;
+      c.a0 = -1.0;
+      c.a1 = 1.0;
+    }
+    if (R) {
+      const double rr = D[i] / D[i + 1];
+      c.b0 = -0.5;
+      c.b1 = 0.5 - 0.5 * rr;
+      c.b2 = 0.5 * rr;
+    } else {
+      c.b0 = -1.0;
+      c.b1 = 1.0;
+      c.b2 = 0.0;
+    }
+    out[i] = c;
+  }
+}
+
+bool strictly_increasing(const double* t, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(t[i])) return false;
+  for (int i = 0; i + 1 < n; ++i)
+    if (!(t[i] < t[i + 1])) return false;
+  return true;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int check_stream_args(const void* a, const void* b, int64_t n) {
+  if (n < 0) return fail(PDF_ERR_ARG, "n < 0");
+  if (n > 0 && (!a || !b)) return fail(PDF_ERR_ARG, "null device pointer");
+  return PDF_OK;
+}
+
+int build_req(const Member& M, const int32_t* pids, int32_t n_pids, ReqCols& rc) {
+  if (!pids) {
+    if ((int)M.pids.size() > kMaxReq) return fail(PDF_ERR_ARG, "too many stored flavours for one call");
+    rc.n = (int)M.pids.size();
+    for (int j = 0; j < rc.n; ++j) rc.col[j] = j;
+    return PDF_OK;
+  }
+  if (n_pids < 1 || n_pids > kMaxReq) return fail(PDF_ERR_ARG, "n_pids must be in [1, %d]", kMaxReq);
+  rc.n = n_pids;
+  for (int j = 0; j < n_pids; ++j) {
+    if (!valid_pid(pids[j])) return fail(PDF_ERR_PID, "invalid flavour id %d", pids[j]);
+    const int p = norm_pid(pids[j]);
+    rc.col[j] = -1;
+    for (size_t c = 0; c < M.pids.size(); ++c)
+      if (M.pids[c] == p) rc.col[j] = (int)c;
+  }
+  return PDF_OK;
+}
+
+Member* get_member(int32_t id) {
+  if (id < 0 || id >= (int32_t)g_members.size() || !g_members[id].used) return nullptr;
+  return &g_members[id];
+}
+
+// Stage the whole grid in LDS for this call?
+int lds_grid_elems(const Member& M, bool f32, int64_t n) {
+  if (g_lds_policy == 1) return 0;
+  const size_t bytes = (size_t)M.grid_elems * (f32 ? 4 : 8) + xfxq2_record_bytes(f32);
+  if (bytes > kLdsBytes - 1024) return 0;
+  if (g_lds_policy == 0) {
+    // each workgroup pays one grid copy; require enough tiles to amortise it
+    const int64_t tiles = (n + 255) / 256;
+    const int per_cu = (int)(kLdsBytes / bytes);
+    if (tiles < (int64_t)4 * g_ncu * (per_cu > 0 ? per_cu : 1)) return 0;
+  }
+  return (int)M.grid_elems;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+
+extern "C" int pdf_validate_grid(int32_t K, const int32_t* shape, int32_t P, const int32_t* pids,
+                                 const double* knots, const double* values) {
+  if (!shape || !pids || !knots || !values) return fail(PDF_ERR_ARG, "null pointer");
+  if (K < 1 || K > kMaxSub) return fail(PDF_ERR_GRID, "n_subgrids must be in [1, %d]", kMaxSub);
+  if (P < 1 || P > 64) return fail(PDF_ERR_GRID, "n_pids must be in [1, 64]");
+  for (int c = 0; c < P; ++c) {
+    if (!valid_pid(pids[c])) return fail(PDF_ERR_PID, "invalid stored flavour id %d", pids[c]);
+    for (int d = 0; d < c; ++d)
+      if (norm_pid(pids[d]) == norm_pid(pids[c])) return fail(PDF_ERR_PID, "duplicated flavour id %d", pids[c]);
+  }
+  int64_t ko = 0, vo = 0;
+  double x0 = 0, x1 = 0, qprev = 0;
+  for (int k = 0; k < K; ++k) {
+    const int nx = shape[2 * k], nq = shape[2 * k + 1];
+    if (nx < 2 || nq < 2 || nx > (1 << 20) || nq > (1 << 20))
+      return fail(PDF_ERR_GRID, "sub-grid %d: need nx >= 2 and nq >= 2", k);
+    const double* xk = knots + ko;
+    const double* qk = knots + ko + nx;
+    if (!strictly_increasing(xk, nx) || !(xk[0] > 0.0) || !(xk[nx - 1] <= 1.0))
+      return fail(PDF_ERR_GRID, "sub-grid %d: x knots must be strictly increasing in (0, 1]", k);
+    if (!strictly_increasing(qk, nq) || !(qk[0] > 0.0))
+      return fail(PDF_ERR_GRID, "sub-grid %d: Q^2 knots must be strictly increasing and > 0", k);
+    if (k == 0) {
+      x0 = xk[0];
+      x1 = xk[nx - 1];
+    } else {
+      if (xk[0] != x0 || xk[nx - 1] != x1) return fail(PDF_ERR_GRID, "sub-grid %d: x range differs from sub-grid 0", k);
+      if (qk[0] != qprev) return fail(PDF_ERR_GRID, "sub-grid %d: first Q^2 knot must repeat the previous last knot", k);
+    }
+    qprev = qk[nq - 1];
+    const int64_t nv = (int64_t)nx * nq * P;
+    for (int64_t i = 0; i < nv; ++i)
+      if (!std::isfinite(values[vo + i])) return fail(PDF_ERR_GRID, "sub-grid %d: non-finite value", k);
+    ko += nx + nq;
+    vo += nv;
+  }
+  if (vo > ((int64_t)1 << 31) / 2) return fail(PDF_ERR_GRID, "grid too large");
+  return PDF_OK;
+}
+
+extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const int32_t* pids, const double* knots,
+                             const double* values, int32_t* member_out) {
+  if (!member_out) return fail(PDF_ERR_ARG, "null member_out");
+  int rc = pdf_validate_grid(K, shape, P, pids, knots, values);
+  if (rc != PDF_OK) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  if ((rc = ensure_init()) != PDF_OK) return rc;
+
+  Member M;
+  M.used = true;
+  for (int c = 0; c < P; ++c) M.pids.push_back(norm_pid(pids[c]));
+  MemberDev& d = M.dev;
+  d.K = K;
+  d.P = P;
+  // host staging of knots, cells and padded values
+  std::vector<double> hk;
+  std::vector<CellCoef> hc;
+  int64_t nvals = 0;
+  for (int k = 0; k < K; ++k) {
+    const int nx = shape[2 * k], nq = shape[2 * k + 1];
+    SubDesc& S = d.sub[k];
+    S.nx = nx;
+    S.nq = nq;
+    S.nxp = nx < 4 ? 4 : nx;
+    S.nqp = nq < 4 ? 4 : nq;
+    S.val_off = nvals;
+    nvals += (int64_t)S.nxp * S.nqp * P;
+  }
+  M.grid_elems = nvals;
+  std::vector<double> hv((size_t)nvals, 0.0);
+  int64_t ko = 0, vo = 0;
+  for (int k = 0; k < K; ++k) {
+    SubDesc& S = d.sub[k];
+    const double* xk = knots + ko;
+    const double* qk = knots + ko + S.nx;
+    S.xk_off = (int)hk.size();
+    hk.insert(hk.end(), xk, xk + S.nx);
+    S.qk_off = (int)hk.size();
+    hk.insert(hk.end(), qk, qk + S.nq);
+    S.xc_off = (int)hc.size();
+    hc.resize(hc.size() + S.nx - 1);
+    cell_coefs(xk, S.nx, &hc[S.xc_off]);
+    S.qc_off = (int)hc.size();
+    hc.resize(hc.size() + S.nq - 1);
+    cell_coefs(qk, S.nq, &hc[S.qc_off]);
+    S.qfirst = qk[0];
+    for (int ix = 0; ix < S.nx; ++ix)
+      for (int iq = 0; iq < S.nq; ++iq)
+        for (int c = 0; c < P; ++c)
+          hv[S.val_off + ((int64_t)ix * S.nqp + iq) * P + c] = values[vo + ((int64_t)ix * S.nq + iq) * P + c];
+    ko += S.nx + S.nq;
+    vo += (int64_t)S.nx * S.nq * P;
+  }
+  d.xmin = knots[0];
+  d.xmax = knots[shape[0] - 1];
+  d.qmin = d.sub[0].qfirst;
+  d.qmax = hk[d.sub[K - 1].qk_off + d.sub[K - 1].nq - 1];
+  M.invL01 = hc[d.sub[0].qc_off].invD;
+
+  const size_t bk = align_up(hk.size() * sizeof(double), 256);
+  const size_t bc = align_up(hc.size() * sizeof(CellCoef), 256);
+  const size_t b64 = align_up((size_t)nvals * sizeof(double), 256);
+  const size_t b32 = align_up((size_t)nvals * sizeof(float), 256);
+  std::vector<unsigned char> blob(bk + bc + b64 + b32, 0);
+  std::memcpy(blob.data(), hk.data(), hk.size() * sizeof(double));
+  std::memcpy(blob.data() + bk, hc.data(), hc.size() * sizeof(CellCoef));
+  std::memcpy(blob.data() + bk + bc, hv.data(), (size_t)nvals * sizeof(double));
+  float* f32 = reinterpret_cast<float*>(blob.data() + bk + bc + b64);
+  for (int64_t i = 0; i < nvals; ++i) f32[i] = (float)hv[i];
+
+  hipError_t e = hipMalloc(&M.dmem, blob.size());
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc(grid)");
+  e = hipMemcpy(M.dmem, blob.data(), blob.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(M.dmem);
+    return fail_hip(e, "hipMemcpy(grid)");
+  }
+  unsigned char* base = static_cast<unsigned char*>(M.dmem);
+  d.knots = reinterpret_cast<const double*>(base);
+  d.cells = reinterpret_cast<const CellCoef*>(base + bk);
+  d.v64 = reinterpret_cast<const double*>(base + bk + bc);
+  d.v32 = reinterpret_cast<const float*>(base + bk + bc + b64);
+
+  for (size_t i = 0; i < g_members.size(); ++i) {
+    if (!g_members[i].used) {
+      g_members[i] = M;
+      *member_out = (int32_t)i;
+      return PDF_OK;
+    }
+  }
+  g_members.push_back(M);
+  *member_out = (int32_t)(g_members.size() - 1);
+  return PDF_OK;
+}
+
+extern "C" int pdf_unload(int32_t member) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  Member* M = get_member(member);
+  if (!M) return fail(PDF_ERR_MEMBER, "unknown member %d", member);
+  hipError_t e = hipFree(M->dmem);
+  *M = Member();
+  if (e != hipSuccess) return fail_hip(e, "hipFree(grid)");
+  return PDF_OK;
+}
+
+extern "C" int pdf_validate_alphas(int32_t n, const double* q2k, const double* a) {
+  if (!q2k || !a) return fail(PDF_ERR_ARG, "null pointer");
+  if (n < 2) return fail(PDF_ERR_GRID, "alpha_s table needs >= 2 knots");
+  int seg_len = 1, nseg = 1;
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(q2k[i]) || !(q2k[i] > 0.0) || !std::isfinite(a[i]))
+      return fail(PDF_ERR_GRID, "alpha_s knot %d: need finite Q^2 > 0 and finite value", i);
+    if (i == 0) continue;
+    if (q2k[i] == q2k[i - 1]) {
+      if (seg_len < 2) return fail(PDF_ERR_GRID, "alpha_s segment ending at knot %d has < 2 knots", i);
+      if (++nseg > kMaxSeg) return fail(PDF_ERR_GRID, "more than %d alpha_s segments", kMaxSeg);
+      seg_len = 1;
+    } else if (q2k[i] > q2k[i - 1]) {
+      ++seg_len;
+    } else {
+      return fail(PDF_ERR_GRID, "alpha_s Q^2 knots must be non-decreasing");
+    }
+  }
+  if (seg_len < 2) return fail(PDF_ERR_GRID, "last alpha_s segment has < 2 knots");
+  return PDF_OK;
+}
+
+extern "C" int pdf_load_alphas(int32_t n, const double* q2k, const double* a) {
+  int rc = pdf_validate_alphas(n, q2k, a);
+  if (rc != PDF_OK) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  if ((rc = ensure_init()) != PDF_OK) return rc;
+  AlphasDev A{};
+  A.n = n;
+  A.nseg = 0;
+  int lo = 0;
+  for (int i = 1; i <= n; ++i) {
+    if (i == n || q2k[i] == q2k[i - 1]) {
+      A.seg_lo[A.nseg] = lo;
+      A.seg_hi[A.nseg] = i - 1;
+      A.seg_first[A.nseg] = q2k[lo];
+      ++A.nseg;
+      lo = i;
+    }
+  }
+  std::vector<CellCoef> hc((size_t)n);  // cell j valid when j, j+1 share a segment
+  for (int s = 0; s < A.nseg; ++s) cell_coefs(q2k + A.seg_lo[s], A.seg_hi[s] - A.seg_lo[s] + 1, &hc[A.seg_lo[s]]);
+  const size_t bk = align_up((size_t)n * 8, 256), bv = align_up((size_t)n * 8, 256);
+  std::vector<unsigned char> blob(bk + bv + hc.size() * sizeof(CellCoef), 0);
+  std::memcpy(blob.data(), q2k, (size_t)n * 8);
+  std::memcpy(blob.data() + bk, a, (size_t)n * 8);
+  std::memcpy(blob.data() + bk + bv, hc.data(), hc.size() * sizeof(CellCoef));
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, blob.size());
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc(alpha_s)");
+  e = hipMemcpy(mem, blob.data(), blob.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    return fail_hip(e, "hipMemcpy(alpha_s)");
+  }
+  unsigned char* b = static_cast<unsigned char*>(mem);
+  A.knots = reinterpret_cast<const double*>(b);
+  A.vals = reinterpret_cast<const double*>(b + bk);
+  A.cells = reinterpret_cast<const CellCoef*>(b + bk + bv);
+  if (g_alphas_mem) (void)hipFree(g_alphas_mem);
+  g_alphas_mem = mem;
+  g_alphas = A;
+  g_has_alphas = true;
+  return PDF_OK;
+}
+
+template <typename T>
+static int xfxq2_impl(int32_t member, const int32_t* pids, int32_t n_pids, const double* x, const double* q2,
+                      int64_t n, T* out, pdf_stream_t stream) {
+  int rc = check_stream_args(x, q2, n);
+  if (rc != PDF_OK) return rc;
+  if (n > 0 && !out) return fail(PDF_ERR_ARG, "null out");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Member* M = get_member(member);
+  if (!M) return fail(PDF_ERR_MEMBER, "unknown member %d", member);
+  ReqCols req{};
+  if ((rc = build_req(*M, pids, n_pids, req)) != PDF_OK) return rc;
+  if (n == 0) return PDF_OK;
+  if (n * (int64_t)req.n > ((int64_t)1 << 40)) return fail(PDF_ERR_ARG, "n too large");
+  const bool f32 = sizeof(T) == 4;
+  const int lds = lds_grid_elems(*M, f32, n);
+  hipError_t e;
+  if constexpr (sizeof(T) == 8)
+    e = launch_xfxq2_f64(M->dev, req, x, q2, n, out, g_nerr, lds, M->invL01, g_ncu, (hipStream_t)stream);
+  else
+    e = launch_xfxq2_f32(M->dev, req, x, q2, n, out, g_nerr, lds, M->invL01, g_ncu, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "launch xfxq2");
+  return PDF_OK;
+}
+
+extern "C" int pdf_xfxq2(int32_t member, const int32_t* pids, int32_t n_pids, const double* x, const double* q2,
+                         int64_t n, double* out, pdf_stream_t stream) {
+  return xfxq2_impl<double>(member, pids, n_pids, x, q2, n, out, stream);
+}
+
+extern "C" int pdf_xfxq2_f32(int32_t member, const int32_t* pids, int32_t n_pids, const double* x,
+                             const double* q2, int64_t n, float* out, pdf_stream_t stream) {
+  return xfxq2_impl<float>(member, pids, n_pids, x, q2, n, out, stream);
+}
+
+extern "C" int pdf_alphas_q2(const double* q2, int64_t n, double* out, pdf_stream_t stream) {
+  int rc = check_stream_args(q2, out, n);
+  if (rc != PDF_OK) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (!g_has_alphas) return fail(PDF_ERR_STATE, "no alpha_s table loaded");
+  if (n == 0) return PDF_OK;
+  hipError_t e = launch_alphas(g_alphas, q2, n, out, g_nerr, g_ncu, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "launch alphas");
+  return PDF_OK;
+}
+
+extern "C" int pdf_locate(int32_t member, const double* x, const double* q2, int64_t n, int32_t* k, int32_t* ix,
+                          int32_t* iq, int8_t* region, pdf_stream_t stream) {
+  int rc = check_stream_args(x, q2, n);
+  if (rc != PDF_OK) return rc;
+  if (n > 0 && (!k || !ix || !iq || !region)) return fail(PDF_ERR_ARG, "null output pointer");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Member* M = get_member(member);
+  if (!M) return fail(PDF_ERR_MEMBER, "unknown member %d", member);
+  if (n == 0) return PDF_OK;
+  hipError_t e = launch_locate(M->dev, x, q2, n, k, ix, iq, region, g_ncu, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "launch locate");
+  return PDF_OK;
+}
+
+extern "C" int pdf_error_count(int64_t* count_out, int32_t reset, pdf_stream_t stream) {
+  if (!count_out) return fail(PDF_ERR_ARG, "null count_out");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int rc = ensure_init();
+  if (rc != PDF_OK) return rc;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  unsigned long long v = 0;
+  e = hipMemcpy(&v, g_nerr, sizeof v, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, "hipMemcpy(error counter)");
+  *count_out = (int64_t)v;
+  if (reset) {
+    e = hipMemset(g_nerr, 0, sizeof v);
+    if (e != hipSuccess) return fail_hip(e, "hipMemset(error counter)");
+  }
+  return PDF_OK;
+}
+
+extern "C" int pdf_set_lds_policy(int32_t policy) {
+  if (policy < 0 || policy > 2) return fail(PDF_ERR_ARG, "policy must be 0, 1 or 2");
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_lds_policy = policy;
+  return PDF_OK;
+}
+
+extern "C" const char* pdf_last_error(void) { return g_err.c_str(); }
+
+extern "C" int pdf_shutdown(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (auto& M : g_members)
+    if (M.used && M.dmem) (void)hipFree(M.dmem);
+  g_members.clear();
+  if (g_alphas_mem) (void)hipFree(g_alphas_mem);
+  g_alphas_mem = nullptr;
+  g_has_alphas = false;
+  if (g_nerr) (void)hipFree(g_nerr);
+  g_nerr = nullptr;
+  g_init = false;
+  return PDF_OK;
+}

@@ -1,0 +1,71 @@
+// Device-side data layout shared by the host runtime (pdfmi.cpp) and the
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+namespace pdfmi {
+
+constexpr int kMaxSub = 16;      // Q^2 sub-grids per member
+constexpr int kMaxReq = 64;      // flavours per query call
+constexpr int kMaxSeg = 16;      // alpha_s segments
+
+// Region / mode bits of a query point.
+enum : int { kLowX = 1, kLowQ = 2, kHighQ = 4, kInvalid = 8, kXHigh = 16 };
+
+// Per-cell Hermite data of one 1D knot table (cell i = [t_i, t_{i+1}]), FP64,
+// computed on the host.  With Hermite basis h00,h10,h01,h11 of the cell
+// parameter u, the weights of the four knots i-1..i+2 are
+//   w(-1) = h10*am1
+//   w(0)  = h00 + h10*a0 + h11*b0
+//   w(1)  = h01 + h10*a1 + h11*b1
+//   w(2)  = h11*b2
+// where (am1,a0,a1) expand Delta_i * slope_i and (b0,b1,b2) expand
+// Delta_i * slope_{i+1} over the knot values (finite-difference slopes:
+// mean of adjacent secants inside the table, the one secant at its ends).
+struct CellCoef {
+  double t0;      // knot i
+  double t1;      // knot i+1
+  double inv_t0;  // 1 / knot i
+  double invD;    // 1 / ln(t1 / t0)
+  double am1, a0, a1;
+  double b0, b1, b2;
+};
+
+struct SubDesc {
+  int nx, nq;        // knot counts
+  int nxp, nqp;      // storage extents (>= 4; rows beyond the knots are zero)
+  int xk_off, qk_off;  // knot offsets (doubles) into MemberDev::knots
+  int xc_off, qc_off;  // cell offsets into MemberDev::cells
+  int64_t val_off;     // element offset of values[ix][iq][c] into v64 / v32
+  double qfirst;       // first Q^2 knot
+};
+
+struct MemberDev {
+  int K;                 // sub-grids
+  int P;                 // stored columns
+  double xmin, xmax;     // x range (shared by all sub-grids)
+  double qmin, qmax;     // Q^2 range (first knot of sub-grid 0, last of K-1)
+  const double* knots;   // device
+  const CellCoef* cells; // device
+  const double* v64;     // device, FP64 values
+  const float* v32;      // device, FP32-rounded values
+  SubDesc sub[kMaxSub];
+};
+
+struct ReqCols {
+  int n;             // requested flavours
+  int col[kMaxReq];  // stored column, or -1 for a valid flavour absent from the grid
+};
+
+struct AlphasDev {
+  int n;                   // knots
+  int nseg;
+  int seg_lo[kMaxSeg];     // first knot index of each segment
+  int seg_hi[kMaxSeg];     // last knot index of each segment
+  double seg_first[kMaxSeg];
+  const double* knots;     // device, n
+  const double* vals;      // device, n
+  const CellCoef* cells;   // device, cell j = [knot j, knot j+1] (within a segment)
+};
+
+}  // namespace pdfmi

@@ -1,0 +1,201 @@
+"""Python binding of libpdfmi.so (include/pdfmi.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; torch is used
+for device memory and streams.  torch is imported before the library is
+loaded so that both share one HIP runtime.  If the library has not been built,
+importing this module raises: there is no fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdfmi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libpdfmi.so is not built (run __graft_entry__.build() or "
+                      "python paper_2009_06635_amd/build.py); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_i32, _i64 = ctypes.c_int32, ctypes.c_int64
+_SIGS = {
+    "pdf_load_grid": [_i32, _P, _i32, _P, _P, _P, _P],
+    "pdf_unload": [_i32],
+    "pdf_load_alphas": [_i32, _P, _P],
+    "pdf_xfxq2": [_i32, _P, _i32, _P, _P, _i64, _P, _P],
+    "pdf_xfxq2_f32": [_i32, _P, _i32, _P, _P, _i64, _P, _P],
+    "pdf_alphas_q2": [_P, _i64, _P, _P],
+    "pdf_locate": [_i32, _P, _P, _i64, _P, _P, _P, _P, _P],
+    "pdf_error_count": [_P, _i32, _P],
+    "pdf_validate_grid": [_i32, _P, _i32, _P, _P, _P],
+    "pdf_validate_alphas": [_i32, _P, _P],
+    "pdf_set_lds_policy": [_i32],
+    "pdf_shutdown": [],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.pdf_last_error.argtypes = []
+_lib.pdf_last_error.restype = ctypes.c_char_p
+
+PDF_OK, PDF_ERR_ARG, PDF_ERR_GRID, PDF_ERR_MEMBER, PDF_ERR_PID, PDF_ERR_NOMEM, PDF_ERR_DEVICE, PDF_ERR_STATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+
+
+class PdfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("pdfmi error %d: %s" % (code, msg))
+        self.code = code
+
+
+def library():
+    """The loaded ctypes library (for ABI-level tests)."""
+    return _lib
+
+
+def last_error():
+    return _lib.pdf_last_error().decode()
+
+
+def _check(rc):
+    if rc != PDF_OK:
+        raise PdfError(rc, last_error())
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_P)
+
+
+def _grid_arrays(xknots, q2knots, values, pids):
+    shape = _np([[len(x), len(q)] for x, q in zip(xknots, q2knots)], np.int32)
+    knots = _np(np.concatenate([np.concatenate([np.asarray(x, np.float64), np.asarray(q, np.float64)])
+                                for x, q in zip(xknots, q2knots)]), np.float64)
+    vals = _np(np.concatenate([np.asarray(v, np.float64).ravel() for v in values]), np.float64)
+    return shape, _np(pids, np.int32), knots, vals
+
+
+def validate_grid(xknots, q2knots, values, pids):
+    """Host-only grid check; returns the status code (no GPU needed)."""
+    shape, p, knots, vals = _grid_arrays(xknots, q2knots, values, pids)
+    return _lib.pdf_validate_grid(len(shape), _ptr(shape), len(p), _ptr(p), _ptr(knots), _ptr(vals))
+
+
+def validate_alphas(q2knots, alphas):
+    k, a = _np(q2knots, np.float64), _np(alphas, np.float64)
+    return _lib.pdf_validate_alphas(len(k), _ptr(k), _ptr(a))
+
+
+def load_grid(xknots, q2knots, values, pids):
+    """Copy one member's grid to the device; returns the member id."""
+    shape, p, knots, vals = _grid_arrays(xknots, q2knots, values, pids)
+    mid = ctypes.c_int32(-1)
+    _check(_lib.pdf_load_grid(len(shape), _ptr(shape), len(p), _ptr(p), _ptr(knots), _ptr(vals),
+                              ctypes.byref(mid)))
+    return mid.value
+
+
+def load_synth(grid):
+    """Load a SynthGrid (paper_2009_06635_amd.synth)."""
+    return load_grid(grid.xknots, grid.q2knots, grid.values, grid.pids)
+
+
+def unload(member):
+    _check(_lib.pdf_unload(int(member)))
+
+
+def load_alphas(q2knots, alphas):
+    k, a = _np(q2knots, np.float64), _np(alphas, np.float64)
+    _check(_lib.pdf_load_alphas(len(k), _ptr(k), _ptr(a)))
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _P(s.cuda_stream)
+
+
+def _dev_f64(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("%s must be a contiguous float64 CUDA tensor" % name)
+    return t
+
+
+def _pid_arg(pids):
+    if pids is None:
+        return None, 0
+    arr = _np(pids, np.int32)
+    return arr, len(arr)
+
+
+def n_columns(member_pids, pids):
+    return len(member_pids) if pids is None else len(pids)
+
+
+def xfxq2(member, pids, x, q2, out=None, n_cols=None, stream=None):
+    """x*f, FP64, point-major [n][len(pids)] (pids=None: every stored column,
+    then pass n_cols = number of stored columns)."""
+    _dev_f64(x, "x")
+    _dev_f64(q2, "q2")
+    arr, npid = _pid_arg(pids)
+    cols = npid if pids is not None else n_cols
+    if out is None:
+        out = torch.empty((x.shape[0], cols), dtype=torch.float64, device=x.device)
+    _check(_lib.pdf_xfxq2(int(member), _ptr(arr) if arr is not None else None, npid, _P(x.data_ptr()),
+                          _P(q2.data_ptr()), x.shape[0], _P(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def xfxq2_f32(member, pids, x, q2, out=None, n_cols=None, stream=None):
+    """x*f with FP32 bulk arithmetic; FP32 point-major output."""
+    _dev_f64(x, "x")
+    _dev_f64(q2, "q2")
+    arr, npid = _pid_arg(pids)
+    cols = npid if pids is not None else n_cols
+    if out is None:
+        out = torch.empty((x.shape[0], cols), dtype=torch.float32, device=x.device)
+    _check(_lib.pdf_xfxq2_f32(int(member), _ptr(arr) if arr is not None else None, npid, _P(x.data_ptr()),
+                              _P(q2.data_ptr()), x.shape[0], _P(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def alphas_q2(q2, out=None, stream=None):
+    _dev_f64(q2, "q2")
+    if out is None:
+        out = torch.empty_like(q2)
+    _check(_lib.pdf_alphas_q2(_P(q2.data_ptr()), q2.shape[0], _P(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def locate(member, x, q2, stream=None):
+    """(subgrid, ix, iq, region) device tensors."""
+    _dev_f64(x, "x")
+    _dev_f64(q2, "q2")
+    n = x.shape[0]
+    k = torch.empty(n, dtype=torch.int32, device=x.device)
+    ix = torch.empty_like(k)
+    iq = torch.empty_like(k)
+    reg = torch.empty(n, dtype=torch.int8, device=x.device)
+    _check(_lib.pdf_locate(int(member), _P(x.data_ptr()), _P(q2.data_ptr()), n, _P(k.data_ptr()),
+                           _P(ix.data_ptr()), _P(iq.data_ptr()), _P(reg.data_ptr()), _stream(stream)))
+    return k, ix, iq, reg
+
+
+def error_count(reset=False, stream=None):
+    v = ctypes.c_int64(0)
+    _check(_lib.pdf_error_count(ctypes.byref(v), 1 if reset else 0, _stream(stream)))
+    return v.value
+
+
+def set_lds_policy(policy):
+    _check(_lib.pdf_set_lds_policy(int(policy)))
+
+
+def shutdown():
+    _check(_lib.pdf_shutdown())
