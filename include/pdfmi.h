@@ -163,6 +163,22 @@ int pdf_validate_alphas(int32_t n_knots, const double* q2_knots, const double* a
  */
 int pdf_set_lds_policy(int32_t policy);
 
+/*
+ * Launch-shape knobs (results are identical under every setting; they only
+ * change speed).  Process-wide; set them before queueing work.
+ *   PDF_TUNE_LDS_POLICY      as pdf_set_lds_policy (0, 1, 2)
+ *   PDF_TUNE_VECTOR_COLUMNS  1: a request for every stored flavour in load
+ *                            order is served by lanes that each own a
+ *                            16-byte group of columns (2 FP64 / 4 FP32);
+ *                            0: one lane per (point, flavour)
+ *   PDF_TUNE_BLOCKS_PER_CU   workgroups launched per compute unit when the
+ *                            grid is read from global memory (1..64)
+ * PDF_ERR_ARG for an unknown knob or value out of range.
+ */
+enum { PDF_TUNE_LDS_POLICY = 0, PDF_TUNE_VECTOR_COLUMNS = 1, PDF_TUNE_BLOCKS_PER_CU = 2 };
+int pdf_set_tuning(int32_t knob, int32_t value);
+int pdf_get_tuning(int32_t knob, int32_t* value);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* pdf_last_error(void);
 

@@ -25,7 +25,6 @@
 
 namespace pdfmi {
 
-constexpr int kTile = 256;  // points per tile == threads per workgroup
 
 // Largest i in [0, n-2] with t[i] <= v, 0 if t[0] > v (t strictly increasing).
 __device__ __forceinline__ int find_cell(const double* __restrict__ t, int n, double v) {
@@ -75,7 +74,8 @@ struct PointLoc {
 
 // Phase 1: everything that depends on the point only.
 template <typename T>
-__device__ __forceinline__ PointLoc locate_point(const MemberDev& m, double x, double q2, T w[4], T v[4]) {
+__device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const double* __restrict__ knots, double x,
+                                                 double q2, T w[4], T v[4]) {
   PointLoc L;
   L.p0 = 0.0;
   L.p1 = 0.0;
@@ -96,8 +96,8 @@ __device__ __forceinline__ PointLoc locate_point(const MemberDev& m, double x, d
   for (int j = 1; j < m.K; ++j)
     if (m.sub[j].qfirst <= q2) k = j;
   const SubDesc& S = m.sub[k];
-  const int ix = find_cell(m.knots + S.xk_off, S.nx, x);
-  const int iq = find_cell(m.knots + S.qk_off, S.nq, q2);
+  const int ix = find_cell(knots + S.xk_off, S.nx, x);
+  const int iq = find_cell(knots + S.qk_off, S.nq, q2);
   const CellCoef cx = m.cells[S.xc_off + ix];
   const CellCoef cq = m.cells[S.qc_off + iq];
   const int sx = min(max(ix - 1, 0), S.nxp - 4);
@@ -126,8 +126,9 @@ __device__ __forceinline__ PointLoc locate_point(const MemberDev& m, double x, d
   L.k = k;
   L.ix = ix;
   L.iq = iq;
-  L.sa = S.nqp * m.P;
-  L.base = (int)(S.val_off + (int64_t)(sx * S.nqp + sq) * m.P);
+  const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
+  L.sa = S.nqp * Pp;
+  L.base = (int)((sizeof(T) == 8 ? S.val_off64 : S.val_off32) + (int64_t)(sx * S.nqp + sq) * Pp);
   return L;
 }
 
@@ -146,34 +147,20 @@ __device__ __forceinline__ double low_q(double f0, double f1, double r, double i
   return f0 * pow(r, gamma * r + 1.0 - r);
 }
 
-// Extrapolated value from the 4x4 stencil F (rare path, FP64 combination).
-template <typename T>
-__device__ __noinline__ double extrapolate(const T F[4][4], int mode, const T w[4], const T v[4],
-                                           double p0, double p1, double invL01) {
+// Extrapolated value from anchor values (rare path, FP64 combination):
+//   x below x_min only:      a0, a1 = rows x_0, x_1 interpolated in Q^2
+//   Q^2 outside, x inside:   a0, a1 = anchor Q^2 rows interpolated in x
+//   corners:                 a0, a1 (x_0, x_1 on the lower anchor row),
+//                            a2, a3 (x_0, x_1 on the upper anchor row)
+__device__ __noinline__ double extrapolate(int mode, double a0, double a1, double a2, double a3, double p0,
+                                           double p1, double invL01) {
   const bool lowx = mode & kLowX, lowq = mode & kLowQ, highq = mode & kHighQ;
   const bool xhigh = mode & kXHigh;
-  const int r0 = (mode >> 8) & 3;
-  if (lowx && !(lowq || highq)) {
-    double f0 = 0.0, f1 = 0.0;
-    for (int b = 0; b < 4; ++b) {
-      f0 += (double)v[b] * (double)F[0][b];
-      f1 += (double)v[b] * (double)F[1][b];
-    }
-    return cont_low(f0, f1, p0);
-  }
-  if (!lowx) {
-    const int ra = lowq ? 0 : r0;
-    double f0 = 0.0, f1 = 0.0;
-    for (int a = 0; a < 4; ++a) {
-      f0 += (double)w[a] * (double)F[a][ra];
-      f1 += (double)w[a] * (double)F[a][ra + 1];
-    }
-    return lowq ? low_q(f0, f1, p0, invL01, xhigh) : cont_high(f0, f1, p0);
-  }
+  if (lowx && !(lowq || highq)) return cont_low(a0, a1, p0);
+  if (!lowx) return lowq ? low_q(a0, a1, p0, invL01, xhigh) : cont_high(a0, a1, p0);
   // corners: continue in x on the two anchor rows first, then in Q^2
-  const int ra = lowq ? 0 : r0;
-  const double g0 = cont_low((double)F[0][ra], (double)F[1][ra], p1);
-  const double g1 = cont_low((double)F[0][ra + 1], (double)F[1][ra + 1], p1);
+  const double g0 = cont_low(a0, a1, p1);
+  const double g1 = cont_low(a2, a3, p1);
   return lowq ? low_q(g0, g1, p0, invL01, xhigh) : cont_high(g0, g1, p0);
 }
 
@@ -184,110 +171,236 @@ __device__ __forceinline__ const double* member_values<double>(const MemberDev& 
 template <>
 __device__ __forceinline__ const float* member_values<float>(const MemberDev& m) { return m.v32; }
 
-// One (point, flavour) output from its stencil.
+// In-grid value of one column from its gathered 4x4 stencil: the x-direction
+// weights on each of the four Q^2 rows, then the Q^2-direction weights.
 template <typename T>
-__device__ __forceinline__ T eval_entry(const T* __restrict__ f, int sa, int P, int mode,
-                                        const T w[4], const T v[4], double p0, double p1,
-                                        double invL01) {
-  T F[4][4];
+__device__ __forceinline__ T interp_stencil(const T F[4][4], const T w[4], const T v[4]) {
+  T acc;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) F[a][b] = f[a * sa + b * P];
-  if ((mode & (kLowX | kLowQ | kHighQ)) == 0) {
-    T acc;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      T g = w[0] * F[0][b];
-      g = fma(w[1], F[1][b], g);
-      g = fma(w[2], F[2][b], g);
-      g = fma(w[3], F[3][b], g);
-      acc = b == 0 ? v[0] * g : fma(v[b], g, acc);
-    }
-    return acc;
+  for (int b = 0; b < 4; ++b) {
+    T g = w[0] * F[0][b];
+    g = fma(w[1], F[1][b], g);
+    g = fma(w[2], F[2][b], g);
+    g = fma(w[3], F[3][b], g);
+    acc = b == 0 ? v[0] * g : fma(v[b], g, acc);
   }
-  return (T)extrapolate<T>(F, mode, w, v, p0, p1, invL01);
+  return acc;
 }
 
-// x*f for a set of flavours; see file header.  out is point-major [n][R].
-template <typename T, bool kLdsGrid>
-__global__ __launch_bounds__(kTile) void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X,
-                                                  const double* __restrict__ Q2, int64_t n, T* __restrict__ out,
-                                                  unsigned long long* __restrict__ nerr, int lds_grid_elems,
-                                                  double invL01) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* sw = reinterpret_cast<T*>(smem);                 // [kTile][4]
-  T* sv = sw + kTile * 4;                             // [kTile][4]
-  double* sp = reinterpret_cast<double*>(sv + kTile * 4);  // [kTile][2]
-  int* sbase = reinterpret_cast<int*>(sp + 2 * kTile);
-  int* ssa = sbase + kTile;
-  int* smode = ssa + kTile;
-  T* sgrid = reinterpret_cast<T*>(smode + kTile);      // 16-byte aligned (kTile multiple of 4)
+// Extrapolated value of one column (rare path).  f points at the column's
+// entry of the stencil origin; only the anchor knots the formula needs are
+// read:
+//   x below x_min only:     rows x_0, x_1 interpolated in Q^2
+//   Q^2 outside, x inside:  the two anchor Q^2 rows interpolated in x
+//   corners:                the four anchor knot values
+struct Wts {
+  double w0, w1, w2, w3, v0, v1, v2, v3;
+};
 
-  const T* gvals = member_values<T>(m);
-  if constexpr (kLdsGrid) {
-    for (int i = threadIdx.x; i < lds_grid_elems; i += kTile) sgrid[i] = gvals[i];
-    __syncthreads();
-  }
-  const int R = rc.n;
-  const int t = threadIdx.x;
-  const int64_t ntiles = (n + kTile - 1) / kTile;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t pbeg = tile * kTile;
-    const int tp = (int)min((int64_t)kTile, n - pbeg);
-    bool bad = false;
-    if (t < tp) {
-      T w[4], v[4];
-      const PointLoc L = locate_point<T>(m, X[pbeg + t], Q2[pbeg + t], w, v);
-      bad = L.mode & kInvalid;
+template <typename T>
+__device__ __noinline__ double extrap_entry(const T* f, int sa, int Pp, int mode, Wts wt, double p0, double p1,
+                                            double invL01) {
+  const double w[4] = {wt.w0, wt.w1, wt.w2, wt.w3};
+  const double v[4] = {wt.v0, wt.v1, wt.v2, wt.v3};
+  const bool lowx = mode & kLowX, lowq = mode & kLowQ, highq = mode & kHighQ;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (lowx && !(lowq || highq)) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      a0 += v[b] * (double)f[b * Pp];
+      a1 += v[b] * (double)f[sa + b * Pp];
+    }
+  } else {
+    const int ra = lowq ? 0 : (mode >> 8) & 3;
+    if (!lowx) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        sw[t * 4 + a] = w[a];
-        sv[t * 4 + a] = v[a];
+        a0 += w[a] * (double)f[a * sa + ra * Pp];
+        a1 += w[a] * (double)f[a * sa + (ra + 1) * Pp];
       }
-      sp[2 * t] = L.p0;
-      sp[2 * t + 1] = L.p1;
-      sbase[t] = L.base;
-      ssa[t] = L.sa;
-      smode[t] = L.mode;
+    } else {
+      a0 = (double)f[ra * Pp];
+      a1 = (double)f[sa + ra * Pp];
+      a2 = (double)f[(ra + 1) * Pp];
+      a3 = (double)f[sa + (ra + 1) * Pp];
+    }
+  }
+  return extrapolate(mode, a0, a1, a2, a3, p0, p1, invL01);
+}
+
+// 16-byte column groups of the vectorised path.
+template <typename T, int G>
+struct VecOf;
+template <>
+struct VecOf<double, 2> { using type = double2; };
+template <>
+struct VecOf<float, 4> { using type = float4; };
+
+// x*f for a set of flavours; see file header.  out is point-major [n][R].
+// Each wave works on its own 64-point tiles with no workgroup barrier after
+// the initial staging, so the knot searches and log transforms of some waves
+// overlap the stencil gathers of others.  In-grid entries run a branch-free
+// gather + FMA loop; the rare extrapolated points of a tile are finished
+// afterwards, one point at a time across the wave.
+constexpr int kWave = 64;
+
+template <typename T>
+__host__ __device__ constexpr size_t wave_record_bytes() {
+  return (size_t)kWave * (8 * sizeof(T) + 16 + 12);
+}
+
+template <typename T, bool kLdsGrid, int G, int BS>
+__global__ __launch_bounds__(BS) void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X,
+                                              const double* __restrict__ Q2, int64_t n, T* __restrict__ out,
+                                              unsigned long long* __restrict__ nerr, int lds_grid_elems,
+                                              double invL01) {
+  constexpr int kWaves = BS / kWave;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sknots = reinterpret_cast<double*>(smem);                       // [nknots_pad]
+  int* scol = reinterpret_cast<int*>(sknots + m.nknots_pad);              // [kMaxReq]
+  unsigned char* srec = reinterpret_cast<unsigned char*>(scol + kMaxReq);  // per-wave records
+  T* sgrid = reinterpret_cast<T*>(srec + kWaves * wave_record_bytes<T>());
+
+  for (int i = threadIdx.x; i < m.nknots; i += BS) sknots[i] = m.knots[i];
+  for (int i = threadIdx.x; i < rc.n; i += BS) scol[i] = rc.col[i];
+  const T* __restrict__ gvals = member_values<T>(m);
+  if constexpr (kLdsGrid) {
+    for (int i = threadIdx.x; i < lds_grid_elems; i += BS) sgrid[i] = gvals[i];
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  unsigned char* rec = srec + wv * wave_record_bytes<T>();
+  T* sw = reinterpret_cast<T*>(rec);                       // [64][4]
+  T* sv = sw + kWave * 4;                                  // [64][4]
+  double* sp = reinterpret_cast<double*>(sv + kWave * 4);  // [64][2]
+  int* sbase = reinterpret_cast<int*>(sp + 2 * kWave);
+  int* ssa = sbase + kWave;
+  int* smode = ssa + kWave;
+
+  const int R = rc.n;
+  const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
+  constexpr int kSlow = kLowX | kLowQ | kHighQ;
+  // lane -> (point, flavour) or (point, column group) walk of the wave's outputs
+  const int NE = G == 1 ? R : (R + G - 1) / G;
+  const int e_p0 = lane / NE, e_j0 = lane - (lane / NE) * NE;
+  const int e_dp = kWave / NE, e_dj = kWave - (kWave / NE) * NE;
+  const int64_t ntiles = (n + kWave - 1) / kWave;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wv; tile < ntiles; tile += (int64_t)gridDim.x * kWaves) {
+    const int64_t pbeg = tile * kWave;
+    const int tp = (int)min((int64_t)kWave, n - pbeg);
+    bool bad = false, slow = false;
+    if (lane < tp) {
+      T w[4], v[4];
+      const PointLoc L = locate_point<T>(m, sknots, X[pbeg + lane], Q2[pbeg + lane], w, v);
+      bad = L.mode & kInvalid;
+      slow = L.mode & kSlow;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        sw[lane * 4 + a] = w[a];
+        sv[lane * 4 + a] = v[a];
+      }
+      sp[2 * lane] = L.p0;
+      sp[2 * lane + 1] = L.p1;
+      sbase[lane] = L.base;
+      ssa[lane] = L.sa;
+      smode[lane] = L.mode;
     }
     const unsigned long long bal = __ballot(bad);
-    if (bal && (t & 63) == 0) atomicAdd(nerr, (unsigned long long)__popcll(bal));
-    __syncthreads();
-    const int nev = tp * R;
+    if (bal && lane == 0) atomicAdd(nerr, (unsigned long long)__popcll(bal));
+    unsigned long long slow_mask = __ballot(slow);
+    // records written by this wave are read back by other lanes of the same wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
     T* obase = out + pbeg * R;
-    int p = t / R, j = t - (t / R) * R;
-    const int dp = kTile / R, dj = kTile - (kTile / R) * R;
-    for (int e = t; e < nev; e += kTile) {
+    const int nev = tp * NE;
+    int p = e_p0, j = e_j0;
+    for (int e = lane; e < nev; e += kWave) {
       const int mode = smode[p];
-      const int col = rc.col[j];
-      T val;
-      if (mode & kInvalid) {
-        val = (T)NAN;
-      } else if (col < 0) {
-        val = (T)0;
-      } else {
+      if (!(mode & kSlow)) {
         T w[4], v[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
           w[a] = sw[p * 4 + a];
           v[a] = sv[p * 4 + a];
         }
-        const int off = sbase[p] + col;
-        if constexpr (kLdsGrid)
-          val = eval_entry<T>(sgrid + off, ssa[p], m.P, mode, w, v, sp[2 * p], sp[2 * p + 1], invL01);
-        else
-          val = eval_entry<T>(gvals + off, ssa[p], m.P, mode, w, v, sp[2 * p], sp[2 * p + 1], invL01);
+        const int base = sbase[p], sa = ssa[p];
+        const bool inv = mode & kInvalid;
+        if constexpr (G == 1) {
+          const int col = scol[j];
+          T val = (T)0;
+          if (inv) {
+            val = (T)NAN;
+          } else if (col >= 0) {
+            T F[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const int o = base + col + a * sa;
+#pragma unroll
+              for (int b = 0; b < 4; ++b) F[a][b] = kLdsGrid ? sgrid[o + b * Pp] : gvals[o + b * Pp];
+            }
+            val = interp_stencil<T>(F, w, v);
+          }
+          obase[e] = val;
+        } else {
+          using V = typename VecOf<T, G>::type;
+          T res[G];
+          if (inv) {
+#pragma unroll
+            for (int i = 0; i < G; ++i) res[i] = (T)NAN;
+          } else {
+            T F[G][4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const int o = base + G * j + a * sa;
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                const V q = kLdsGrid ? *reinterpret_cast<const V*>(sgrid + o + b * Pp)
+                                     : *reinterpret_cast<const V*>(gvals + o + b * Pp);
+                const T* qs = reinterpret_cast<const T*>(&q);
+#pragma unroll
+                for (int i = 0; i < G; ++i) F[i][a][b] = qs[i];
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < G; ++i) res[i] = interp_stencil<T>(F[i], w, v);
+          }
+          T* o = obase + p * R + G * j;
+#pragma unroll
+          for (int i = 0; i < G; ++i)
+            if (G * j + i < R) o[i] = res[i];
+        }
       }
-      obase[e] = val;
-      p += dp;
-      j += dj;
-      if (j >= R) {
-        j -= R;
+      p += e_dp;
+      j += e_dj;
+      if (j >= NE) {
+        j -= NE;
         ++p;
       }
     }
-    __syncthreads();
+    // extrapolated points of the tile, one at a time across the wave
+    while (slow_mask) {
+      const int q = __builtin_ctzll(slow_mask);
+      slow_mask &= slow_mask - 1;
+      const int mode = smode[q];
+      const Wts wt{(double)sw[q * 4], (double)sw[q * 4 + 1], (double)sw[q * 4 + 2], (double)sw[q * 4 + 3],
+                   (double)sv[q * 4], (double)sv[q * 4 + 1], (double)sv[q * 4 + 2], (double)sv[q * 4 + 3]};
+      for (int jj = lane; jj < R; jj += kWave) {
+        const int col = scol[jj];
+        T val = (T)0;
+        if (col >= 0) {
+          const T* f = (kLdsGrid ? (const T*)sgrid : gvals) + sbase[q] + col;
+          val = (T)extrap_entry<T>(f, ssa[q], Pp, mode, wt, sp[2 * q], sp[2 * q + 1], invL01);
+        }
+        obase[q * R + jj] = val;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -298,7 +411,7 @@ __global__ __launch_bounds__(256) void k_locate(MemberDev m, const double* __res
                                                 int32_t* __restrict__ iqo, int8_t* __restrict__ rego) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double w[4], v[4];
-    const PointLoc L = locate_point<double>(m, X[i], Q2[i], w, v);
+    const PointLoc L = locate_point<double>(m, m.knots, X[i], Q2[i], w, v);
     ko[i] = L.k;
     ixo[i] = L.ix;
     iqo[i] = L.iq;
@@ -346,41 +459,62 @@ __global__ __launch_bounds__(256) void k_alphas(AlphasDev A, const double* __res
 // ---------------------------------------------------------------------------------------
 // Launchers (host side, called by pdfmi.cpp)
 
-size_t xfxq2_record_bytes(bool f32) { return (size_t)kTile * (8 * (f32 ? 4 : 8) + 16 + 12); }
+// LDS bytes of k_xfxq2 other than the staged grid, for a block of bs threads.
+static size_t shared_bytes(const MemberDev& m, bool f32, int bs) {
+  return (size_t)m.nknots_pad * 8 + kMaxReq * 4 +
+         (bs / kWave) * (f32 ? wave_record_bytes<float>() : wave_record_bytes<double>());
+}
+constexpr int kBlockGlobal = 256;   // grid read from global memory
+constexpr int kBlockLds = 1024;     // grid staged once per workgroup in LDS
+size_t xfxq2_shared_bytes(const MemberDev& m, bool f32) { return shared_bytes(m, f32, kBlockLds); }
 
-template <typename T>
-static hipError_t launch_xfxq2_t(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2,
+template <typename T, int G>
+static hipError_t launch_xfxq2_g(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2,
                                  int64_t n, T* out, unsigned long long* nerr, int lds_grid_elems,
-                                 double invL01, int n_cu, hipStream_t s) {
-  const size_t rec = xfxq2_record_bytes(sizeof(T) == 4);
-  const int64_t ntiles = (n + kTile - 1) / kTile;
+                                 double invL01, const LaunchCfg& cfg, hipStream_t s) {
+  const int n_cu = cfg.n_cu;
   if (lds_grid_elems > 0) {
-    const size_t shm = rec + (size_t)lds_grid_elems * sizeof(T);
+    const size_t shm = shared_bytes(m, sizeof(T) == 4, kBlockLds) + (size_t)lds_grid_elems * sizeof(T);
     const int per_cu = (int)(160 * 1024 / shm) > 0 ? (int)(160 * 1024 / shm) : 1;
+    const int64_t ntiles = (n + kBlockLds - 1) / kBlockLds;
     const int64_t nb = min(ntiles, (int64_t)n_cu * per_cu);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xfxq2<T, true>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xfxq2<T, true, G, kBlockLds>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_xfxq2<T, true>), dim3((unsigned)nb), dim3(kTile), shm, s, m, rc, x, q2, n, out, nerr,
-                       lds_grid_elems, invL01);
+    hipLaunchKernelGGL((k_xfxq2<T, true, G, kBlockLds>), dim3((unsigned)nb), dim3(kBlockLds), shm, s, m, rc, x, q2,
+                       n, out, nerr, lds_grid_elems, invL01);
   } else {
-    const int64_t nb = min(ntiles, (int64_t)n_cu * 8);
-    hipLaunchKernelGGL((k_xfxq2<T, false>), dim3((unsigned)nb), dim3(kTile), rec, s, m, rc, x, q2, n, out, nerr,
-                       0, invL01);
+    const size_t shm = shared_bytes(m, sizeof(T) == 4, kBlockGlobal);
+    const int64_t ntiles = (n + kBlockGlobal - 1) / kBlockGlobal;
+    const int64_t nb = min(ntiles, (int64_t)n_cu * cfg.blocks_per_cu);
+    hipLaunchKernelGGL((k_xfxq2<T, false, G, kBlockGlobal>), dim3((unsigned)nb), dim3(kBlockGlobal), shm, s, m, rc,
+                       x, q2, n, out, nerr, 0, invL01);
   }
   return hipGetLastError();
 }
 
+// The vectorised kernel serves requests for every stored column in load order.
+static bool all_columns(const MemberDev& m, const ReqCols& rc) {
+  if (rc.n != m.P) return false;
+  for (int j = 0; j < rc.n; ++j)
+    if (rc.col[j] != j) return false;
+  return true;
+}
+
 hipError_t launch_xfxq2_f64(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2, int64_t n,
-                            double* out, unsigned long long* nerr, int lds_grid_elems, double invL01, int n_cu,
-                            hipStream_t s) {
-  return launch_xfxq2_t<double>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, n_cu, s);
+                            double* out, unsigned long long* nerr, int lds_grid_elems, double invL01,
+                            const LaunchCfg& cfg, hipStream_t s) {
+  if (cfg.vector_cols && all_columns(m, rc))
+    return launch_xfxq2_g<double, 2>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
+  return launch_xfxq2_g<double, 1>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
 }
 
 hipError_t launch_xfxq2_f32(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2, int64_t n,
-                            float* out, unsigned long long* nerr, int lds_grid_elems, double invL01, int n_cu,
-                            hipStream_t s) {
-  return launch_xfxq2_t<float>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, n_cu, s);
+                            float* out, unsigned long long* nerr, int lds_grid_elems, double invL01,
+                            const LaunchCfg& cfg, hipStream_t s) {
+  if (cfg.vector_cols && all_columns(m, rc))
+    return launch_xfxq2_g<float, 4>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
+  return launch_xfxq2_g<float, 1>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
 }
 
 hipError_t launch_locate(const MemberDev& m, const double* x, const double* q2, int64_t n, int32_t* k, int32_t* ix,

@@ -17,11 +17,11 @@
 #include "pdfmi_dev.h"
 
 namespace pdfmi {
-size_t xfxq2_record_bytes(bool f32);
+size_t xfxq2_shared_bytes(const MemberDev& m, bool f32);
 hipError_t launch_xfxq2_f64(const MemberDev&, const ReqCols&, const double*, const double*, int64_t, double*,
-                            unsigned long long*, int, double, int, hipStream_t);
+                            unsigned long long*, int, double, const LaunchCfg&, hipStream_t);
 hipError_t launch_xfxq2_f32(const MemberDev&, const ReqCols&, const double*, const double*, int64_t, float*,
-                            unsigned long long*, int, double, int, hipStream_t);
+                            unsigned long long*, int, double, const LaunchCfg&, hipStream_t);
 hipError_t launch_locate(const MemberDev&, const double*, const double*, int64_t, int32_t*, int32_t*, int32_t*,
                          int8_t*, int, hipStream_t);
 hipError_t launch_alphas(const AlphasDev&, const double*, int64_t, double*, unsigned long long*, int, hipStream_t);
@@ -52,7 +52,6 @@ struct Member {
   MemberDev dev{};
   void* dmem = nullptr;
   std::vector<int> pids;   // stored column -> pid (0 normalised to 21)
-  int64_t grid_elems = 0;  // padded value elements
   double invL01 = 0.0;
 };
 
@@ -65,6 +64,8 @@ bool g_has_alphas = false;
 AlphasDev g_alphas{};
 void* g_alphas_mem = nullptr;
 int g_lds_policy = 0;  // 0 auto, 1 never stage the grid in LDS, 2 whenever it fits
+int g_vector_cols = 1; // serve all-column requests with G-wide vector gathers
+int g_blocks_per_cu = 16;
 constexpr size_t kLdsBytes = 160 * 1024;
 
 int ensure_init() {
@@ -164,7 +165,8 @@ Member* get_member(int32_t id) {
 // Stage the whole grid in LDS for this call?
 int lds_grid_elems(const Member& M, bool f32, int64_t n) {
   if (g_lds_policy == 1) return 0;
-  const size_t bytes = (size_t)M.grid_elems * (f32 ? 4 : 8) + xfxq2_record_bytes(f32);
+  const int64_t elems = f32 ? M.dev.elems32 : M.dev.elems64;
+  const size_t bytes = (size_t)elems * (f32 ? 4 : 8) + xfxq2_shared_bytes(M.dev, f32);
   if (bytes > kLdsBytes - 1024) return 0;
   if (g_lds_policy == 0) {
     // each workgroup pays one grid copy; require enough tiles to amortise it
@@ -172,7 +174,7 @@ int lds_grid_elems(const Member& M, bool f32, int64_t n) {
     const int per_cu = (int)(kLdsBytes / bytes);
     if (tiles < (int64_t)4 * g_ncu * (per_cu > 0 ? per_cu : 1)) return 0;
   }
-  return (int)M.grid_elems;
+  return (int)elems;
 }
 
 }  // namespace
@@ -216,6 +218,7 @@ extern "C" int pdf_validate_grid(int32_t K, const int32_t* shape, int32_t P, con
     vo += nv;
   }
   if (vo > ((int64_t)1 << 31) / 2) return fail(PDF_ERR_GRID, "grid too large");
+  if (ko > 8192) return fail(PDF_ERR_GRID, "more than 8192 knots in total (they are staged in LDS)");
   return PDF_OK;
 }
 
@@ -236,7 +239,10 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
   // host staging of knots, cells and padded values
   std::vector<double> hk;
   std::vector<CellCoef> hc;
-  int64_t nvals = 0;
+  const int P64 = (P + 1) & ~1, P32 = (P + 3) & ~3;
+  d.P64 = P64;
+  d.P32 = P32;
+  int64_t n64 = 0, n32 = 0;
   for (int k = 0; k < K; ++k) {
     const int nx = shape[2 * k], nq = shape[2 * k + 1];
     SubDesc& S = d.sub[k];
@@ -244,11 +250,15 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
     S.nq = nq;
     S.nxp = nx < 4 ? 4 : nx;
     S.nqp = nq < 4 ? 4 : nq;
-    S.val_off = nvals;
-    nvals += (int64_t)S.nxp * S.nqp * P;
+    S.val_off64 = n64;
+    S.val_off32 = n32;
+    n64 += (int64_t)S.nxp * S.nqp * P64;
+    n32 += (int64_t)S.nxp * S.nqp * P32;
   }
-  M.grid_elems = nvals;
-  std::vector<double> hv((size_t)nvals, 0.0);
+  d.elems64 = n64;
+  d.elems32 = n32;
+  std::vector<double> hv((size_t)n64, 0.0);
+  std::vector<float> hf((size_t)n32, 0.0f);
   int64_t ko = 0, vo = 0;
   for (int k = 0; k < K; ++k) {
     SubDesc& S = d.sub[k];
@@ -267,11 +277,16 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
     S.qfirst = qk[0];
     for (int ix = 0; ix < S.nx; ++ix)
       for (int iq = 0; iq < S.nq; ++iq)
-        for (int c = 0; c < P; ++c)
-          hv[S.val_off + ((int64_t)ix * S.nqp + iq) * P + c] = values[vo + ((int64_t)ix * S.nq + iq) * P + c];
+        for (int c = 0; c < P; ++c) {
+          const double v = values[vo + ((int64_t)ix * S.nq + iq) * P + c];
+          hv[S.val_off64 + ((int64_t)ix * S.nqp + iq) * P64 + c] = v;
+          hf[S.val_off32 + ((int64_t)ix * S.nqp + iq) * P32 + c] = (float)v;
+        }
     ko += S.nx + S.nq;
     vo += (int64_t)S.nx * S.nq * P;
   }
+  d.nknots = (int)hk.size();
+  d.nknots_pad = (d.nknots + 1) & ~1;
   d.xmin = knots[0];
   d.xmax = knots[shape[0] - 1];
   d.qmin = d.sub[0].qfirst;
@@ -280,14 +295,13 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
 
   const size_t bk = align_up(hk.size() * sizeof(double), 256);
   const size_t bc = align_up(hc.size() * sizeof(CellCoef), 256);
-  const size_t b64 = align_up((size_t)nvals * sizeof(double), 256);
-  const size_t b32 = align_up((size_t)nvals * sizeof(float), 256);
+  const size_t b64 = align_up((size_t)n64 * sizeof(double), 256);
+  const size_t b32 = align_up((size_t)n32 * sizeof(float), 256);
   std::vector<unsigned char> blob(bk + bc + b64 + b32, 0);
   std::memcpy(blob.data(), hk.data(), hk.size() * sizeof(double));
   std::memcpy(blob.data() + bk, hc.data(), hc.size() * sizeof(CellCoef));
-  std::memcpy(blob.data() + bk + bc, hv.data(), (size_t)nvals * sizeof(double));
-  float* f32 = reinterpret_cast<float*>(blob.data() + bk + bc + b64);
-  for (int64_t i = 0; i < nvals; ++i) f32[i] = (float)hv[i];
+  std::memcpy(blob.data() + bk + bc, hv.data(), (size_t)n64 * sizeof(double));
+  std::memcpy(blob.data() + bk + bc + b64, hf.data(), (size_t)n32 * sizeof(float));
 
   hipError_t e = hipMalloc(&M.dmem, blob.size());
   if (e != hipSuccess) return fail_hip(e, "hipMalloc(grid)");
@@ -406,10 +420,11 @@ static int xfxq2_impl(int32_t member, const int32_t* pids, int32_t n_pids, const
   const bool f32 = sizeof(T) == 4;
   const int lds = lds_grid_elems(*M, f32, n);
   hipError_t e;
+  const LaunchCfg cfg{g_ncu, g_blocks_per_cu, g_vector_cols};
   if constexpr (sizeof(T) == 8)
-    e = launch_xfxq2_f64(M->dev, req, x, q2, n, out, g_nerr, lds, M->invL01, g_ncu, (hipStream_t)stream);
+    e = launch_xfxq2_f64(M->dev, req, x, q2, n, out, g_nerr, lds, M->invL01, cfg, (hipStream_t)stream);
   else
-    e = launch_xfxq2_f32(M->dev, req, x, q2, n, out, g_nerr, lds, M->invL01, g_ncu, (hipStream_t)stream);
+    e = launch_xfxq2_f32(M->dev, req, x, q2, n, out, g_nerr, lds, M->invL01, cfg, (hipStream_t)stream);
   if (e != hipSuccess) return fail_hip(e, "launch xfxq2");
   return PDF_OK;
 }
@@ -465,6 +480,37 @@ extern "C" int pdf_error_count(int64_t* count_out, int32_t reset, pdf_stream_t s
     if (e != hipSuccess) return fail_hip(e, "hipMemset(error counter)");
   }
   return PDF_OK;
+}
+
+extern "C" int pdf_set_tuning(int32_t knob, int32_t value) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  switch (knob) {
+    case PDF_TUNE_LDS_POLICY:
+      if (value < 0 || value > 2) return fail(PDF_ERR_ARG, "LDS policy must be 0, 1 or 2");
+      g_lds_policy = value;
+      return PDF_OK;
+    case PDF_TUNE_VECTOR_COLUMNS:
+      if (value < 0 || value > 1) return fail(PDF_ERR_ARG, "vector-columns knob must be 0 or 1");
+      g_vector_cols = value;
+      return PDF_OK;
+    case PDF_TUNE_BLOCKS_PER_CU:
+      if (value < 1 || value > 64) return fail(PDF_ERR_ARG, "blocks per CU must be in [1, 64]");
+      g_blocks_per_cu = value;
+      return PDF_OK;
+    default:
+      return fail(PDF_ERR_ARG, "unknown tuning knob %d", knob);
+  }
+}
+
+extern "C" int pdf_get_tuning(int32_t knob, int32_t* value) {
+  if (!value) return fail(PDF_ERR_ARG, "null value");
+  std::lock_guard<std::mutex> lock(g_mu);
+  switch (knob) {
+    case PDF_TUNE_LDS_POLICY: *value = g_lds_policy; return PDF_OK;
+    case PDF_TUNE_VECTOR_COLUMNS: *value = g_vector_cols; return PDF_OK;
+    case PDF_TUNE_BLOCKS_PER_CU: *value = g_blocks_per_cu; return PDF_OK;
+    default: return fail(PDF_ERR_ARG, "unknown tuning knob %d", knob);
+  }
 }
 
 extern "C" int pdf_set_lds_policy(int32_t policy) {

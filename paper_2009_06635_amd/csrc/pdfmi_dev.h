@@ -36,13 +36,18 @@ struct SubDesc {
   int nxp, nqp;      // storage extents (>= 4; rows beyond the knots are zero)
   int xk_off, qk_off;  // knot offsets (doubles) into MemberDev::knots
   int xc_off, qc_off;  // cell offsets into MemberDev::cells
-  int64_t val_off;     // element offset of values[ix][iq][c] into v64 / v32
+  int64_t val_off64;   // element offset of values[ix][iq][c] into v64 (row stride P64)
+  int64_t val_off32;   // element offset into v32 (row stride P32)
   double qfirst;       // first Q^2 knot
 };
 
 struct MemberDev {
   int K;                 // sub-grids
   int P;                 // stored columns
+  int P64, P32;          // row strides of v64 / v32: P rounded up to 2 / 4 (zero padding)
+  int64_t elems64, elems32;  // value elements (padded) of v64 / v32
+  int nknots;            // total knots (all sub-grids, x then Q^2 each)
+  int nknots_pad;        // nknots rounded up to an even count (16-byte LDS alignment)
   double xmin, xmax;     // x range (shared by all sub-grids)
   double qmin, qmax;     // Q^2 range (first knot of sub-grid 0, last of K-1)
   const double* knots;   // device
@@ -55,6 +60,12 @@ struct MemberDev {
 struct ReqCols {
   int n;             // requested flavours
   int col[kMaxReq];  // stored column, or -1 for a valid flavour absent from the grid
+};
+
+struct LaunchCfg {
+  int n_cu;           // compute units
+  int blocks_per_cu;  // workgroups per CU for the global-grid kernels
+  int vector_cols;    // use G-wide column groups for all-column requests
 };
 
 struct AlphasDev {

@@ -33,6 +33,8 @@ _SIGS = {
     "pdf_validate_grid": [_i32, _P, _i32, _P, _P, _P],
     "pdf_validate_alphas": [_i32, _P, _P],
     "pdf_set_lds_policy": [_i32],
+    "pdf_set_tuning": [_i32, _i32],
+    "pdf_get_tuning": [_i32, _P],
     "pdf_shutdown": [],
 }
 for _name, _args in _SIGS.items():
@@ -195,6 +197,19 @@ def error_count(reset=False, stream=None):
 
 def set_lds_policy(policy):
     _check(_lib.pdf_set_lds_policy(int(policy)))
+
+
+TUNE_LDS_POLICY, TUNE_VECTOR_COLUMNS, TUNE_BLOCKS_PER_CU = 0, 1, 2
+
+
+def set_tuning(knob, value):
+    _check(_lib.pdf_set_tuning(int(knob), int(value)))
+
+
+def get_tuning(knob):
+    v = ctypes.c_int32(0)
+    _check(_lib.pdf_get_tuning(int(knob), ctypes.byref(v)))
+    return v.value
 
 
 def shutdown():

@@ -97,15 +97,18 @@ def test_locate_bit_exact(which, request):
 
 @pytest.mark.parametrize("which", ["cfg1", "cfg2"])
 @pytest.mark.parametrize("f32", [False, True])
-def test_xfxq2_parity_edges(which, f32, request):
+@pytest.mark.parametrize("vec", [0, 1])
+def test_xfxq2_parity_edges(which, f32, vec, request):
     g, m = request.getfixturevalue(which)
     rng = np.random.default_rng(2)
     x, q2 = edge_queries(g, rng)
     pdfmi.set_lds_policy(1)
+    pdfmi.set_tuning(pdfmi.TUNE_VECTOR_COLUMNS, vec)
     try:
         _, _, lit, mx = run_parity(m, g, g.pids, x, q2, f32=f32)
     finally:
         pdfmi.set_lds_policy(0)
+        pdfmi.set_tuning(pdfmi.TUNE_VECTOR_COLUMNS, 1)
     print("literal pass fraction %.6f, max eq.(1) %.3g" % (lit, mx))
 
 
@@ -166,10 +169,13 @@ def test_tiny_grids_all_regions(seed):
         x, q2 = edge_queries(g, rng, n_rand=800)
         for f32 in (False, True):
             for pol in (1, 2):
-                pdfmi.set_lds_policy(pol)
-                run_parity(m, g, g.pids, x, q2, f32=f32)
+                for vec in (0, 1):
+                    pdfmi.set_lds_policy(pol)
+                    pdfmi.set_tuning(pdfmi.TUNE_VECTOR_COLUMNS, vec)
+                    run_parity(m, g, g.pids, x, q2, f32=f32)
     finally:
         pdfmi.set_lds_policy(0)
+        pdfmi.set_tuning(pdfmi.TUNE_VECTOR_COLUMNS, 1)
         pdfmi.unload(m)
 
 
