@@ -179,6 +179,67 @@ enum { PDF_TUNE_LDS_POLICY = 0, PDF_TUNE_VECTOR_COLUMNS = 1, PDF_TUNE_BLOCKS_PER
 int pdf_set_tuning(int32_t knob, int32_t value);
 int pdf_get_tuning(int32_t knob, int32_t* value);
 
+/*
+ * Batched evaluation: many requests, each on its own member and flavour list
+ * (the multi-member evaluation of section 4.3), served by one persistent
+ * launch.  Workgroups take tiles (tile_points consecutive points of one
+ * request) from a device counter, stage the tile's member grid in LDS when it
+ * is not the one already staged, and evaluate it like pdf_xfxq2 (FP32 bulk
+ * arithmetic like pdf_xfxq2_f32 when out_f64 == 0, FP64 otherwise).
+ * Results are identical to the per-request calls for every tile size.
+ */
+typedef struct {
+    int32_t member;        /* id from pdf_load_grid */
+    int32_t n_pids;        /* requested flavours (ignored when pids == NULL) */
+    const int32_t* pids;   /* HOST list; NULL = every stored flavour in load order */
+    const double* x;       /* DEVICE [n] */
+    const double* q2;      /* DEVICE [n] */
+    int64_t n;             /* points (>= 0) */
+    void* out;             /* DEVICE point-major [n][P], float (out_f64 == 0) or double */
+} pdf_request;
+
+/*
+ * Build a plan (request, flavour and tile tables copied to the device).  The
+ * members and the x / q2 / out buffers named by the requests must stay valid
+ * for the plan's lifetime; running the plan again evaluates whatever the x
+ * and q2 buffers then hold.  *plan_out receives the plan id.
+ */
+int pdf_batch_create(const pdf_request* reqs, int32_t n_req, int32_t out_f64, int32_t* plan_out);
+/*
+ * Plan settings: tile_points (multiple of 64, default 4096), vector_cols
+ * (1: 16-byte column groups for requests of every stored flavour in order),
+ * use_graph (1: pdf_batch_run replays a hipGraph holding the counter reset
+ * and the persistent kernel, built on first use).
+ */
+int pdf_batch_configure(int32_t plan, int32_t tile_points, int32_t vector_cols, int32_t use_graph);
+/* Queue one evaluation of every request of the plan on stream. */
+int pdf_batch_run(int32_t plan, pdf_stream_t stream);
+/*
+ * Time the plan on stream for each tile size in {1024, 2048, 4096, 8192,
+ * 16384} and vector_cols in {0, 1} (reps timed runs each, after one warm-up;
+ * outputs are overwritten with identical values), keep the fastest, and
+ * remember it for plans with the same request signature in this process.
+ * Synchronises stream.  tile_out / vector_out (nullable) receive the choice.
+ */
+int pdf_batch_autotune(int32_t plan, int32_t reps, pdf_stream_t stream, int32_t* tile_out, int32_t* vector_out);
+int pdf_batch_destroy(int32_t plan);
+/* One-shot: create, run, synchronise stream, destroy. */
+int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, int32_t out_f64, pdf_stream_t stream);
+
+/*
+ * Monte-Carlo luminosity chunk sum (the integrand-shaped use of section 4.1:
+ * PDFs of both incoming partons at one scale, weighted by alpha_s):
+ *   *sum_out = sum_i alphas[i] * sum_j xf1[i*n_pids + j] * xf2[i*n_pids + j]
+ * in FP64, with a fixed summation order that depends only on n (the result
+ * is bit-identical from run to run).  xf1, xf2 (point-major [n][n_pids]),
+ * alphas, workspace and sum_out are DEVICE pointers; workspace holds at least
+ * pdf_mc_workspace_bytes(n) bytes and is overwritten.  n == 0 writes 0.
+ */
+int pdf_mc_workspace_bytes(int64_t n, int64_t* bytes_out);
+int pdf_mc_chunk_sum(const double* xf1, const double* xf2, int32_t n_pids,
+                     const double* alphas, int64_t n, double* workspace,
+                     double* sum_out, pdf_stream_t stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* pdf_last_error(void);
 

@@ -249,6 +249,140 @@ __host__ __device__ constexpr size_t wave_record_bytes() {
   return (size_t)kWave * (8 * sizeof(T) + 16 + 12);
 }
 
+// One wave's 64-point tile [pbeg, pbeg + tp): phase 1 (one lane per point)
+// into the wave's LDS record, then the in-grid outputs (one lane per entry),
+// then the extrapolated points.  obase = output row of point pbeg.
+template <typename T, bool kLdsGrid, int G>
+__device__ __forceinline__ void wave_tile(const MemberDev& m, const double* sknots, const int* scol, int R,
+                                          const T* sgrid, const T* __restrict__ gvals,
+                                          const double* __restrict__ X, const double* __restrict__ Q2,
+                                          int64_t pbeg, int tp, T* __restrict__ obase,
+                                          unsigned long long* __restrict__ nerr, double invL01,
+                                          unsigned char* rec, int lane) {
+  T* sw = reinterpret_cast<T*>(rec);                       // [64][4]
+  T* sv = sw + kWave * 4;                                  // [64][4]
+  double* sp = reinterpret_cast<double*>(sv + kWave * 4);  // [64][2]
+  int* sbase = reinterpret_cast<int*>(sp + 2 * kWave);
+  int* ssa = sbase + kWave;
+  int* smode = ssa + kWave;
+  const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
+  constexpr int kSlow = kLowX | kLowQ | kHighQ;
+  // lane -> (point, flavour) or (point, column group) walk of the tile's outputs
+  const int NE = G == 1 ? R : (R + G - 1) / G;
+  const int e_p0 = lane / NE, e_j0 = lane - (lane / NE) * NE;
+  const int e_dp = kWave / NE, e_dj = kWave - (kWave / NE) * NE;
+  bool bad = false, slow = false;
+  if (lane < tp) {
+    T w[4], v[4];
+    const PointLoc L = locate_point<T>(m, sknots, X[pbeg + lane], Q2[pbeg + lane], w, v);
+    bad = L.mode & kInvalid;
+    slow = L.mode & kSlow;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      sw[lane * 4 + a] = w[a];
+      sv[lane * 4 + a] = v[a];
+    }
+    sp[2 * lane] = L.p0;
+    sp[2 * lane + 1] = L.p1;
+    sbase[lane] = L.base;
+    ssa[lane] = L.sa;
+    smode[lane] = L.mode;
+  }
+  const unsigned long long bal = __ballot(bad);
+  if (bal && lane == 0) atomicAdd(nerr, (unsigned long long)__popcll(bal));
+  unsigned long long slow_mask = __ballot(slow);
+  // records written by this wave are read back by other lanes of the same wave
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  const int nev = tp * NE;
+  int p = e_p0, j = e_j0;
+  for (int e = lane; e < nev; e += kWave) {
+    const int mode = smode[p];
+    if (!(mode & kSlow)) {
+      T w[4], v[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        w[a] = sw[p * 4 + a];
+        v[a] = sv[p * 4 + a];
+      }
+      const int base = sbase[p], sa = ssa[p];
+      const bool inv = mode & kInvalid;
+      if constexpr (G == 1) {
+        const int col = scol[j];
+        T val = (T)0;
+        if (inv) {
+          val = (T)NAN;
+        } else if (col >= 0) {
+          T F[4][4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int o = base + col + a * sa;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) F[a][b] = kLdsGrid ? sgrid[o + b * Pp] : gvals[o + b * Pp];
+          }
+          val = interp_stencil<T>(F, w, v);
+        }
+        obase[e] = val;
+      } else {
+        using V = typename VecOf<T, G>::type;
+        T res[G];
+        if (inv) {
+#pragma unroll
+          for (int i = 0; i < G; ++i) res[i] = (T)NAN;
+        } else {
+          T F[G][4][4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int o = base + G * j + a * sa;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const V q = kLdsGrid ? *reinterpret_cast<const V*>(sgrid + o + b * Pp)
+                                   : *reinterpret_cast<const V*>(gvals + o + b * Pp);
+              const T* qs = reinterpret_cast<const T*>(&q);
+#pragma unroll
+              for (int i = 0; i < G; ++i) F[i][a][b] = qs[i];
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < G; ++i) res[i] = interp_stencil<T>(F[i], w, v);
+        }
+        T* o = obase + p * R + G * j;
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+          if (G * j + i < R) o[i] = res[i];
+      }
+    }
+    p += e_dp;
+    j += e_dj;
+    if (j >= NE) {
+      j -= NE;
+      ++p;
+    }
+  }
+  // extrapolated points of the tile, one at a time across the wave
+  while (slow_mask) {
+    const int q = __builtin_ctzll(slow_mask);
+    slow_mask &= slow_mask - 1;
+    const int mode = smode[q];
+    const Wts wt{(double)sw[q * 4], (double)sw[q * 4 + 1], (double)sw[q * 4 + 2], (double)sw[q * 4 + 3],
+                 (double)sv[q * 4], (double)sv[q * 4 + 1], (double)sv[q * 4 + 2], (double)sv[q * 4 + 3]};
+    for (int jj = lane; jj < R; jj += kWave) {
+      const int col = scol[jj];
+      T val = (T)0;
+      if (col >= 0) {
+        const T* f = (kLdsGrid ? (const T*)sgrid : gvals) + sbase[q] + col;
+        val = (T)extrap_entry<T>(f, ssa[q], Pp, mode, wt, sp[2 * q], sp[2 * q + 1], invL01);
+      }
+      obase[q * R + jj] = val;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T, bool kLdsGrid, int G, int BS>
 __global__ __launch_bounds__(BS) void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X,
                                               const double* __restrict__ Q2, int64_t n, T* __restrict__ out,
@@ -272,135 +406,13 @@ __global__ __launch_bounds__(BS) void k_xfxq2(MemberDev m, ReqCols rc, const dou
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   unsigned char* rec = srec + wv * wave_record_bytes<T>();
-  T* sw = reinterpret_cast<T*>(rec);                       // [64][4]
-  T* sv = sw + kWave * 4;                                  // [64][4]
-  double* sp = reinterpret_cast<double*>(sv + kWave * 4);  // [64][2]
-  int* sbase = reinterpret_cast<int*>(sp + 2 * kWave);
-  int* ssa = sbase + kWave;
-  int* smode = ssa + kWave;
-
   const int R = rc.n;
-  const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
-  constexpr int kSlow = kLowX | kLowQ | kHighQ;
-  // lane -> (point, flavour) or (point, column group) walk of the wave's outputs
-  const int NE = G == 1 ? R : (R + G - 1) / G;
-  const int e_p0 = lane / NE, e_j0 = lane - (lane / NE) * NE;
-  const int e_dp = kWave / NE, e_dj = kWave - (kWave / NE) * NE;
   const int64_t ntiles = (n + kWave - 1) / kWave;
   for (int64_t tile = (int64_t)blockIdx.x * kWaves + wv; tile < ntiles; tile += (int64_t)gridDim.x * kWaves) {
     const int64_t pbeg = tile * kWave;
     const int tp = (int)min((int64_t)kWave, n - pbeg);
-    bool bad = false, slow = false;
-    if (lane < tp) {
-      T w[4], v[4];
-      const PointLoc L = locate_point<T>(m, sknots, X[pbeg + lane], Q2[pbeg + lane], w, v);
-      bad = L.mode & kInvalid;
-      slow = L.mode & kSlow;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        sw[lane * 4 + a] = w[a];
-        sv[lane * 4 + a] = v[a];
-      }
-      sp[2 * lane] = L.p0;
-      sp[2 * lane + 1] = L.p1;
-      sbase[lane] = L.base;
-      ssa[lane] = L.sa;
-      smode[lane] = L.mode;
-    }
-    const unsigned long long bal = __ballot(bad);
-    if (bal && lane == 0) atomicAdd(nerr, (unsigned long long)__popcll(bal));
-    unsigned long long slow_mask = __ballot(slow);
-    // records written by this wave are read back by other lanes of the same wave
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    T* obase = out + pbeg * R;
-    const int nev = tp * NE;
-    int p = e_p0, j = e_j0;
-    for (int e = lane; e < nev; e += kWave) {
-      const int mode = smode[p];
-      if (!(mode & kSlow)) {
-        T w[4], v[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          w[a] = sw[p * 4 + a];
-          v[a] = sv[p * 4 + a];
-        }
-        const int base = sbase[p], sa = ssa[p];
-        const bool inv = mode & kInvalid;
-        if constexpr (G == 1) {
-          const int col = scol[j];
-          T val = (T)0;
-          if (inv) {
-            val = (T)NAN;
-          } else if (col >= 0) {
-            T F[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-              const int o = base + col + a * sa;
-#pragma unroll
-              for (int b = 0; b < 4; ++b) F[a][b] = kLdsGrid ? sgrid[o + b * Pp] : gvals[o + b * Pp];
-            }
-            val = interp_stencil<T>(F, w, v);
-          }
-          obase[e] = val;
-        } else {
-          using V = typename VecOf<T, G>::type;
-          T res[G];
-          if (inv) {
-#pragma unroll
-            for (int i = 0; i < G; ++i) res[i] = (T)NAN;
-          } else {
-            T F[G][4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-              const int o = base + G * j + a * sa;
-#pragma unroll
-              for (int b = 0; b < 4; ++b) {
-                const V q = kLdsGrid ? *reinterpret_cast<const V*>(sgrid + o + b * Pp)
-                                     : *reinterpret_cast<const V*>(gvals + o + b * Pp);
-                const T* qs = reinterpret_cast<const T*>(&q);
-#pragma unroll
-                for (int i = 0; i < G; ++i) F[i][a][b] = qs[i];
-              }
-            }
-#pragma unroll
-            for (int i = 0; i < G; ++i) res[i] = interp_stencil<T>(F[i], w, v);
-          }
-          T* o = obase + p * R + G * j;
-#pragma unroll
-          for (int i = 0; i < G; ++i)
-            if (G * j + i < R) o[i] = res[i];
-        }
-      }
-      p += e_dp;
-      j += e_dj;
-      if (j >= NE) {
-        j -= NE;
-        ++p;
-      }
-    }
-    // extrapolated points of the tile, one at a time across the wave
-    while (slow_mask) {
-      const int q = __builtin_ctzll(slow_mask);
-      slow_mask &= slow_mask - 1;
-      const int mode = smode[q];
-      const Wts wt{(double)sw[q * 4], (double)sw[q * 4 + 1], (double)sw[q * 4 + 2], (double)sw[q * 4 + 3],
-                   (double)sv[q * 4], (double)sv[q * 4 + 1], (double)sv[q * 4 + 2], (double)sv[q * 4 + 3]};
-      for (int jj = lane; jj < R; jj += kWave) {
-        const int col = scol[jj];
-        T val = (T)0;
-        if (col >= 0) {
-          const T* f = (kLdsGrid ? (const T*)sgrid : gvals) + sbase[q] + col;
-          val = (T)extrap_entry<T>(f, ssa[q], Pp, mode, wt, sp[2 * q], sp[2 * q + 1], invL01);
-        }
-        obase[q * R + jj] = val;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_tile<T, kLdsGrid, G>(m, sknots, scol, R, sgrid, gvals, X, Q2, pbeg, tp, out + pbeg * R, nerr, invL01, rec,
+                              lane);
   }
 }
 
@@ -529,6 +541,177 @@ hipError_t launch_alphas(const AlphasDev& A, const double* q2, int64_t n, double
   const int64_t nb = min((n + 255) / 256, (int64_t)n_cu * 16);
   hipLaunchKernelGGL(k_alphas, dim3((unsigned)nb), dim3(256), 0, s, A, q2, n, out, nerr);
   return hipGetLastError();
+}
+
+}  // namespace pdfmi
+
+namespace pdfmi {
+
+// ---------------------------------------------------------------------------------------
+// Monte-Carlo luminosity chunk sum (the integrand-shaped load of the paper's
+// section 4.1): S = sum_i alpha_s(Q^2_i) * sum_j xf1[i][j] * xf2[i][j], FP64,
+// in a fixed order that depends only on n: stage 1 gives one partial per
+// block of kMcBlock points (each thread sums its strided points in index
+// order, then a fixed binary tree in LDS); stage 2 sums the partials with the
+// same tree in one workgroup.  Bit-identical across runs.
+constexpr int kMcThreads = 256;
+constexpr int kMcBlock = 4096;
+
+__device__ __forceinline__ double block_tree_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kMcThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ __launch_bounds__(kMcThreads) void k_mc_partial(const double* __restrict__ xf1, const double* __restrict__ xf2,
+                                                           int P, const double* __restrict__ as, int64_t n,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[kMcThreads];
+  const int64_t beg = (int64_t)blockIdx.x * kMcBlock;
+  const int64_t end = min(beg + kMcBlock, n);
+  double acc = 0.0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += kMcThreads) {
+    double lum = 0.0;
+    for (int j = 0; j < P; ++j) lum = fma(xf1[i * P + j], xf2[i * P + j], lum);
+    acc = fma(as[i], lum, acc);
+  }
+  const double s = block_tree_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kMcThreads) void k_mc_final(const double* __restrict__ partial, int64_t np,
+                                                         double* __restrict__ sum_out) {
+  __shared__ double sh[kMcThreads];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < np; i += kMcThreads) acc += partial[i];
+  const double s = block_tree_sum(acc, sh);
+  if (threadIdx.x == 0) *sum_out = s;
+}
+
+int64_t mc_partials(int64_t n) { return (n + kMcBlock - 1) / kMcBlock; }
+
+hipError_t launch_mc_sum(const double* xf1, const double* xf2, int P, const double* as, int64_t n, double* partial,
+                         double* sum_out, hipStream_t s) {
+  const int64_t np = mc_partials(n);
+  if (np > 0)
+    hipLaunchKernelGGL(k_mc_partial, dim3((unsigned)np), dim3(kMcThreads), 0, s, xf1, xf2, P, as, n, partial);
+  hipLaunchKernelGGL(k_mc_final, dim3(1), dim3(kMcThreads), 0, s, partial, np, sum_out);
+  return hipGetLastError();
+}
+
+}  // namespace pdfmi
+
+namespace pdfmi {
+
+// ---------------------------------------------------------------------------------------
+// Batched evaluation of many requests over many members (the paper's
+// multi-member evaluation of section 4.3): one persistent launch in which
+// each workgroup repeatedly takes the next tile from a global counter,
+// stages that tile's member grid (and knots) in LDS when it differs from the
+// one already staged, and runs the same per-wave tile pipeline as k_xfxq2.
+// Every wave reaches the exit once the counter passes the tile count.
+constexpr int kBatchBS = 1024;
+
+__global__ void k_batch_reset(unsigned* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+template <typename T, bool kLdsGrid>
+__global__ __launch_bounds__(kBatchBS) void k_batched(const BatchReq* __restrict__ reqs, const int* __restrict__ cols,
+                                                      const BatchTile* __restrict__ tiles, int ntiles,
+                                                      const MemberDev* __restrict__ members,
+                                                      const double* __restrict__ invL01s, unsigned* counter,
+                                                      unsigned long long* __restrict__ nerr, int max_knots,
+                                                      int vector_cols) {
+  constexpr int kWaves = kBatchBS / kWave;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_tile, s_member;
+  double* sknots = reinterpret_cast<double*>(smem);                        // [max_knots]
+  int* scol = reinterpret_cast<int*>(sknots + max_knots);                  // [kMaxReq]
+  unsigned char* srec = reinterpret_cast<unsigned char*>(scol + kMaxReq);  // per-wave records
+  T* sgrid = reinterpret_cast<T*>(srec + kWaves * wave_record_bytes<T>());
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  unsigned char* rec = srec + wv * wave_record_bytes<T>();
+  if (threadIdx.x == 0) s_member = -1;
+  for (;;) {
+    __syncthreads();  // previous tile finished by every wave before the LDS is reused
+    if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int t = s_tile;
+    if (t >= ntiles) break;
+    const BatchTile tl = tiles[t];
+    const BatchReq rq = reqs[tl.req];
+    const MemberDev& m = members[rq.member];
+    const T* __restrict__ gvals = member_values<T>(m);
+    if (rq.member != s_member) {
+      for (int i = threadIdx.x; i < m.nknots; i += kBatchBS) sknots[i] = m.knots[i];
+      if constexpr (kLdsGrid) {
+        const int64_t ne = sizeof(T) == 8 ? m.elems64 : m.elems32;
+        for (int64_t i = threadIdx.x; i < ne; i += kBatchBS) sgrid[i] = gvals[i];
+      }
+    }
+    for (int i = threadIdx.x; i < rq.R; i += kBatchBS) scol[i] = cols[rq.col_off + i];
+    __syncthreads();
+    if (threadIdx.x == 0) s_member = rq.member;
+    const double invL01 = invL01s[rq.member];
+    T* out = reinterpret_cast<T*>(rq.out);
+    for (int w0 = wv * kWave; w0 < tl.count; w0 += kWaves * kWave) {
+      const int64_t pbeg = tl.start + w0;
+      const int tp = min(kWave, tl.count - w0);
+      if (vector_cols && rq.all_cols)
+        wave_tile<T, kLdsGrid, 16 / sizeof(T)>(m, sknots, scol, rq.R, sgrid, gvals, rq.x, rq.q2, pbeg, tp,
+                                               out + pbeg * rq.R, nerr, invL01, rec, lane);
+      else
+        wave_tile<T, kLdsGrid, 1>(m, sknots, scol, rq.R, sgrid, gvals, rq.x, rq.q2, pbeg, tp, out + pbeg * rq.R,
+                                  nerr, invL01, rec, lane);
+    }
+  }
+}
+
+size_t batch_shared_bytes(int max_knots, bool f32) {
+  return (size_t)max_knots * 8 + kMaxReq * 4 +
+         (kBatchBS / kWave) * (f32 ? wave_record_bytes<float>() : wave_record_bytes<double>());
+}
+
+// Kernel node parameters of one batched run: the counter reset and the
+// persistent kernel (used for direct launches and for building a hipGraph).
+struct BatchLaunch {
+  const void* reset_fn;
+  const void* main_fn;
+  unsigned grid;
+  size_t shm;
+};
+
+BatchLaunch batch_launch_params(bool f32, bool lds, int max_knots, int64_t max_elems, int n_cu, int blocks_per_cu,
+                                int ntiles) {
+  BatchLaunch L{};
+  L.reset_fn = reinterpret_cast<const void*>(&k_batch_reset);
+  L.shm = batch_shared_bytes(max_knots, f32) + (lds ? (size_t)max_elems * (f32 ? 4 : 8) : 0);
+  if (f32)
+    L.main_fn = lds ? reinterpret_cast<const void*>(&k_batched<float, true>)
+                    : reinterpret_cast<const void*>(&k_batched<float, false>);
+  else
+    L.main_fn = lds ? reinterpret_cast<const void*>(&k_batched<double, true>)
+                    : reinterpret_cast<const void*>(&k_batched<double, false>);
+  const int64_t g = min((int64_t)ntiles, (int64_t)n_cu * blocks_per_cu);
+  L.grid = (unsigned)max((int64_t)1, g);
+  return L;
+}
+
+hipError_t batch_prepare(const BatchLaunch& L) {
+  return hipFuncSetAttribute(L.main_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.shm);
+}
+
+hipError_t batch_launch(const BatchLaunch& L, void** args, unsigned* counter, hipStream_t s) {
+  void* rargs[] = {&counter};
+  hipError_t e = hipLaunchKernel(L.reset_fn, dim3(1), dim3(64), rargs, 0, s);
+  if (e != hipSuccess) return e;
+  return hipLaunchKernel(L.main_fn, dim3(L.grid), dim3(kBatchBS), args, L.shm, s);
 }
 
 }  // namespace pdfmi

@@ -5,11 +5,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -25,6 +27,19 @@ hipError_t launch_xfxq2_f32(const MemberDev&, const ReqCols&, const double*, con
 hipError_t launch_locate(const MemberDev&, const double*, const double*, int64_t, int32_t*, int32_t*, int32_t*,
                          int8_t*, int, hipStream_t);
 hipError_t launch_alphas(const AlphasDev&, const double*, int64_t, double*, unsigned long long*, int, hipStream_t);
+int64_t mc_partials(int64_t n);
+struct BatchLaunch {
+  const void* reset_fn;
+  const void* main_fn;
+  unsigned grid;
+  size_t shm;
+};
+size_t batch_shared_bytes(int max_knots, bool f32);
+BatchLaunch batch_launch_params(bool f32, bool lds, int max_knots, int64_t max_elems, int n_cu, int blocks_per_cu,
+                                int ntiles);
+hipError_t batch_prepare(const BatchLaunch& L);
+hipError_t batch_launch(const BatchLaunch& L, void** args, unsigned* counter, hipStream_t s);
+hipError_t launch_mc_sum(const double*, const double*, int, const double*, int64_t, double*, double*, hipStream_t);
 }  // namespace pdfmi
 
 using namespace pdfmi;
@@ -513,6 +528,378 @@ extern "C" int pdf_get_tuning(int32_t knob, int32_t* value) {
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Batched plans
+
+namespace {
+
+struct Plan {
+  bool used = false;
+  int out_f64 = 0;
+  int tile_points = 4096;
+  int blocks_per_cu = 1;
+  int vector_cols = 1;
+  int use_graph = 0;
+  bool lds = false;
+  int max_knots = 0;
+  int64_t max_elems = 0;
+  std::vector<BatchReq> reqs;
+  std::vector<int> cols;
+  std::vector<MemberDev> members;
+  std::vector<double> invL01;
+  int ntiles = 0;
+  void* dmem = nullptr;        // reqs, cols, members, invL01, counter
+  BatchTile* d_tiles = nullptr;
+  int tiles_cap = 0;
+  BatchReq* d_reqs = nullptr;
+  int* d_cols = nullptr;
+  MemberDev* d_members = nullptr;
+  double* d_invL01 = nullptr;
+  unsigned* d_counter = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // kernel argument storage (addresses handed to hipLaunchKernel / graph nodes)
+  int a_ntiles = 0, a_max_knots = 0, a_vec = 0;
+  void* args[10];
+};
+
+std::vector<Plan> g_plans;
+
+void plan_free_graph(Plan& P) {
+  if (P.exec) (void)hipGraphExecDestroy(P.exec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
+  P.exec = nullptr;
+  P.graph = nullptr;
+}
+
+void plan_release(Plan& P) {
+  plan_free_graph(P);
+  if (P.dmem) (void)hipFree(P.dmem);
+  if (P.d_tiles) (void)hipFree(P.d_tiles);
+  P = Plan();
+}
+
+// (Re)build the tile list for the plan's tile size and upload it.
+int plan_tiles(Plan& P) {
+  std::vector<BatchTile> t;
+  // tiles grouped by member so that consecutive tiles tend to share a staged grid
+  std::vector<int> order(P.reqs.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P.reqs[a].member < P.reqs[b].member; });
+  for (int r : order)
+    for (int64_t s0 = 0; s0 < P.reqs[r].n; s0 += P.tile_points)
+      t.push_back(BatchTile{r, (int)std::min<int64_t>(P.tile_points, P.reqs[r].n - s0), s0});
+  if ((int64_t)t.size() > (1LL << 30)) return fail(PDF_ERR_ARG, "too many tiles");
+  P.ntiles = (int)t.size();
+  if (P.ntiles > P.tiles_cap) {
+    if (P.d_tiles) (void)hipFree(P.d_tiles);
+    P.d_tiles = nullptr;
+    hipError_t e = hipMalloc(&P.d_tiles, sizeof(BatchTile) * std::max(1, P.ntiles));
+    if (e != hipSuccess) return fail_hip(e, "hipMalloc(tiles)");
+    P.tiles_cap = P.ntiles;
+  }
+  if (P.ntiles) {
+    hipError_t e = hipMemcpy(P.d_tiles, t.data(), sizeof(BatchTile) * t.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpy(tiles)");
+  }
+  return PDF_OK;
+}
+
+BatchLaunch plan_params(const Plan& P) {
+  return batch_launch_params(!P.out_f64, P.lds, P.max_knots, P.max_elems, g_ncu, P.blocks_per_cu, P.ntiles);
+}
+
+void plan_args(Plan& P) {
+  P.a_ntiles = P.ntiles;
+  P.a_max_knots = P.max_knots;
+  P.a_vec = P.vector_cols;
+  P.args[0] = &P.d_reqs;
+  P.args[1] = &P.d_cols;
+  P.args[2] = &P.d_tiles;
+  P.args[3] = &P.a_ntiles;
+  P.args[4] = &P.d_members;
+  P.args[5] = &P.d_invL01;
+  P.args[6] = &P.d_counter;
+  P.args[7] = &g_nerr;
+  P.args[8] = &P.a_max_knots;
+  P.args[9] = &P.a_vec;
+}
+
+int plan_build_graph(Plan& P) {
+  plan_free_graph(P);
+  const BatchLaunch L = plan_params(P);
+  hipError_t e = batch_prepare(L);
+  if (e != hipSuccess) return fail_hip(e, "hipFuncSetAttribute(batched)");
+  if ((e = hipGraphCreate(&P.graph, 0)) != hipSuccess) return fail_hip(e, "hipGraphCreate");
+  hipKernelNodeParams r{};
+  void* rargs[] = {&P.d_counter};
+  r.func = const_cast<void*>(L.reset_fn);
+  r.gridDim = dim3(1);
+  r.blockDim = dim3(64);
+  r.sharedMemBytes = 0;
+  r.kernelParams = rargs;
+  hipGraphNode_t n1, n2;
+  if ((e = hipGraphAddKernelNode(&n1, P.graph, nullptr, 0, &r)) != hipSuccess) return fail_hip(e, "graph node");
+  hipKernelNodeParams k{};
+  k.func = const_cast<void*>(L.main_fn);
+  k.gridDim = dim3(L.grid);
+  k.blockDim = dim3(1024);
+  k.sharedMemBytes = (unsigned)L.shm;
+  k.kernelParams = P.args;
+  if ((e = hipGraphAddKernelNode(&n2, P.graph, &n1, 1, &k)) != hipSuccess) return fail_hip(e, "graph node");
+  if ((e = hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0)) != hipSuccess)
+    return fail_hip(e, "hipGraphInstantiate");
+  return PDF_OK;
+}
+
+int plan_run(Plan& P, hipStream_t s) {
+  if (P.ntiles == 0) return PDF_OK;
+  plan_args(P);
+  if (P.use_graph) {
+    if (!P.exec) {
+      int rc = plan_build_graph(P);
+      if (rc != PDF_OK) return rc;
+    }
+    hipError_t e = hipGraphLaunch(P.exec, s);
+    if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+    return PDF_OK;
+  }
+  const BatchLaunch L = plan_params(P);
+  hipError_t e = batch_prepare(L);
+  if (e != hipSuccess) return fail_hip(e, "hipFuncSetAttribute(batched)");
+  e = batch_launch(L, P.args, P.d_counter, s);
+  if (e != hipSuccess) return fail_hip(e, "launch batched");
+  return PDF_OK;
+}
+
+Plan* get_plan(int32_t id) {
+  if (id < 0 || id >= (int32_t)g_plans.size() || !g_plans[id].used) return nullptr;
+  return &g_plans[id];
+}
+
+std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+}  // namespace
+
+extern "C" int pdf_batch_create(const pdf_request* reqs, int32_t n_req, int32_t out_f64, int32_t* plan_out) {
+  if (!plan_out || (n_req > 0 && !reqs) || n_req < 0) return fail(PDF_ERR_ARG, "bad argument");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int rc = ensure_init();
+  if (rc != PDF_OK) return rc;
+  Plan P;
+  P.used = true;
+  P.out_f64 = out_f64 ? 1 : 0;
+  std::map<int, int> slot;  // member id -> plan member index
+  for (int i = 0; i < n_req; ++i) {
+    const pdf_request& q = reqs[i];
+    if (q.n < 0) return fail(PDF_ERR_ARG, "request %d: n < 0", i);
+    if (q.n > 0 && (!q.x || !q.q2 || !q.out)) return fail(PDF_ERR_ARG, "request %d: null device pointer", i);
+    Member* M = get_member(q.member);
+    if (!M) return fail(PDF_ERR_MEMBER, "request %d: unknown member %d", i, q.member);
+    ReqCols rcols{};
+    if ((rc = build_req(*M, q.pids, q.n_pids, rcols)) != PDF_OK) return rc;
+    if (!slot.count(q.member)) {
+      slot[q.member] = (int)P.members.size();
+      P.members.push_back(M->dev);
+      P.invL01.push_back(M->invL01);
+      P.max_knots = std::max(P.max_knots, M->dev.nknots_pad);
+      P.max_elems = std::max(P.max_elems, P.out_f64 ? M->dev.elems64 : M->dev.elems32);
+    }
+    BatchReq b{};
+    b.member = slot[q.member];
+    b.R = rcols.n;
+    b.col_off = (int)P.cols.size();
+    b.all_cols = rcols.n == M->dev.P;
+    for (int j = 0; j < rcols.n; ++j) {
+      P.cols.push_back(rcols.col[j]);
+      if (rcols.col[j] != j) b.all_cols = 0;
+    }
+    b.x = q.x;
+    b.q2 = q.q2;
+    b.out = q.out;
+    b.n = q.n;
+    P.reqs.push_back(b);
+  }
+  const size_t fixed = batch_shared_bytes(P.max_knots, !P.out_f64);
+  P.lds = fixed + (size_t)P.max_elems * (P.out_f64 ? 8 : 4) <= kLdsBytes - 1024;
+  if (!P.lds && fixed > kLdsBytes - 1024) return fail(PDF_ERR_GRID, "too many knots for the batched kernel");
+  P.blocks_per_cu = 1;
+  const size_t br = align_up(sizeof(BatchReq) * std::max<size_t>(1, P.reqs.size()), 256);
+  const size_t bc = align_up(sizeof(int) * std::max<size_t>(1, P.cols.size()), 256);
+  const size_t bm = align_up(sizeof(MemberDev) * std::max<size_t>(1, P.members.size()), 256);
+  const size_t bi = align_up(sizeof(double) * std::max<size_t>(1, P.invL01.size()), 256);
+  hipError_t e = hipMalloc(&P.dmem, br + bc + bm + bi + 256);
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc(plan)");
+  unsigned char* b = static_cast<unsigned char*>(P.dmem);
+  P.d_reqs = reinterpret_cast<BatchReq*>(b);
+  P.d_cols = reinterpret_cast<int*>(b + br);
+  P.d_members = reinterpret_cast<MemberDev*>(b + br + bc);
+  P.d_invL01 = reinterpret_cast<double*>(b + br + bc + bm);
+  P.d_counter = reinterpret_cast<unsigned*>(b + br + bc + bm + bi);
+  if (!P.reqs.empty() && (e = hipMemcpy(P.d_reqs, P.reqs.data(), sizeof(BatchReq) * P.reqs.size(),
+                                        hipMemcpyHostToDevice)) != hipSuccess) {
+    plan_release(P);
+    return fail_hip(e, "hipMemcpy(plan)");
+  }
+  if (!P.cols.empty() &&
+      (e = hipMemcpy(P.d_cols, P.cols.data(), sizeof(int) * P.cols.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+    plan_release(P);
+    return fail_hip(e, "hipMemcpy(plan)");
+  }
+  if (!P.members.empty() && ((e = hipMemcpy(P.d_members, P.members.data(), sizeof(MemberDev) * P.members.size(),
+                                            hipMemcpyHostToDevice)) != hipSuccess ||
+                             (e = hipMemcpy(P.d_invL01, P.invL01.data(), sizeof(double) * P.invL01.size(),
+                                            hipMemcpyHostToDevice)) != hipSuccess)) {
+    plan_release(P);
+    return fail_hip(e, "hipMemcpy(plan)");
+  }
+  if ((rc = plan_tiles(P)) != PDF_OK) {
+    plan_release(P);
+    return rc;
+  }
+  for (size_t i = 0; i < g_plans.size(); ++i)
+    if (!g_plans[i].used) {
+      g_plans[i] = P;
+      *plan_out = (int32_t)i;
+      return PDF_OK;
+    }
+  g_plans.push_back(P);
+  *plan_out = (int32_t)(g_plans.size() - 1);
+  return PDF_OK;
+}
+
+extern "C" int pdf_batch_configure(int32_t plan, int32_t tile_points, int32_t vector_cols, int32_t use_graph) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  Plan* P = get_plan(plan);
+  if (!P) return fail(PDF_ERR_ARG, "unknown plan %d", plan);
+  if (tile_points < 64 || tile_points > (1 << 22) || (tile_points & 63))
+    return fail(PDF_ERR_ARG, "tile_points must be a multiple of 64 in [64, 4194304]");
+  if (vector_cols < 0 || vector_cols > 1 || use_graph < 0 || use_graph > 1)
+    return fail(PDF_ERR_ARG, "flags must be 0 or 1");
+  plan_free_graph(*P);
+  P->vector_cols = vector_cols;
+  P->use_graph = use_graph;
+  if (tile_points != P->tile_points) {
+    P->tile_points = tile_points;
+    return plan_tiles(*P);
+  }
+  return PDF_OK;
+}
+
+extern "C" int pdf_batch_run(int32_t plan, pdf_stream_t stream) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  Plan* P = get_plan(plan);
+  if (!P) return fail(PDF_ERR_ARG, "unknown plan %d", plan);
+  return plan_run(*P, (hipStream_t)stream);
+}
+
+extern "C" int pdf_batch_autotune(int32_t plan, int32_t reps, pdf_stream_t stream, int32_t* tile_out,
+                                  int32_t* vector_out) {
+  if (reps < 1) return fail(PDF_ERR_ARG, "reps must be >= 1");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Plan* P = get_plan(plan);
+  if (!P) return fail(PDF_ERR_ARG, "unknown plan %d", plan);
+  hipStream_t s = (hipStream_t)stream;
+  // signature of the work: request count, point total, flavour total, precision
+  int64_t pts = 0, evals = 0;
+  for (auto& r : P->reqs) {
+    pts += r.n;
+    evals += r.n * r.R;
+  }
+  char key[160];
+  snprintf(key, sizeof key, "%zu/%lld/%lld/%d/%d", P->reqs.size(), (long long)pts, (long long)evals, P->out_f64,
+           (int)P->lds);
+  auto it = g_tune_cache.find(key);
+  int best_tile = P->tile_points, best_vec = P->vector_cols;
+  if (it != g_tune_cache.end()) {
+    best_tile = it->second.first;
+    best_vec = it->second.second;
+  } else {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      return fail(PDF_ERR_DEVICE, "hipEventCreate");
+    float best = 1e30f;
+    const int saved_graph = P->use_graph;
+    P->use_graph = 0;
+    for (int tp : {1024, 2048, 4096, 8192, 16384}) {
+      for (int vec : {0, 1}) {
+        P->tile_points = tp;
+        P->vector_cols = vec;
+        int rc = plan_tiles(*P);
+        if (rc != PDF_OK) return rc;
+        if ((rc = plan_run(*P, s)) != PDF_OK) return rc;  // warm-up
+        float tot = 0.0f;
+        for (int r = 0; r < reps; ++r) {
+          (void)hipEventRecord(e0, s);
+          if ((rc = plan_run(*P, s)) != PDF_OK) return rc;
+          (void)hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) return fail(PDF_ERR_DEVICE, "hipEventSynchronize");
+          float ms = 0.0f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          tot += ms;
+        }
+        if (tot < best) {
+          best = tot;
+          best_tile = tp;
+          best_vec = vec;
+        }
+      }
+    }
+    P->use_graph = saved_graph;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_tune_cache[key] = {best_tile, best_vec};
+  }
+  plan_free_graph(*P);
+  P->tile_points = best_tile;
+  P->vector_cols = best_vec;
+  int rc = plan_tiles(*P);
+  if (rc != PDF_OK) return rc;
+  if (tile_out) *tile_out = best_tile;
+  if (vector_out) *vector_out = best_vec;
+  return PDF_OK;
+}
+
+extern "C" int pdf_batch_destroy(int32_t plan) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  Plan* P = get_plan(plan);
+  if (!P) return fail(PDF_ERR_ARG, "unknown plan %d", plan);
+  plan_release(*P);
+  return PDF_OK;
+}
+
+extern "C" int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, int32_t out_f64, pdf_stream_t stream) {
+  int32_t plan = -1;
+  int rc = pdf_batch_create(reqs, n_req, out_f64, &plan);
+  if (rc != PDF_OK) return rc;
+  rc = pdf_batch_run(plan, stream);
+  if (rc == PDF_OK) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) rc = fail_hip(e, "hipStreamSynchronize");
+  }
+  pdf_batch_destroy(plan);
+  return rc;
+}
+
+extern "C" int pdf_mc_workspace_bytes(int64_t n, int64_t* bytes_out) {
+  if (!bytes_out || n < 0) return fail(PDF_ERR_ARG, "bad argument");
+  *bytes_out = (n == 0 ? 1 : mc_partials(n)) * (int64_t)sizeof(double);
+  return PDF_OK;
+}
+
+extern "C" int pdf_mc_chunk_sum(const double* xf1, const double* xf2, int32_t n_pids, const double* alphas, int64_t n,
+                                double* workspace, double* sum_out, pdf_stream_t stream) {
+  if (n < 0 || n_pids < 1 || n_pids > kMaxReq) return fail(PDF_ERR_ARG, "bad n or n_pids");
+  if (!sum_out || !workspace) return fail(PDF_ERR_ARG, "null output or workspace");
+  if (n > 0 && (!xf1 || !xf2 || !alphas)) return fail(PDF_ERR_ARG, "null input");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int rc = ensure_init();
+  if (rc != PDF_OK) return rc;
+  hipError_t e = launch_mc_sum(xf1, xf2, n_pids, alphas, n, workspace, sum_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "launch mc sum");
+  return PDF_OK;
+}
+
 extern "C" int pdf_set_lds_policy(int32_t policy) {
   if (policy < 0 || policy > 2) return fail(PDF_ERR_ARG, "policy must be 0, 1 or 2");
   std::lock_guard<std::mutex> lock(g_mu);
@@ -530,6 +917,9 @@ extern "C" int pdf_shutdown(void) {
   if (g_alphas_mem) (void)hipFree(g_alphas_mem);
   g_alphas_mem = nullptr;
   g_has_alphas = false;
+  for (auto& P : g_plans)
+    if (P.used) plan_release(P);
+  g_plans.clear();
   if (g_nerr) (void)hipFree(g_nerr);
   g_nerr = nullptr;
   g_init = false;

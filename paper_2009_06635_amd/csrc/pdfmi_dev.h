@@ -80,3 +80,27 @@ struct AlphasDev {
 };
 
 }  // namespace pdfmi
+
+namespace pdfmi {
+
+// One request of a batched plan (device copy).
+struct BatchReq {
+  int member;        // index into the plan's member table
+  int R;             // requested flavours
+  int col_off;       // offset of this request's column list in the plan's column array
+  int all_cols;      // 1 if the request is every stored column in load order
+  const double* x;
+  const double* q2;
+  void* out;         // FP32 or FP64 point-major [n][R], per the plan
+  int64_t n;
+};
+
+// A tile: tile_points consecutive points of one request (the last tile of a
+// request may be shorter).
+struct BatchTile {
+  int req;
+  int count;
+  int64_t start;
+};
+
+}  // namespace pdfmi

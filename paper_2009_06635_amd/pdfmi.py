@@ -35,6 +35,14 @@ _SIGS = {
     "pdf_set_lds_policy": [_i32],
     "pdf_set_tuning": [_i32, _i32],
     "pdf_get_tuning": [_i32, _P],
+    "pdf_mc_workspace_bytes": [_i64, _P],
+    "pdf_mc_chunk_sum": [_P, _P, _i32, _P, _i64, _P, _P, _P],
+    "pdf_batch_create": [_P, _i32, _i32, _P],
+    "pdf_batch_configure": [_i32, _i32, _i32, _i32],
+    "pdf_batch_run": [_i32, _P],
+    "pdf_batch_autotune": [_i32, _i32, _P, _P, _P],
+    "pdf_batch_destroy": [_i32],
+    "pdf_xfxq2_batched": [_P, _i32, _i32, _P],
     "pdf_shutdown": [],
 }
 for _name, _args in _SIGS.items():
@@ -193,6 +201,83 @@ def error_count(reset=False, stream=None):
     v = ctypes.c_int64(0)
     _check(_lib.pdf_error_count(ctypes.byref(v), 1 if reset else 0, _stream(stream)))
     return v.value
+
+
+def mc_workspace(n, device="cuda"):
+    v = ctypes.c_int64(0)
+    _check(_lib.pdf_mc_workspace_bytes(int(n), ctypes.byref(v)))
+    return torch.empty(max(1, v.value // 8), dtype=torch.float64, device=device)
+
+
+def mc_chunk_sum(xf1, xf2, alphas, workspace=None, out=None, stream=None):
+    """FP64 sum_i alphas[i] * sum_j xf1[i,j] * xf2[i,j] (fixed order); returns a
+    one-element device tensor."""
+    for t, nm in ((xf1, "xf1"), (xf2, "xf2"), (alphas, "alphas")):
+        _dev_f64(t, nm)
+    n, P = xf1.shape
+    if workspace is None:
+        workspace = mc_workspace(n, xf1.device)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=xf1.device)
+    _check(_lib.pdf_mc_chunk_sum(_P(xf1.data_ptr()), _P(xf2.data_ptr()), P, _P(alphas.data_ptr()), n,
+                                 _P(workspace.data_ptr()), _P(out.data_ptr()), _stream(stream)))
+    return out
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("member", ctypes.c_int32), ("n_pids", ctypes.c_int32), ("pids", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("q2", ctypes.c_void_p), ("n", ctypes.c_int64), ("out", ctypes.c_void_p)]
+
+
+class BatchPlan:
+    """A batched plan over requests [(member, pids, x, q2, out), ...] with
+    device tensors x, q2 (float64) and out (float32, or float64 if out_f64)."""
+
+    def __init__(self, requests, out_f64=False):
+        self._keep = []
+        arr = (_Request * max(1, len(requests)))()
+        for i, (member, pids, x, q2, out) in enumerate(requests):
+            _dev_f64(x, "x")
+            _dev_f64(q2, "q2")
+            want = torch.float64 if out_f64 else torch.float32
+            if not (out.is_cuda and out.dtype == want and out.is_contiguous()):
+                raise TypeError("out must be a contiguous %s CUDA tensor" % want)
+            pa, npid = _pid_arg(pids)
+            if pa is not None:
+                self._keep.append(pa)
+            self._keep.append((x, q2, out))
+            arr[i] = _Request(int(member), npid, _ptr(pa) if pa is not None else None, x.data_ptr(),
+                              q2.data_ptr(), x.shape[0], out.data_ptr())
+        self._reqs = arr
+        pid = ctypes.c_int32(-1)
+        _check(_lib.pdf_batch_create(ctypes.cast(arr, _P), len(requests), 1 if out_f64 else 0, ctypes.byref(pid)))
+        self.id = pid.value
+
+    def configure(self, tile_points=4096, vector_cols=1, use_graph=0):
+        _check(_lib.pdf_batch_configure(self.id, int(tile_points), int(vector_cols), int(use_graph)))
+
+    def run(self, stream=None):
+        _check(_lib.pdf_batch_run(self.id, _stream(stream)))
+
+    def autotune(self, reps=3, stream=None):
+        t, v = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(_lib.pdf_batch_autotune(self.id, int(reps), _stream(stream), ctypes.byref(t), ctypes.byref(v)))
+        return t.value, v.value
+
+    def destroy(self):
+        if self.id >= 0:
+            _check(_lib.pdf_batch_destroy(self.id))
+            self.id = -1
+
+
+def xfxq2_batched(requests, out_f64=False, stream=None):
+    """One-shot batched evaluation (synchronises the stream)."""
+    plan = BatchPlan(requests, out_f64)
+    try:
+        plan.run(stream)
+        (torch.cuda.current_stream() if stream is None else stream).synchronize()
+    finally:
+        plan.destroy()
 
 
 def set_lds_policy(policy):

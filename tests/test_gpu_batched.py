@@ -1,0 +1,134 @@
+"""Batched multi-member path (persistent launch, hipGraph replay, autotuned
+tiles) vs per-request calls (bit-identical) and vs the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_06635_amd import synth
+from tolerance import check_f32, check_f64, grid_L
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_2009_06635_amd import pdfmi  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float64)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def members():
+    grids = synth.config3_members(n_members=6)
+    ids = [pdfmi.load_synth(g) for g in grids]
+    yield grids, ids
+    for m in ids:
+        pdfmi.unload(m)
+
+
+def make_requests(grids, ids, out_f64, seed=1, sizes=(1, 63, 65, 1000, 4097, 20000, 0, 777)):
+    rng = np.random.default_rng(seed)
+    reqs, host = [], []
+    for i, n in enumerate(sizes):
+        mi = int(rng.integers(0, len(ids)))
+        if i % 3 == 0:
+            pids = None
+            P = len(grids[mi].pids)
+        else:
+            pids = [int(p) for p in rng.permutation(synth.PIDS_11 + [6, 0])[: int(rng.integers(1, 13))]]
+            P = len(pids)
+        x, q2 = synth.config1_queries(n=n, seed=100 + i)
+        if n > 10:   # a few points outside the grid and invalid
+            x[:3] = [1e-8, 0.5, -1.0]
+            q2[:3] = [10.0, 1e9, 10.0]
+        out = torch.full((n, P), -7.0, dtype=torch.float64 if out_f64 else torch.float32, device=DEV)
+        reqs.append((ids[mi], pids, dev(x), dev(q2), out))
+        host.append((mi, pids, x, q2))
+    return reqs, host
+
+
+@pytest.mark.parametrize("out_f64", [False, True])
+def test_batched_equals_per_request_and_oracle(members, out_f64):
+    grids, ids = members
+    reqs, host = make_requests(grids, ids, out_f64)
+    plan = pdfmi.BatchPlan(reqs, out_f64=out_f64)
+    try:
+        for tile, vec in ((64, 0), (1024, 1), (4096, 1), (8192, 0)):
+            plan.configure(tile_points=tile, vector_cols=vec)
+            for r in reqs:
+                r[4].fill_(-7.0)
+            plan.run()
+            torch.cuda.synchronize()
+            for (m, pids, x, q2, out), (mi, _, xh, qh) in zip(reqs, host):
+                if x.shape[0] == 0:
+                    continue
+                fn = pdfmi.xfxq2 if out_f64 else pdfmi.xfxq2_f32
+                ref = fn(m, pids, x, q2, n_cols=len(grids[mi].pids))
+                assert torch.equal(torch.nan_to_num(out, nan=123.0), torch.nan_to_num(ref, nan=123.0)), (tile, vec)
+        # oracle on every request
+        for (m, pids, x, q2, out), (mi, p2, xh, qh) in zip(reqs, host):
+            if xh.shape[0] == 0:
+                continue
+            g = grids[mi]
+            req = g.pids if p2 is None else p2
+            ora, sc = oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, g.values, g.pids), req, xh, qh, with_scale=True)
+            o = out.cpu().numpy()
+            ok = check_f64(o, ora, sc, grid_L(g))[0] if out_f64 else check_f32(o, ora, sc)[0]
+            assert ok.all()
+    finally:
+        plan.destroy()
+
+
+def test_graph_replay_matches_eager(members):
+    grids, ids = members
+    reqs, host = make_requests(grids, ids, False, seed=2)
+    plan = pdfmi.BatchPlan(reqs)
+    try:
+        plan.configure(tile_points=2048, vector_cols=1, use_graph=0)
+        plan.run()
+        torch.cuda.synchronize()
+        eager = [r[4].clone() for r in reqs]
+        plan.configure(tile_points=2048, vector_cols=1, use_graph=1)
+        for rep in range(4):
+            for r in reqs:
+                r[4].fill_(float(rep))     # eager work between replays
+            torch.cuda.synchronize()
+            plan.run()
+            torch.cuda.synchronize()
+            for r, e in zip(reqs, eager):
+                assert torch.equal(torch.nan_to_num(r[4], nan=9.0), torch.nan_to_num(e, nan=9.0)), rep
+    finally:
+        plan.destroy()
+
+
+def test_autotune_keeps_results(members):
+    grids, ids = members
+    reqs, host = make_requests(grids, ids, False, seed=3)
+    plan = pdfmi.BatchPlan(reqs)
+    try:
+        plan.run()
+        torch.cuda.synchronize()
+        before = [r[4].clone() for r in reqs]
+        tile, vec = plan.autotune(reps=1)
+        assert tile in (1024, 2048, 4096, 8192, 16384) and vec in (0, 1)
+        plan.run()
+        torch.cuda.synchronize()
+        for r, b in zip(reqs, before):
+            assert torch.equal(torch.nan_to_num(r[4], nan=9.0), torch.nan_to_num(b, nan=9.0))
+    finally:
+        plan.destroy()
+
+
+def test_one_shot_and_errors(members):
+    grids, ids = members
+    reqs, _ = make_requests(grids, ids, False, seed=4, sizes=(100, 5))
+    pdfmi.xfxq2_batched(reqs)
+    assert not torch.isnan(reqs[0][4][3:]).any()
+    bad = [(9999, None, reqs[0][2], reqs[0][3], reqs[0][4])]
+    with pytest.raises(pdfmi.PdfError) as e:
+        pdfmi.BatchPlan(bad)
+    assert e.value.code == pdfmi.PDF_ERR_MEMBER
+    pdfmi.xfxq2_batched([])
