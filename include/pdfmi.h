@@ -227,6 +227,48 @@ int pdf_batch_destroy(int32_t plan);
 int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, int32_t out_f64, pdf_stream_t stream);
 
 /*
+ * MLP surrogate of one member's PDFs (an alternative evaluator grown on top
+ * of the interpolator; the interpolator stays the judge of its error).
+ * Network (ln x, ln Q^2) normalised to [-1,1]^2 -> 64 -> 64 -> 64 -> 16,
+ * tanh hidden activations; BF16 weights and activations on the matrix cores
+ * with FP32 accumulation; FP32 master weights trained with Adam.  Output c is
+ * scaled by a positive envelope E_c(x) of the grid (largest |xf_c| over Q^2
+ * at each x knot, linear in ln x), so the network predicts xf_c / E_c.  At
+ * most 16 stored flavours.  Flat FP32 parameter layout: W1[64][2], b1[64],
+ * W2[64][64], b2[64], W3[64][64], b3[64], W4[16][64], b4[16].
+ */
+int pdf_surrogate_param_count(int32_t* n_out);
+/* New surrogate for a member; Glorot-uniform weights from a counter-based
+ * generator seeded by seed, zero biases and Adam moments. */
+int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_out);
+int pdf_surrogate_destroy(int32_t sid);
+/* Training set: n DEVICE points (x, q2); targets are computed by the
+ * library's FP64 interpolator and kept on the device.  Synchronises stream. */
+int pdf_surrogate_set_data(int32_t sid, const double* x, const double* q2, int64_t n, pdf_stream_t stream);
+/* steps Adam steps (beta 0.9 / 0.999, eps 1e-8) on consecutive batches of
+ * `batch` samples (multiple of 16); learning rate on a cosine schedule from
+ * lr to lr_final over total_steps, indexed by the surrogate's global step, so
+ * a run split across calls (or across a save/load) is identical to one call. */
+int pdf_surrogate_train(int32_t sid, int32_t steps, int32_t batch, float lr, float lr_final,
+                        int32_t total_steps, pdf_stream_t stream);
+/* One forward + backward pass on DEVICE inputs in[batch][2] (normalised) and
+ * targets[batch][16]: writes the flat FP32 gradient (param_count floats) and
+ * the mean-squared-error loss (1 float) to DEVICE memory.  No update. */
+int pdf_surrogate_grad(int32_t sid, const float* in, const float* target, int32_t batch,
+                       float* grad_out, float* loss_out, pdf_stream_t stream);
+/* Read (write == 0) or replace (write != 0) the FP32 master parameters
+ * (HOST array of param_count floats).  Synchronises the device. */
+int pdf_surrogate_params(int32_t sid, float* host, int32_t write);
+/* Every stored flavour at n DEVICE points, FP32 point-major [n][P]; points
+ * outside the grid or in the first/last x or Q^2 cell of a sub-grid are
+ * evaluated by the FP32 interpolator instead. */
+int pdf_surrogate_xfxq2(int32_t sid, const double* x, const double* q2, int64_t n, float* out,
+                        pdf_stream_t stream);
+/* Checkpoint: parameters, Adam moments and step count, with a checksum. */
+int pdf_surrogate_save(int32_t sid, const char* path);
+int pdf_surrogate_load(int32_t sid, const char* path);
+
+/*
  * Monte-Carlo luminosity chunk sum (the integrand-shaped use of section 4.1:
  * PDFs of both incoming partons at one scale, weighted by alpha_s):
  *   *sum_out = sum_i alphas[i] * sum_j xf1[i*n_pids + j] * xf2[i*n_pids + j]

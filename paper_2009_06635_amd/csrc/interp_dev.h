@@ -1,0 +1,239 @@
+// Device functions of the interpolation (shared by the interpolation,
+// batched and surrogate kernels): knot search, Hermite stencil weights,
+// point location, in-grid stencil sum and the extrapolation formulas.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pdfmi_dev.h"
+
+namespace pdfmi {
+
+// Largest i in [0, n-2] with t[i] <= v, 0 if t[0] > v (t strictly increasing).
+__device__ __forceinline__ int find_cell(const double* __restrict__ t, int n, double v) {
+  const int last = n - 2;
+  int i = 0;
+  int step = last > 0 ? (1 << (31 - __builtin_clz((unsigned)last))) : 0;
+  for (; step > 0; step >>= 1) {
+    const int j = i + step;
+    if (j <= last && t[j] <= v) i = j;
+  }
+  return i;
+}
+
+// Hermite weights of knots i-1..i+2 re-based onto the stencil that starts at
+// knot i - d (d = 0 left edge, 1 interior, 2 right edge).
+template <typename T>
+__device__ __forceinline__ void stencil_weights(double u64, const CellCoef& c, int d, T out[4]) {
+  const T u = (T)u64;
+  const T u2 = u * u;
+  const T h00 = ((T)2 * u - (T)3) * u2 + (T)1;
+  const T h10 = ((u - (T)2) * u + (T)1) * u;
+  const T h01 = ((T)3 - (T)2 * u) * u2;
+  const T h11 = (u - (T)1) * u2;
+  T r[4];
+  r[0] = h10 * (T)c.am1;
+  r[1] = h00 + h10 * (T)c.a0 + h11 * (T)c.b0;
+  r[2] = h01 + h10 * (T)c.a1 + h11 * (T)c.b1;
+  r[3] = h11 * (T)c.b2;
+  out[0] = d == 0 ? r[1] : (d == 1 ? r[0] : (T)0);
+  out[1] = d == 0 ? r[2] : (d == 1 ? r[1] : r[0]);
+  out[2] = d == 0 ? r[3] : (d == 1 ? r[2] : r[1]);
+  out[3] = d == 1 ? r[3] : (d == 2 ? r[2] : (T)0);
+}
+
+// Cell parameter with exact 0 / 1 at the cell's knots.
+__device__ __forceinline__ double cell_u(double v, const CellCoef& c) {
+  return v == c.t0 ? 0.0 : (v == c.t1 ? 1.0 : log(v * c.inv_t0) * c.invD);
+}
+
+struct PointLoc {
+  int mode;      // region bits | kXHigh | (anchor row << 8) for high Q^2
+  int k, ix, iq;
+  int base;      // element offset of f[sx][sq][0]
+  int sa;        // element stride between x knots
+  double p0, p1; // extrapolation parameters
+};
+
+// Phase 1: everything that depends on the point only.
+template <typename T>
+__device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const double* __restrict__ knots, double x,
+                                                 double q2, T w[4], T v[4]) {
+  PointLoc L;
+  L.p0 = 0.0;
+  L.p1 = 0.0;
+  const bool valid = (x > 0.0) && (x <= m.xmax) && (q2 > 0.0) && (q2 < INFINITY);
+  if (!valid) {
+    L.mode = kInvalid;
+    L.k = L.ix = L.iq = -1;
+    L.base = 0;
+    L.sa = 0;
+    for (int a = 0; a < 4; ++a) w[a] = v[a] = (T)0;
+    return L;
+  }
+  int mode = 0;
+  if (x < m.xmin) mode |= kLowX;
+  if (q2 < m.qmin) mode |= kLowQ;
+  if (q2 > m.qmax) mode |= kHighQ;
+  int k = 0;
+  for (int j = 1; j < m.K; ++j)
+    if (m.sub[j].qfirst <= q2) k = j;
+  const SubDesc& S = m.sub[k];
+  const int ix = find_cell(knots + S.xk_off, S.nx, x);
+  const int iq = find_cell(knots + S.qk_off, S.nq, q2);
+  const CellCoef cx = m.cells[S.xc_off + ix];
+  const CellCoef cq = m.cells[S.qc_off + iq];
+  const int sx = min(max(ix - 1, 0), S.nxp - 4);
+  const int sq = min(max(iq - 1, 0), S.nqp - 4);
+  if (!(mode & kLowX)) {
+    stencil_weights<T>(cell_u(x, cx), cx, ix - sx, w);
+  } else {
+    for (int a = 0; a < 4; ++a) w[a] = (T)0;
+    // continuation in ln x from knots 0 and 1: s = ln(x/x_0) / ln(x_1/x_0)
+    const double sx_par = log(x * cx.inv_t0) * cx.invD;
+    if (mode & (kLowQ | kHighQ)) L.p1 = sx_par; else L.p0 = sx_par;
+  }
+  if (!(mode & (kLowQ | kHighQ))) {
+    stencil_weights<T>(cell_u(q2, cq), cq, iq - sq, v);
+  } else {
+    for (int b = 0; b < 4; ++b) v[b] = (T)0;
+    if (mode & kLowQ) {
+      L.p0 = q2 / cq.t0;                          // r = Q^2 / Q^2_0
+    } else {
+      L.p0 = log(q2 / cq.t1) * cq.invD;            // s = ln(Q^2/q_n-1) / ln(q_n-1/q_n-2)
+      mode |= (S.nq - 2 - sq) << 8;                // stencil row of q_n-2
+    }
+  }
+  if (x > 0.9) mode |= kXHigh;
+  L.mode = mode;
+  L.k = k;
+  L.ix = ix;
+  L.iq = iq;
+  const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
+  L.sa = S.nqp * Pp;
+  L.base = (int)((sizeof(T) == 8 ? S.val_off64 : S.val_off32) + (int64_t)(sx * S.nqp + sq) * Pp);
+  return L;
+}
+
+// Two-anchor continuation (log-linear when both anchors exceed 1e-3).
+__device__ __forceinline__ double cont_low(double f0, double f1, double s) {
+  return (f0 > 1e-3 && f1 > 1e-3) ? f0 * pow(f1 / f0, s) : f0 + s * (f1 - f0);
+}
+__device__ __forceinline__ double cont_high(double f0, double f1, double s) {
+  return (f0 > 1e-3 && f1 > 1e-3) ? f1 * pow(f1 / f0, s) : f1 + s * (f1 - f0);
+}
+// Below Q^2_min: f0 * r^(gamma r + 1 - r), gamma from the first two Q^2 knots.
+__device__ __forceinline__ double low_q(double f0, double f1, double r, double invL01, bool xhigh) {
+  const bool use_gamma = f0 > 1e-5 && f1 > 1e-5 && !xhigh;
+  if (!use_gamma) return f0 * r;
+  const double gamma = log(f1 / f0) * invL01;
+  return f0 * pow(r, gamma * r + 1.0 - r);
+}
+
+// Extrapolated value from anchor values (rare path, FP64 combination):
+//   x below x_min only:      a0, a1 = rows x_0, x_1 interpolated in Q^2
+//   Q^2 outside, x inside:   a0, a1 = anchor Q^2 rows interpolated in x
+//   corners:                 a0, a1 (x_0, x_1 on the lower anchor row),
+//                            a2, a3 (x_0, x_1 on the upper anchor row)
+static __device__ __noinline__ double extrapolate(int mode, double a0, double a1, double a2, double a3, double p0,
+                                           double p1, double invL01) {
+  const bool lowx = mode & kLowX, lowq = mode & kLowQ, highq = mode & kHighQ;
+  const bool xhigh = mode & kXHigh;
+  if (lowx && !(lowq || highq)) return cont_low(a0, a1, p0);
+  if (!lowx) return lowq ? low_q(a0, a1, p0, invL01, xhigh) : cont_high(a0, a1, p0);
+  // corners: continue in x on the two anchor rows first, then in Q^2
+  const double g0 = cont_low(a0, a1, p1);
+  const double g1 = cont_low(a2, a3, p1);
+  return lowq ? low_q(g0, g1, p0, invL01, xhigh) : cont_high(g0, g1, p0);
+}
+
+template <typename T>
+__device__ __forceinline__ const T* member_values(const MemberDev& m);
+template <>
+__device__ __forceinline__ const double* member_values<double>(const MemberDev& m) { return m.v64; }
+template <>
+__device__ __forceinline__ const float* member_values<float>(const MemberDev& m) { return m.v32; }
+
+// In-grid value of one column from its gathered 4x4 stencil: the x-direction
+// weights on each of the four Q^2 rows, then the Q^2-direction weights.
+template <typename T>
+__device__ __forceinline__ T interp_stencil(const T F[4][4], const T w[4], const T v[4]) {
+  T acc;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    T g = w[0] * F[0][b];
+    g = fma(w[1], F[1][b], g);
+    g = fma(w[2], F[2][b], g);
+    g = fma(w[3], F[3][b], g);
+    acc = b == 0 ? v[0] * g : fma(v[b], g, acc);
+  }
+  return acc;
+}
+
+// Extrapolated value of one column (rare path).  f points at the column's
+// entry of the stencil origin; only the anchor knots the formula needs are
+// read:
+//   x below x_min only:     rows x_0, x_1 interpolated in Q^2
+//   Q^2 outside, x inside:  the two anchor Q^2 rows interpolated in x
+//   corners:                the four anchor knot values
+struct Wts {
+  double w0, w1, w2, w3, v0, v1, v2, v3;
+};
+
+template <typename T>
+__device__ __noinline__ double extrap_entry(const T* f, int sa, int Pp, int mode, Wts wt, double p0, double p1,
+                                            double invL01) {
+  const double w[4] = {wt.w0, wt.w1, wt.w2, wt.w3};
+  const double v[4] = {wt.v0, wt.v1, wt.v2, wt.v3};
+  const bool lowx = mode & kLowX, lowq = mode & kLowQ, highq = mode & kHighQ;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (lowx && !(lowq || highq)) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      a0 += v[b] * (double)f[b * Pp];
+      a1 += v[b] * (double)f[sa + b * Pp];
+    }
+  } else {
+    const int ra = lowq ? 0 : (mode >> 8) & 3;
+    if (!lowx) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        a0 += w[a] * (double)f[a * sa + ra * Pp];
+        a1 += w[a] * (double)f[a * sa + (ra + 1) * Pp];
+      }
+    } else {
+      a0 = (double)f[ra * Pp];
+      a1 = (double)f[sa + ra * Pp];
+      a2 = (double)f[(ra + 1) * Pp];
+      a3 = (double)f[sa + (ra + 1) * Pp];
+    }
+  }
+  return extrapolate(mode, a0, a1, a2, a3, p0, p1, invL01);
+}
+
+
+// Value of one stored column at one point (location, weights, stencil and,
+// outside the grid, the extrapolation formula); NaN for an invalid point.
+template <typename T>
+__device__ __forceinline__ T interp_point(const MemberDev& m, const double* knots, double x, double q2, int col,
+                                          double invL01) {
+  T w[4], v[4];
+  const PointLoc L = locate_point<T>(m, knots, x, q2, w, v);
+  if (L.mode & kInvalid) return (T)NAN;
+  const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
+  const T* f = member_values<T>(m) + L.base + col;
+  if (!(L.mode & (kLowX | kLowQ | kHighQ))) {
+    T F[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) F[a][b] = f[a * L.sa + b * Pp];
+    return interp_stencil<T>(F, w, v);
+  }
+  const Wts wt{(double)w[0], (double)w[1], (double)w[2], (double)w[3],
+               (double)v[0], (double)v[1], (double)v[2], (double)v[3]};
+  return (T)extrap_entry<T>(f, L.sa, Pp, L.mode, wt, L.p0, L.p1, invL01);
+}
+
+}  // namespace pdfmi

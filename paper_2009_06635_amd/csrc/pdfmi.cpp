@@ -28,17 +28,21 @@ hipError_t launch_locate(const MemberDev&, const double*, const double*, int64_t
                          int8_t*, int, hipStream_t);
 hipError_t launch_alphas(const AlphasDev&, const double*, int64_t, double*, unsigned long long*, int, hipStream_t);
 int64_t mc_partials(int64_t n);
-struct BatchLaunch {
-  const void* reset_fn;
-  const void* main_fn;
-  unsigned grid;
-  size_t shm;
-};
 size_t batch_shared_bytes(int max_knots, bool f32);
 BatchLaunch batch_launch_params(bool f32, bool lds, int max_knots, int64_t max_elems, int n_cu, int blocks_per_cu,
                                 int ntiles);
 hipError_t batch_prepare(const BatchLaunch& L);
 hipError_t batch_launch(const BatchLaunch& L, void** args, unsigned* counter, hipStream_t s);
+int sur_nparams();
+int sur_out_width();
+int sur_hidden();
+hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s);
+hipError_t sur_adam(const SurBufs& b, float lr, int step, hipStream_t s);
+hipError_t sur_refresh_bf16(const SurBufs& b, hipStream_t s);
+hipError_t sur_prep(const SurDev& S, const double* x, const double* q2, const double* xf, int64_t n, float* in,
+                    float* T, hipStream_t s);
+hipError_t sur_infer(const SurDev& S, const MemberDev& m, const SurBufs& b, const double* x, const double* q2,
+                     int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu, hipStream_t s);
 hipError_t launch_mc_sum(const double*, const double*, int, const double*, int64_t, double*, double*, hipStream_t);
 }  // namespace pdfmi
 
@@ -67,6 +71,8 @@ struct Member {
   MemberDev dev{};
   void* dmem = nullptr;
   std::vector<int> pids;   // stored column -> pid (0 normalised to 21)
+  std::vector<int> h_shape;       // host copy of the load arguments (surrogate envelopes)
+  std::vector<double> h_knots, h_values;
   double invL01 = 0.0;
 };
 
@@ -248,6 +254,16 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
   Member M;
   M.used = true;
   for (int c = 0; c < P; ++c) M.pids.push_back(norm_pid(pids[c]));
+  {
+    int64_t nk = 0, nv = 0;
+    for (int k = 0; k < K; ++k) {
+      nk += shape[2 * k] + shape[2 * k + 1];
+      nv += (int64_t)shape[2 * k] * shape[2 * k + 1] * P;
+    }
+    M.h_shape.assign(shape, shape + 2 * K);
+    M.h_knots.assign(knots, knots + nk);
+    M.h_values.assign(values, values + nv);
+  }
   MemberDev& d = M.dev;
   d.K = K;
   d.P = P;
@@ -881,6 +897,369 @@ extern "C" int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, int32_t
   return rc;
 }
 
+// ---------------------------------------------------------------------------------------
+// MLP surrogates
+
+namespace {
+
+struct Surrogate {
+  bool used = false;
+  int member = -1;
+  SurDev sd{};
+  SurBufs b{};
+  void* pmem = nullptr;      // parameters, moments, gradients, envelope tables
+  void* bmem = nullptr;      // batch activations (sized for bcap)
+  int bcap = 0;
+  float* d_in = nullptr;     // training inputs [n][2]
+  float* d_t = nullptr;      // training targets [n][kO]
+  int64_t n_train = 0;
+  int64_t step = 0;          // Adam steps taken
+  uint64_t seed = 0;
+};
+
+std::vector<Surrogate> g_surs;
+
+Surrogate* get_sur(int32_t id) {
+  if (id < 0 || id >= (int32_t)g_surs.size() || !g_surs[id].used) return nullptr;
+  return &g_surs[id];
+}
+
+void sur_release(Surrogate& S) {
+  if (S.pmem) (void)hipFree(S.pmem);
+  if (S.bmem) (void)hipFree(S.bmem);
+  if (S.d_in) (void)hipFree(S.d_in);
+  S = Surrogate();
+}
+
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Glorot-uniform weights, zero biases, from a counter-based generator.
+std::vector<float> sur_init_params(uint64_t seed) {
+  const int H = sur_hidden(), O = sur_out_width();
+  std::vector<float> p((size_t)sur_nparams(), 0.0f);
+  uint64_t st = seed;
+  auto fill = [&](size_t off, int fan_out, int fan_in) {
+    const double a = std::sqrt(6.0 / (fan_in + fan_out));
+    for (int i = 0; i < fan_out * fan_in; ++i) {
+      const double u = (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0);
+      p[off + i] = (float)((2.0 * u - 1.0) * a);
+    }
+  };
+  size_t off = 0;
+  fill(off, H, 2); off += (size_t)H * 2 + H;
+  fill(off, H, H); off += (size_t)H * H + H;
+  fill(off, H, H); off += (size_t)H * H + H;
+  fill(off, O, H);
+  return p;
+}
+
+int sur_ensure_batch(Surrogate& S, int B) {
+  if (B <= S.bcap) return PDF_OK;
+  if (S.bmem) (void)hipFree(S.bmem);
+  S.bmem = nullptr;
+  const int H = sur_hidden(), O = sur_out_width();
+  // floats: h1,h2,h3,dh,dz (B*H each) + y,dy,sq (B*O each); shorts: h1b,h2b,h3b,dzb (B*H), dyb (B*O)
+  const size_t nf = (size_t)B * (5 * H + 3 * O), ns = (size_t)B * (4 * H + O);
+  hipError_t e = hipMalloc(&S.bmem, nf * 4 + ns * 2 + 256);
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc(surrogate batch)");
+  float* f = static_cast<float*>(S.bmem);
+  S.b.h1 = f; f += (size_t)B * H;
+  S.b.h2 = f; f += (size_t)B * H;
+  S.b.h3 = f; f += (size_t)B * H;
+  S.b.dh = f; f += (size_t)B * H;
+  S.b.dz = f; f += (size_t)B * H;
+  S.b.y = f; f += (size_t)B * O;
+  S.b.dy = f; f += (size_t)B * O;
+  S.b.sq = f; f += (size_t)B * O;
+  unsigned short* h = reinterpret_cast<unsigned short*>(f);
+  S.b.h1b = h; h += (size_t)B * H;
+  S.b.h2b = h; h += (size_t)B * H;
+  S.b.h3b = h; h += (size_t)B * H;
+  S.b.dzb = h; h += (size_t)B * H;
+  S.b.dyb = h;
+  S.bcap = B;
+  return PDF_OK;
+}
+
+constexpr char kSurMagic[8] = {'P', 'D', 'F', 'M', 'I', 'S', 'R', '1'};
+
+uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+}  // namespace
+
+extern "C" int pdf_surrogate_param_count(int32_t* n_out) {
+  if (!n_out) return fail(PDF_ERR_ARG, "null n_out");
+  *n_out = sur_nparams();
+  return PDF_OK;
+}
+
+extern "C" int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_out) {
+  if (!sid_out) return fail(PDF_ERR_ARG, "null sid_out");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int rc = ensure_init();
+  if (rc != PDF_OK) return rc;
+  Member* M = get_member(member);
+  if (!M) return fail(PDF_ERR_MEMBER, "unknown member %d", member);
+  const int O = sur_out_width(), NP = sur_nparams();
+  const int P = (int)M->pids.size();
+  if (P > O) return fail(PDF_ERR_ARG, "surrogate supports at most %d stored flavours", O);
+  const int K = (int)M->h_shape.size() / 2;
+  const int nx0 = M->h_shape[0];
+  const double* xk0 = M->h_knots.data();
+  // envelope over sub-grid 0's x knots: largest |xf| over every Q^2 knot of every sub-grid
+  std::vector<float> env((size_t)nx0 * O, 0.0f), lxk(nx0);
+  for (int i = 0; i < nx0; ++i) lxk[i] = (float)std::log(xk0[i]);
+  int64_t ko = 0, vo = 0;
+  for (int k = 0; k < K; ++k) {
+    const int nx = M->h_shape[2 * k], nq = M->h_shape[2 * k + 1];
+    const double* xk = M->h_knots.data() + ko;
+    for (int ix = 0; ix < nx; ++ix) {
+      int i0 = 0;  // nearest sub-grid-0 knot
+      for (int j = 0; j < nx0; ++j)
+        if (std::fabs(std::log(xk0[j] / xk[ix])) < std::fabs(std::log(xk0[i0] / xk[ix]))) i0 = j;
+      for (int iq = 0; iq < nq; ++iq)
+        for (int c = 0; c < P; ++c) {
+          const float a = (float)std::fabs(M->h_values[vo + ((int64_t)ix * nq + iq) * P + c]);
+          if (a > env[(size_t)i0 * O + c]) env[(size_t)i0 * O + c] = a;
+        }
+    }
+    ko += nx + nq;
+    vo += (int64_t)nx * nq * P;
+  }
+  Surrogate S;
+  S.used = true;
+  S.member = member;
+  S.seed = seed;
+  S.sd.P = P;
+  S.sd.nx = nx0;
+  S.sd.lx0 = std::log(M->dev.xmin);
+  S.sd.ilx = 1.0 / (std::log(M->dev.xmax) - std::log(M->dev.xmin));
+  S.sd.lq0 = std::log(M->dev.qmin);
+  S.sd.ilq = 1.0 / (std::log(M->dev.qmax) - std::log(M->dev.qmin));
+  const size_t bp = align_up((size_t)NP * 4, 256), bpb = align_up((size_t)NP * 2, 256);
+  const size_t be = align_up(env.size() * 4, 256), bl = align_up(lxk.size() * 4, 256);
+  hipError_t e = hipMalloc(&S.pmem, 4 * bp + bpb + be + bl + 2048);
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc(surrogate)");
+  unsigned char* b = static_cast<unsigned char*>(S.pmem);
+  S.b.P = reinterpret_cast<float*>(b);
+  S.b.M = reinterpret_cast<float*>(b + bp);
+  S.b.V = reinterpret_cast<float*>(b + 2 * bp);
+  S.b.G = reinterpret_cast<float*>(b + 3 * bp);
+  S.b.Pb = reinterpret_cast<unsigned short*>(b + 4 * bp);
+  float* envd = reinterpret_cast<float*>(b + 4 * bp + bpb);
+  float* lxkd = reinterpret_cast<float*>(b + 4 * bp + bpb + be);
+  S.b.loss = reinterpret_cast<float*>(b + 4 * bp + bpb + be + bl);
+  S.b.partial = S.b.loss + 64;
+  S.sd.env = envd;
+  S.sd.lxk = lxkd;
+  const std::vector<float> p0 = sur_init_params(seed);
+  std::vector<float> zeros((size_t)NP, 0.0f);
+  if ((e = hipMemcpy(S.b.P, p0.data(), (size_t)NP * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(S.b.M, zeros.data(), (size_t)NP * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(S.b.V, zeros.data(), (size_t)NP * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(envd, env.data(), env.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(lxkd, lxk.data(), lxk.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = sur_refresh_bf16(S.b, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+    sur_release(S);
+    return fail_hip(e, "surrogate upload");
+  }
+  for (size_t i = 0; i < g_surs.size(); ++i)
+    if (!g_surs[i].used) {
+      g_surs[i] = S;
+      *sid_out = (int32_t)i;
+      return PDF_OK;
+    }
+  g_surs.push_back(S);
+  *sid_out = (int32_t)(g_surs.size() - 1);
+  return PDF_OK;
+}
+
+extern "C" int pdf_surrogate_destroy(int32_t sid) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  Surrogate* S = get_sur(sid);
+  if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
+  sur_release(*S);
+  return PDF_OK;
+}
+
+extern "C" int pdf_surrogate_set_data(int32_t sid, const double* x, const double* q2, int64_t n,
+                                      pdf_stream_t stream) {
+  if (n < 16 || !x || !q2) return fail(PDF_ERR_ARG, "need >= 16 device training points");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Surrogate* S = get_sur(sid);
+  if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
+  Member* M = get_member(S->member);
+  if (!M) return fail(PDF_ERR_MEMBER, "surrogate's member %d was unloaded", S->member);
+  hipStream_t s = (hipStream_t)stream;
+  const int O = sur_out_width(), P = (int)M->pids.size();
+  if (S->d_in) (void)hipFree(S->d_in);
+  S->d_in = nullptr;
+  hipError_t e = hipMalloc(&S->d_in, (size_t)n * (2 + O) * 4);
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc(training data)");
+  S->d_t = S->d_in + 2 * n;
+  double* xf = nullptr;
+  if ((e = hipMalloc(&xf, (size_t)n * P * 8)) != hipSuccess) return fail_hip(e, "hipMalloc(targets)");
+  ReqCols rc{};
+  build_req(*M, nullptr, 0, rc);
+  // targets from this library's FP64 interpolator
+  const LaunchCfg cfg{g_ncu, g_blocks_per_cu, g_vector_cols};
+  e = launch_xfxq2_f64(M->dev, rc, x, q2, n, xf, g_nerr, lds_grid_elems(*M, false, n), M->invL01, cfg, s);
+  if (e == hipSuccess) e = sur_prep(S->sd, x, q2, xf, n, S->d_in, S->d_t, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(xf);
+  if (e != hipSuccess) return fail_hip(e, "surrogate targets");
+  S->n_train = n;
+  return PDF_OK;
+}
+
+extern "C" int pdf_surrogate_train(int32_t sid, int32_t steps, int32_t batch, float lr, float lr_final,
+                                   int32_t total_steps, pdf_stream_t stream) {
+  if (steps < 0 || batch < 16 || (batch & 15) || total_steps < 1) return fail(PDF_ERR_ARG, "bad training arguments");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Surrogate* S = get_sur(sid);
+  if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
+  if (S->n_train < batch) return fail(PDF_ERR_STATE, "training data smaller than one batch (call set_data)");
+  int rc = sur_ensure_batch(*S, batch);
+  if (rc != PDF_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int O = sur_out_width();
+  const int64_t nb = S->n_train / batch;
+  for (int i = 0; i < steps; ++i) {
+    const int64_t t = S->step;  // global step: batch slice and learning rate depend only on it
+    const int64_t off = (t % nb) * batch;
+    const double frac = std::min(1.0, (double)t / (double)total_steps);
+    const float lr_t = (float)(lr_final + 0.5 * (lr - lr_final) * (1.0 + std::cos(3.141592653589793 * frac)));
+    hipError_t e = sur_forward_backward(S->b, S->d_in + 2 * off, S->d_t + O * off, batch, s);
+    if (e == hipSuccess) e = sur_adam(S->b, lr_t, (int)(t + 1), s);
+    if (e != hipSuccess) return fail_hip(e, "surrogate training step");
+    ++S->step;
+  }
+  return PDF_OK;
+}
+
+extern "C" int pdf_surrogate_grad(int32_t sid, const float* in, const float* target, int32_t batch, float* grad_out,
+                                  float* loss_out, pdf_stream_t stream) {
+  if (!in || !target || !grad_out || !loss_out || batch < 16 || (batch & 15))
+    return fail(PDF_ERR_ARG, "bad gradient arguments");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Surrogate* S = get_sur(sid);
+  if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
+  int rc = sur_ensure_batch(*S, batch);
+  if (rc != PDF_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = sur_forward_backward(S->b, in, target, batch, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(grad_out, S->b.G, (size_t)sur_nparams() * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(loss_out, S->b.loss, 4, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return fail_hip(e, "surrogate gradient");
+  return PDF_OK;
+}
+
+extern "C" int pdf_surrogate_params(int32_t sid, float* host, int32_t write) {
+  if (!host) return fail(PDF_ERR_ARG, "null host buffer");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Surrogate* S = get_sur(sid);
+  if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
+  const size_t nb = (size_t)sur_nparams() * 4;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) {
+    if (write) {
+      e = hipMemcpy(S->b.P, host, nb, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = sur_refresh_bf16(S->b, nullptr);
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+    } else {
+      e = hipMemcpy(host, S->b.P, nb, hipMemcpyDeviceToHost);
+    }
+  }
+  if (e != hipSuccess) return fail_hip(e, "surrogate parameters");
+  return PDF_OK;
+}
+
+extern "C" int pdf_surrogate_xfxq2(int32_t sid, const double* x, const double* q2, int64_t n, float* out,
+                                   pdf_stream_t stream) {
+  int rc = check_stream_args(x, q2, n);
+  if (rc != PDF_OK) return rc;
+  if (n > 0 && !out) return fail(PDF_ERR_ARG, "null out");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Surrogate* S = get_sur(sid);
+  if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
+  Member* M = get_member(S->member);
+  if (!M) return fail(PDF_ERR_MEMBER, "surrogate's member %d was unloaded", S->member);
+  if (n == 0) return PDF_OK;
+  hipError_t e = sur_infer(S->sd, M->dev, S->b, x, q2, n, out, M->invL01, g_nerr, g_ncu, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "launch surrogate inference");
+  return PDF_OK;
+}
+
+extern "C" int pdf_surrogate_save(int32_t sid, const char* path) {
+  if (!path) return fail(PDF_ERR_ARG, "null path");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Surrogate* S = get_sur(sid);
+  if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
+  const int NP = sur_nparams();
+  std::vector<float> buf((size_t)3 * NP);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(buf.data(), S->b.P, (size_t)NP * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(buf.data() + NP, S->b.M, (size_t)NP * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(buf.data() + 2 * NP, S->b.V, (size_t)NP * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, "surrogate save");
+  const uint32_t version = 1, np = (uint32_t)NP;
+  const int64_t step = S->step;
+  uint64_t h = fnv1a(reinterpret_cast<const unsigned char*>(&step), 8);
+  h = fnv1a(reinterpret_cast<const unsigned char*>(buf.data()), buf.size() * 4, h);
+  FILE* f = fopen(path, "wb");
+  if (!f) return fail(PDF_ERR_ARG, "cannot open %s for writing", path);
+  bool ok = fwrite(kSurMagic, 1, 8, f) == 8 && fwrite(&version, 4, 1, f) == 1 && fwrite(&np, 4, 1, f) == 1 &&
+            fwrite(&step, 8, 1, f) == 1 && fwrite(buf.data(), 4, buf.size(), f) == buf.size() &&
+            fwrite(&h, 8, 1, f) == 1;
+  ok = (fclose(f) == 0) && ok;
+  if (!ok) return fail(PDF_ERR_ARG, "write to %s failed", path);
+  return PDF_OK;
+}
+
+extern "C" int pdf_surrogate_load(int32_t sid, const char* path) {
+  if (!path) return fail(PDF_ERR_ARG, "null path");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Surrogate* S = get_sur(sid);
+  if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
+  const int NP = sur_nparams();
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(PDF_ERR_ARG, "cannot open %s", path);
+  char mg[8];
+  uint32_t version = 0, np = 0;
+  int64_t step = 0;
+  uint64_t h = 0;
+  std::vector<float> buf((size_t)3 * NP);
+  bool ok = fread(mg, 1, 8, f) == 8 && fread(&version, 4, 1, f) == 1 && fread(&np, 4, 1, f) == 1;
+  ok = ok && std::memcmp(mg, kSurMagic, 8) == 0 && version == 1 && np == (uint32_t)NP;
+  ok = ok && fread(&step, 8, 1, f) == 1 && fread(buf.data(), 4, buf.size(), f) == buf.size() &&
+       fread(&h, 8, 1, f) == 1;
+  fclose(f);
+  if (!ok) return fail(PDF_ERR_ARG, "%s is not a surrogate checkpoint of this layout", path);
+  uint64_t h2 = fnv1a(reinterpret_cast<const unsigned char*>(&step), 8);
+  h2 = fnv1a(reinterpret_cast<const unsigned char*>(buf.data()), buf.size() * 4, h2);
+  if (h2 != h) return fail(PDF_ERR_ARG, "%s: checksum mismatch", path);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(S->b.P, buf.data(), (size_t)NP * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(S->b.M, buf.data() + NP, (size_t)NP * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(S->b.V, buf.data() + 2 * NP, (size_t)NP * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = sur_refresh_bf16(S->b, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail_hip(e, "surrogate load");
+  S->step = step;
+  return PDF_OK;
+}
+
 extern "C" int pdf_mc_workspace_bytes(int64_t n, int64_t* bytes_out) {
   if (!bytes_out || n < 0) return fail(PDF_ERR_ARG, "bad argument");
   *bytes_out = (n == 0 ? 1 : mc_partials(n)) * (int64_t)sizeof(double);
@@ -920,6 +1299,9 @@ extern "C" int pdf_shutdown(void) {
   for (auto& P : g_plans)
     if (P.used) plan_release(P);
   g_plans.clear();
+  for (auto& S : g_surs)
+    if (S.used) sur_release(S);
+  g_surs.clear();
   if (g_nerr) (void)hipFree(g_nerr);
   g_nerr = nullptr;
   g_init = false;

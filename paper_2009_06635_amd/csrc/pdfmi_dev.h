@@ -103,4 +103,33 @@ struct BatchTile {
   int64_t start;
 };
 
+// Kernel node parameters of one batched run (counter reset + persistent kernel).
+struct BatchLaunch {
+  const void* reset_fn;
+  const void* main_fn;
+  unsigned grid;
+  size_t shm;
+};
+
+// Surrogate input normalisation and output envelope (device tables).
+struct SurDev {
+  int P;              // stored columns (<= 16)
+  int nx;             // envelope knots (sub-grid 0 x knots)
+  double lx0, ilx;    // u = 2 (ln x - lx0) * ilx - 1
+  double lq0, ilq;    // v = 2 (ln Q^2 - lq0) * ilq - 1
+  const float* lxk;   // [nx] ln of the envelope knots
+  const float* env;   // [nx][16] envelope values
+};
+
+// Surrogate device buffers (parameters, Adam moments, gradients, batch activations).
+struct SurBufs {
+  float* P;                 // FP32 master parameters
+  unsigned short* Pb;       // BF16 copies
+  float *M, *V, *G;         // Adam moments, gradients
+  float *h1, *h2, *h3, *y, *dy, *dh, *dz, *sq;
+  unsigned short *h1b, *h2b, *h3b, *dyb, *dzb;
+  float* loss;              // [1]
+  float* partial;           // [256]
+};
+
 }  // namespace pdfmi

@@ -1,0 +1,454 @@
+// MLP surrogate of one member's PDFs (growth path of the interpolation
+// library): (ln x, ln Q^2) -> all stored flavours, 2 -> 64 -> 64 -> 64 -> 16
+// (outputs beyond the stored columns are padding), tanh hidden activations,
+// BF16 weights and activations with FP32 accumulation on the matrix cores
+// (v_mfma_f32_16x16x32_bf16), FP32 master weights, Adam.
+//
+// The network predicts y_c = xf_c / E_c(x), where E_c is a positive envelope
+// of the grid (largest |xf_c| over Q^2 at each x knot, linear in ln x between
+// knots), so every target is O(1).  Inference falls back to the FP32
+// interpolator outside the grid and in the first/last x or Q^2 cell of a
+// sub-grid (which includes the cells next to flavour thresholds).
+//
+// Training is deterministic: every reduction has a fixed order (one wave per
+// 16x16 output tile loops over the whole batch; bias sums are sequential per
+// column), so a checkpointed and resumed run reproduces a straight run bit for
+// bit.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "interp_dev.h"
+#include "pdfmi_dev.h"
+
+namespace pdfmi {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kH = 64;   // hidden width
+constexpr int kO = 16;   // output width (stored columns padded)
+// flat FP32 parameter layout
+constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kH * 2, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH,
+              kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kH * kH, kOffW4 = kOffB3 + kH, kOffB4 = kOffW4 + kO * kH,
+              kNParams = kOffB4 + kO;
+
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  const __bf16 h = (__bf16)f;  // round to nearest even
+  return __builtin_bit_cast(unsigned short, h);
+}
+__device__ __forceinline__ float bf16_float(unsigned short b) {
+  return __uint_as_float(((unsigned)b) << 16);
+}
+
+// tanh from one exp and one division; relative error far below BF16 rounding.
+__device__ __forceinline__ float tanh_f(float z) {
+  const float t = __expf(-2.0f * fabsf(z));
+  const float r = (1.0f - t) / (1.0f + t);
+  return copysignf(r, z);
+}
+
+// ---------------------------------------------------------------------------------------
+// Generic BF16 GEMM tile: C[m][n] = sum_k A(m,k) B(k,n) (+ bias[n]) (then tanh)
+// A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (BF16 bit patterns);
+// M, N multiples of 16; K any (zero padded to 32).  One wave per 16x16 tile,
+// K walked in order (fixed summation order).  Writes FP32 C (ldc) and, if
+// Cb != null, its BF16 copy.
+__global__ __launch_bounds__(64) void k_gemm_bf16(const unsigned short* __restrict__ A, int sam, int sak,
+                                                  const unsigned short* __restrict__ B, int sbk, int sbn,
+                                                  float* __restrict__ C, int ldc, unsigned short* __restrict__ Cb,
+                                                  int M, int N, int K, const float* __restrict__ bias, int act) {
+  const int tn = N / 16;
+  const int m0 = (blockIdx.x / tn) * 16, n0 = (blockIdx.x % tn) * 16;
+  const int l = threadIdx.x, r = l & 15, g = l >> 4;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = k0 + 8 * g + i;
+      const unsigned short av = k < K ? A[(int64_t)(m0 + r) * sam + (int64_t)k * sak] : (unsigned short)0;
+      const unsigned short bv = k < K ? B[(int64_t)k * sbk + (int64_t)(n0 + r) * sbn] : (unsigned short)0;
+      a[i] = __builtin_bit_cast(__bf16, av);
+      b[i] = __builtin_bit_cast(__bf16, bv);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + 4 * g + i, n = n0 + r;
+    float v = acc[i];
+    if (bias) v += bias[n];
+    if (act) v = tanh_f(v);
+    C[(int64_t)m * ldc + n] = v;
+    if (Cb) Cb[(int64_t)m * ldc + n] = bf16_bits(v);
+  }
+}
+
+// Layer 1 (K = 2, on the vector ALUs): h1 = tanh(W1 in + b1), FP32 and BF16.
+__global__ void k_layer1(const float* __restrict__ in, const float* __restrict__ P, int B, float* __restrict__ h,
+                         unsigned short* __restrict__ hb) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * kH) return;
+  const int b = (int)(i / kH), j = (int)(i % kH);
+  // the inputs and W1 are BF16-rounded like every other matrix operand
+  const float u = bf16_float(bf16_bits(in[2 * b])), v = bf16_float(bf16_bits(in[2 * b + 1]));
+  const float w0 = bf16_float(bf16_bits(P[kOffW1 + 2 * j])), w1 = bf16_float(bf16_bits(P[kOffW1 + 2 * j + 1]));
+  const float z = fmaf(w0, u, fmaf(w1, v, P[kOffB1 + j]));
+  const float t = tanh_f(z);
+  h[i] = t;
+  hb[i] = bf16_bits(t);
+}
+
+// Loss (mean squared error over B x kO) and its gradient dY = 2 (Y - T) / (B kO).
+__global__ void k_loss_grad(const float* __restrict__ Y, const float* __restrict__ T, int B, float* __restrict__ dY,
+                            unsigned short* __restrict__ dYb, float* __restrict__ sq) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * kO) return;
+  const float d = Y[i] - T[i];
+  const float gr = 2.0f * d / (float)((int64_t)B * kO);
+  dY[i] = gr;
+  dYb[i] = bf16_bits(gr);
+  sq[i] = d * d;
+}
+
+// dZ = dH * (1 - H^2) (tanh derivative), FP32 and BF16.
+__global__ void k_tanh_back(const float* __restrict__ dH, const float* __restrict__ H, int64_t n,
+                            float* __restrict__ dZ, unsigned short* __restrict__ dZb) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float h = H[i];
+  const float v = dH[i] * (1.0f - h * h);
+  dZ[i] = v;
+  dZb[i] = bf16_bits(v);
+}
+
+// out[c] = sum_b X[b][c] (sequential in b: fixed order), for c < ncols.
+__global__ void k_col_sum(const float* __restrict__ X, int B, int ncols, float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  float s = 0.0f;
+  for (int b = 0; b < B; ++b) s += X[(int64_t)b * ncols + c];
+  out[c] = s;
+}
+
+// dW1[j][t] = sum_b dZ1[b][j] in[b][t] (BF16-rounded operands, FP32 sum in b order).
+__global__ void k_dw1(const unsigned short* __restrict__ dZb, const float* __restrict__ in, int B,
+                      float* __restrict__ dW1) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= kH * 2) return;
+  const int j = o / 2, t = o % 2;
+  float s = 0.0f;
+  for (int b = 0; b < B; ++b) s = fmaf(bf16_float(dZb[(int64_t)b * kH + j]), bf16_float(bf16_bits(in[2 * b + t])), s);
+  dW1[o] = s;
+}
+
+// Adam step on the FP32 masters, then their BF16 copies.
+__global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ Mm,
+                       float* __restrict__ Vm, unsigned short* __restrict__ Pb, int n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = G[i];
+  const float m = b1 * Mm[i] + (1.0f - b1) * g;
+  const float v = b2 * Vm[i] + (1.0f - b2) * g * g;
+  Mm[i] = m;
+  Vm[i] = v;
+  const float p = P[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+  P[i] = p;
+  Pb[i] = bf16_bits(p);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ P, unsigned short* __restrict__ Pb, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) Pb[i] = bf16_bits(P[i]);
+}
+
+// ---------------------------------------------------------------------------------------
+// Sample preparation: normalised inputs and envelope-scaled targets.
+
+
+__device__ __forceinline__ void envelope(const SurDev& S, float lx, float e[kO]) {
+  int lo = 0, hi = S.nx - 2;
+  while (lo < hi) {  // largest i <= nx-2 with lxk[i] <= lx
+    const int mid = (lo + hi + 1) >> 1;
+    if (S.lxk[mid] <= lx) lo = mid; else hi = mid - 1;
+  }
+  const float t = fminf(fmaxf((lx - S.lxk[lo]) / (S.lxk[lo + 1] - S.lxk[lo]), 0.0f), 1.0f);
+#pragma unroll
+  for (int c = 0; c < kO; ++c) e[c] = S.env[lo * kO + c] + t * (S.env[(lo + 1) * kO + c] - S.env[lo * kO + c]);
+}
+
+// Envelope of one column c at ln x.
+__device__ __forceinline__ float envelope_col(const SurDev& S, float lx, int c) {
+  int lo = 0, hi = S.nx - 2;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (S.lxk[mid] <= lx) lo = mid; else hi = mid - 1;
+  }
+  const float t = fminf(fmaxf((lx - S.lxk[lo]) / (S.lxk[lo + 1] - S.lxk[lo]), 0.0f), 1.0f);
+  const float e0 = S.env[lo * kO + c], e1 = S.env[(lo + 1) * kO + c];
+  return e0 + t * (e1 - e0);
+}
+
+__global__ void k_prep_samples(SurDev S, const double* __restrict__ X, const double* __restrict__ Q2,
+                               const double* __restrict__ XF, int64_t n, float* __restrict__ in,
+                               float* __restrict__ T) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double lx = log(X[i]), lq = log(Q2[i]);
+  in[2 * i] = (float)(2.0 * (lx - S.lx0) * S.ilx - 1.0);
+  in[2 * i + 1] = (float)(2.0 * (lq - S.lq0) * S.ilq - 1.0);
+  float e[kO];
+  envelope(S, (float)lx, e);
+  for (int c = 0; c < kO; ++c) {
+    float t = 0.0f;
+    if (c < S.P && e[c] > 0.0f) {
+      const double xf = XF[i * S.P + c];
+      t = isfinite(xf) ? (float)(xf / (double)e[c]) : 0.0f;
+    }
+    T[i * kO + c] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Fused inference.  One wave = 16 points; layer 1 on the VALUs directly into
+// the A-operand layout of layer 2; layers 2-4 on the matrix cores with the
+// weight fragments held in registers; hidden activations re-laid out from the
+// accumulator layout to the A-operand layout through 2 KB of LDS per wave.
+// Points in the fallback domain are evaluated by the FP32 interpolator inside
+// the same wave (one lane per flavour).
+constexpr int kSurWaves = 4;
+
+__device__ __forceinline__ bool trusted(const MemberDev& m, double x, double q2) {
+  if (!(x >= m.xmin && x <= m.xmax && q2 >= m.qmin && q2 <= m.qmax)) return false;
+  int k = 0;
+  for (int j = 1; j < m.K; ++j)
+    if (m.sub[j].qfirst <= q2) k = j;
+  const SubDesc& S = m.sub[k];
+  const double* xk = m.knots + S.xk_off;
+  const double* qk = m.knots + S.qk_off;
+  if (S.nx < 4 || S.nq < 4) return false;
+  return x >= xk[1] && x < xk[S.nx - 2] && q2 >= qk[1] && q2 < qk[S.nq - 2];
+}
+
+__global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDev m, const unsigned short* __restrict__ Pb,
+                                                             const float* __restrict__ Pf,
+                                                             const double* __restrict__ X,
+                                                             const double* __restrict__ Q2, int64_t n,
+                                                             float* __restrict__ out, double invL01,
+                                                             unsigned long long* __restrict__ nerr) {
+  __shared__ unsigned short sh[kSurWaves][16 * kH];
+  __shared__ float spt[kSurWaves][16][2];
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
+  unsigned short* hs = sh[wv];
+  // weight fragments: B operand of layer L, N-tile t, K-step s: lane holds W[n = 16t + r][k = 32s + 8g + i]
+  bf16x8 w2[4][2], w3[4][2], w4[2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int nn = 16 * t + r, kk = 32 * s + 8 * g + i;
+        w2[t][s][i] = __builtin_bit_cast(__bf16, Pb[kOffW2 + nn * kH + kk]);
+        w3[t][s][i] = __builtin_bit_cast(__bf16, Pb[kOffW3 + nn * kH + kk]);
+      }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w4[s][i] = __builtin_bit_cast(__bf16, Pb[kOffW4 + r * kH + 32 * s + 8 * g + i]);
+
+  const int64_t ntiles = (n + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * kSurWaves + wv; tile < ntiles; tile += (int64_t)gridDim.x * kSurWaves) {
+    const int64_t p0 = tile * 16;
+    const int np = (int)min((int64_t)16, n - p0);
+    // inputs of the wave's 16 points (lanes 0..15), shared through LDS
+    double xr = 0.5, qr = 1.0, lxr = 0.0;
+    bool fb = false;
+    if (l < np) {
+      xr = X[p0 + l];
+      qr = Q2[p0 + l];
+      fb = !trusted(m, xr, qr);
+      const double lx = log(xr), lq = log(qr);
+      lxr = lx;
+      spt[wv][l][0] = (float)(2.0 * (lx - S.lx0) * S.ilx - 1.0);
+      spt[wv][l][1] = (float)(2.0 * (lq - S.lq0) * S.ilq - 1.0);
+    } else if (l < 16) {
+      spt[wv][l][0] = 0.0f;
+      spt[wv][l][1] = 0.0f;
+    }
+    const unsigned long long fbmask = __ballot(fb) & 0xFFFFull;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // layer 1 straight into the A layout: lane (r, g) holds h1[r][32 s + 8 g + i]
+    const float u = bf16_float(bf16_bits(spt[wv][r][0])), v = bf16_float(bf16_bits(spt[wv][r][1]));
+    bf16x8 a[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int j = 32 * s + 8 * g + i;
+        const float z = fmaf(bf16_float(bf16_bits(Pf[kOffW1 + 2 * j])), u,
+                             fmaf(bf16_float(bf16_bits(Pf[kOffW1 + 2 * j + 1])), v, Pf[kOffB1 + j]));
+        a[s][i] = __builtin_bit_cast(__bf16, bf16_bits(tanh_f(z)));
+      }
+    // layers 2 and 3
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+      const int boff = layer == 0 ? kOffB2 : kOffB3;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], layer == 0 ? w2[t][0] : w3[t][0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], layer == 0 ? w2[t][1] : w3[t][1], acc, 0, 0, 0);
+        const float bn = Pf[boff + 16 * t + r];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) hs[(4 * g + i) * kH + 16 * t + r] = bf16_bits(tanh_f(acc[i] + bn));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[s][i] = __builtin_bit_cast(__bf16, hs[r * kH + 32 * s + 8 * g + i]);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // layer 4: lane (r, g) gets y[point 4 g + i][output r]
+    f32x4 y = {0.f, 0.f, 0.f, 0.f};
+    y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], w4[0], y, 0, 0, 0);
+    y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], w4[1], y, 0, 0, 0);
+    const float b4 = Pf[kOffB4 + r];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int pt = 4 * g + i;
+      const float lxp = (float)__shfl(lxr, pt);
+      if (pt < np && r < S.P && !((fbmask >> pt) & 1ull))
+        out[(p0 + pt) * S.P + r] = (y[i] + b4) * envelope_col(S, lxp, r);
+    }
+    // fallback points: FP32 interpolator, one lane per stored column
+    unsigned long long fm = fbmask;
+    while (fm) {
+      const int pt = __builtin_ctzll(fm);
+      fm &= fm - 1;
+      const double xp = __shfl(xr, pt), qp = __shfl(qr, pt);
+      if (l < S.P) {
+        const float v2 = interp_point<float>(m, m.knots, xp, qp, l, invL01);
+        out[(p0 + pt) * S.P + l] = v2;
+      }
+      if (l == 0 && !((xp > 0.0) && (xp <= m.xmax) && (qp > 0.0) && (qp < INFINITY))) atomicAdd(nerr, 1ull);
+    }
+  }
+}
+
+}  // namespace pdfmi
+
+namespace pdfmi {
+
+// ---------------------------------------------------------------------------------------
+// Host-side launchers.
+
+
+int sur_nparams() { return kNParams; }
+int sur_out_width() { return kO; }
+int sur_hidden() { return kH; }
+size_t sur_batch_floats(int B) { return (size_t)B * (3 * kH + 3 * kO + 2 * kH) ; }
+
+static unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+static void gemm(const unsigned short* A, int sam, int sak, const unsigned short* B, int sbk, int sbn, float* C, int ldc,
+                 unsigned short* Cb, int M, int N, int K, const float* bias, int act, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((M / 16) * (N / 16))), dim3(64), 0, s, A, sam, sak, B, sbk, sbn, C,
+                     ldc, Cb, M, N, K, bias, act);
+}
+
+__global__ void k_sum_partial(const float* __restrict__ x, int64_t n, float* __restrict__ partial) {
+  // 256 threads, each sums a contiguous chunk in order
+  const int64_t per = (n + 255) / 256;
+  const int64_t b = threadIdx.x * per, e = min(b + per, n);
+  float s = 0.0f;
+  for (int64_t i = b; i < e; ++i) s += x[i];
+  partial[threadIdx.x] = s;
+}
+__global__ void k_sum_final(const float* __restrict__ partial, float scale, float* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    float s = 0.0f;
+    for (int i = 0; i < 256; ++i) s += partial[i];
+    *out = s * scale;
+  }
+}
+
+// One forward + backward pass on a batch (inputs in[B][2], targets T[B][kO]):
+// gradients into buf.G, loss (mean squared error) into buf.loss.
+hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s) {
+  const unsigned short* W2 = b.Pb + kOffW2;
+  const unsigned short* W3 = b.Pb + kOffW3;
+  const unsigned short* W4 = b.Pb + kOffW4;
+  hipLaunchKernelGGL(k_layer1, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, in, b.P, B, b.h1, b.h1b);
+  // z = h W^T + b: A(m=b,k) = h[b][k]; B(k,n) = W[n][k]
+  gemm(b.h1b, kH, 1, W2, 1, kH, b.h2, kH, b.h2b, B, kH, kH, b.P + kOffB2, 1, s);
+  gemm(b.h2b, kH, 1, W3, 1, kH, b.h3, kH, b.h3b, B, kH, kH, b.P + kOffB3, 1, s);
+  gemm(b.h3b, kH, 1, W4, 1, kH, b.y, kO, nullptr, B, kO, kH, b.P + kOffB4, 0, s);
+  hipLaunchKernelGGL(k_loss_grad, dim3(nb((int64_t)B * kO, 256)), dim3(256), 0, s, b.y, T, B, b.dy, b.dyb, b.sq);
+  hipLaunchKernelGGL(k_sum_partial, dim3(1), dim3(256), 0, s, b.sq, (int64_t)B * kO, b.partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, s, b.partial, 1.0f / (float)((int64_t)B * kO), b.loss);
+  // layer 4: dW4[o][i] = sum_b dy[b][o] h3[b][i]; db4; dh3 = dy W4
+  gemm(b.dyb, 1, kO, b.h3b, kH, 1, b.G + kOffW4, kH, nullptr, kO, kH, B, nullptr, 0, s);
+  hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(64), 0, s, b.dy, B, kO, b.G + kOffB4);
+  gemm(b.dyb, kO, 1, W4, kH, 1, b.dh, kH, nullptr, B, kH, kO, nullptr, 0, s);
+  // layers 3 and 2
+  const float* Hs[3] = {b.h1, b.h2, b.h3};
+  const unsigned short* Hbs[3] = {b.h1b, b.h2b, b.h3b};
+  const unsigned short* Ws[2] = {W2, W3};
+  const int offW[2] = {kOffW2, kOffW3}, offB[2] = {kOffB2, kOffB3};
+  for (int L = 1; L >= 0; --L) {  // L = 1: layer 3 (input h2, output h3); L = 0: layer 2 (h1 -> h2)
+    hipLaunchKernelGGL(k_tanh_back, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, b.dh, Hs[L + 1],
+                       (int64_t)B * kH, b.dz, b.dzb);
+    gemm(b.dzb, 1, kH, Hbs[L], kH, 1, b.G + offW[L], kH, nullptr, kH, kH, B, nullptr, 0, s);
+    hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(64), 0, s, b.dz, B, kH, b.G + offB[L]);
+    // dh_in = dz W: A(m=b, k=j) = dz[b][j]; B(k=j, n=i) = W[j][i]
+    gemm(b.dzb, kH, 1, Ws[L], kH, 1, b.dh, kH, nullptr, B, kH, kH, nullptr, 0, s);
+  }
+  // layer 1
+  hipLaunchKernelGGL(k_tanh_back, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, b.dh, b.h1, (int64_t)B * kH, b.dz,
+                     b.dzb);
+  hipLaunchKernelGGL(k_dw1, dim3(1), dim3(128), 0, s, b.dzb, in, B, b.G + kOffW1);
+  hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(64), 0, s, b.dz, B, kH, b.G + kOffB1);
+  return hipGetLastError();
+}
+
+hipError_t sur_adam(const SurBufs& b, float lr, int step, hipStream_t s) {
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = (float)(1.0 - pow(b1, step)), c2 = (float)(1.0 - pow(b2, step));
+  hipLaunchKernelGGL(k_adam, dim3(nb(kNParams, 256)), dim3(256), 0, s, b.P, b.G, b.M, b.V, b.Pb, kNParams, lr,
+                     (float)b1, (float)b2, 1e-8f, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t sur_refresh_bf16(const SurBufs& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(nb(kNParams, 256)), dim3(256), 0, s, b.P, b.Pb, kNParams);
+  return hipGetLastError();
+}
+
+hipError_t sur_prep(const SurDev& S, const double* x, const double* q2, const double* xf, int64_t n, float* in,
+                    float* T, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_prep_samples, dim3(nb(n, 256)), dim3(256), 0, s, S, x, q2, xf, n, in, T);
+  return hipGetLastError();
+}
+
+hipError_t sur_infer(const SurDev& S, const MemberDev& m, const SurBufs& b, const double* x, const double* q2,
+                     int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu, hipStream_t s) {
+  const int64_t tiles = (n + 15) / 16;
+  const int64_t blocks = min((tiles + kSurWaves - 1) / kSurWaves, (int64_t)n_cu * 8);
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_sur_infer, dim3((unsigned)blocks), dim3(64 * kSurWaves), 0, s, S, m, b.Pb, b.P, x, q2, n,
+                       out, invL01, nerr);
+  return hipGetLastError();
+}
+
+}  // namespace pdfmi

@@ -43,6 +43,16 @@ _SIGS = {
     "pdf_batch_autotune": [_i32, _i32, _P, _P, _P],
     "pdf_batch_destroy": [_i32],
     "pdf_xfxq2_batched": [_P, _i32, _i32, _P],
+    "pdf_surrogate_param_count": [_P],
+    "pdf_surrogate_create": [_i32, ctypes.c_uint64, _P],
+    "pdf_surrogate_destroy": [_i32],
+    "pdf_surrogate_set_data": [_i32, _P, _P, _i64, _P],
+    "pdf_surrogate_train": [_i32, _i32, _i32, ctypes.c_float, ctypes.c_float, _i32, _P],
+    "pdf_surrogate_grad": [_i32, _P, _P, _i32, _P, _P, _P],
+    "pdf_surrogate_params": [_i32, _P, _i32],
+    "pdf_surrogate_xfxq2": [_i32, _P, _P, _i64, _P, _P],
+    "pdf_surrogate_save": [_i32, ctypes.c_char_p],
+    "pdf_surrogate_load": [_i32, ctypes.c_char_p],
     "pdf_shutdown": [],
 }
 for _name, _args in _SIGS.items():
@@ -278,6 +288,68 @@ def xfxq2_batched(requests, out_f64=False, stream=None):
         (torch.cuda.current_stream() if stream is None else stream).synchronize()
     finally:
         plan.destroy()
+
+
+def surrogate_param_count():
+    v = ctypes.c_int32(0)
+    _check(_lib.pdf_surrogate_param_count(ctypes.byref(v)))
+    return v.value
+
+
+class Surrogate:
+    """MLP surrogate of one member (see pdf_surrogate_* in include/pdfmi.h)."""
+
+    def __init__(self, member, seed=0):
+        sid = ctypes.c_int32(-1)
+        _check(_lib.pdf_surrogate_create(int(member), ctypes.c_uint64(seed), ctypes.byref(sid)))
+        self.id = sid.value
+        self.n_params = surrogate_param_count()
+
+    def set_data(self, x, q2, stream=None):
+        _dev_f64(x, "x")
+        _dev_f64(q2, "q2")
+        _check(_lib.pdf_surrogate_set_data(self.id, _P(x.data_ptr()), _P(q2.data_ptr()), x.shape[0], _stream(stream)))
+
+    def train(self, steps, batch, lr, lr_final, total_steps, stream=None):
+        _check(_lib.pdf_surrogate_train(self.id, int(steps), int(batch), float(lr), float(lr_final), int(total_steps),
+                                        _stream(stream)))
+
+    def grad(self, inp, target, stream=None):
+        """(gradient tensor, loss tensor) for device float32 inp[B][2], target[B][16]."""
+        g = torch.empty(self.n_params, dtype=torch.float32, device=inp.device)
+        loss = torch.empty(1, dtype=torch.float32, device=inp.device)
+        _check(_lib.pdf_surrogate_grad(self.id, _P(inp.data_ptr()), _P(target.data_ptr()), inp.shape[0],
+                                       _P(g.data_ptr()), _P(loss.data_ptr()), _stream(stream)))
+        return g, loss
+
+    def params(self):
+        a = np.empty(self.n_params, np.float32)
+        _check(_lib.pdf_surrogate_params(self.id, _ptr(a), 0))
+        return a
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, np.float32)
+        _check(_lib.pdf_surrogate_params(self.id, _ptr(a), 1))
+
+    def xfxq2(self, x, q2, n_cols, out=None, stream=None):
+        _dev_f64(x, "x")
+        _dev_f64(q2, "q2")
+        if out is None:
+            out = torch.empty((x.shape[0], n_cols), dtype=torch.float32, device=x.device)
+        _check(_lib.pdf_surrogate_xfxq2(self.id, _P(x.data_ptr()), _P(q2.data_ptr()), x.shape[0],
+                                        _P(out.data_ptr()), _stream(stream)))
+        return out
+
+    def save(self, path):
+        _check(_lib.pdf_surrogate_save(self.id, str(path).encode()))
+
+    def load(self, path):
+        _check(_lib.pdf_surrogate_load(self.id, str(path).encode()))
+
+    def destroy(self):
+        if self.id >= 0:
+            _check(_lib.pdf_surrogate_destroy(self.id))
+            self.id = -1
 
 
 def set_lds_policy(policy):

@@ -1,0 +1,208 @@
+"""MLP surrogate: matrix-core gradients vs the FP64 oracle on the same BF16
+operands, fused inference vs the oracle forward, fallback points vs the
+interpolator, deterministic checkpoint/resume, and what a trained network
+gains over the interpolator (speed at its measured error)."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_2009_06635_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_2009_06635_amd import pdfmi  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def dev(a, dt=np.float64):
+    return torch.from_numpy(np.ascontiguousarray(a, dt)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    g = synth.config1_grid()
+    m = pdfmi.load_synth(g)
+    yield g, m
+    pdfmi.unload(m)
+
+
+def envelope(g, x):
+    """Independent restatement of the output envelope: largest |xf_c| over the
+    Q^2 knots at each x knot, linear in ln x."""
+    xk = g.xknots[0]
+    E = np.max(np.abs(np.concatenate(g.values, axis=1)), axis=1)   # [nx][P]
+    lx = np.log(x)
+    i = np.clip(np.searchsorted(np.log(xk), lx, side="right") - 1, 0, len(xk) - 2)
+    t = np.clip((lx - np.log(xk[i])) / (np.log(xk[i + 1]) - np.log(xk[i])), 0, 1)
+    return E[i] + t[:, None] * (E[i + 1] - E[i])
+
+
+def normalise(g, x, q2):
+    lx0, lx1 = np.log(g.xknots[0][0]), np.log(g.xknots[0][-1])
+    lq0, lq1 = np.log(g.q2knots[0][0]), np.log(g.q2knots[-1][-1])
+    u = 2 * (np.log(x) - lx0) / (lx1 - lx0) - 1
+    v = 2 * (np.log(q2) - lq0) / (lq1 - lq0) - 1
+    return np.stack([u, v], axis=1).astype(np.float32)
+
+
+def trusted_mask(g, x, q2):
+    xk, qk = g.xknots[0], g.q2knots[0]
+    return (x >= xk[1]) & (x < xk[-2]) & (q2 >= qk[1]) & (q2 < qk[-2])
+
+
+@pytest.mark.parametrize("B", [16, 48, 256])
+def test_gradients_match_oracle(cfg1, B):
+    g, m = cfg1
+    s = pdfmi.Surrogate(m, seed=7)
+    try:
+        rng = np.random.default_rng(B)
+        p = (rng.normal(0, 0.25, mlp.NPARAMS)).astype(np.float32)
+        s.set_params(p)
+        inp = rng.uniform(-1, 1, (B, 2)).astype(np.float32)
+        tgt = rng.normal(0, 1, (B, 16)).astype(np.float32)
+        gr, loss = s.grad(dev(inp, np.float32), dev(tgt, np.float32))
+        gr = gr.cpu().numpy().astype(np.float64)
+        lo, go, _ = mlp.loss_grad_bf16(p.astype(np.float64), inp.astype(np.float64), tgt.astype(np.float64))
+        assert abs(loss.item() - lo) <= 1e-3 * lo
+        d = mlp.unpack(gr)
+        do = mlp.unpack(go)
+        for k in do:
+            err = np.linalg.norm(d[k] - do[k]) / (np.linalg.norm(do[k]) + 1e-30)
+            assert err < 5e-3, (k, err)
+    finally:
+        s.destroy()
+
+
+def test_inference_matches_oracle_forward(cfg1):
+    g, m = cfg1
+    s = pdfmi.Surrogate(m, seed=11)
+    try:
+        rng = np.random.default_rng(3)
+        p = rng.normal(0, 0.3, mlp.NPARAMS).astype(np.float32)
+        s.set_params(p)
+        x, q2 = synth.config1_queries(n=4000, seed=31)
+        out = s.xfxq2(dev(x), dev(q2), len(g.pids)).cpu().numpy().astype(np.float64)
+        tm = trusted_mask(g, x, q2)
+        y = mlp.forward_bf16(p.astype(np.float64), normalise(g, x, q2).astype(np.float64))[:, :len(g.pids)]
+        want = y * envelope(g, x)
+        E = envelope(g, x)
+        err = np.abs(out - want)[tm]
+        scale = ((np.abs(y) + 0.05) * E)[tm]
+        assert np.all(err <= 2e-2 * scale), np.max(err / scale)
+    finally:
+        s.destroy()
+
+
+def test_fallback_points_use_interpolator(cfg1):
+    g, m = cfg1
+    s = pdfmi.Surrogate(m, seed=1)
+    try:
+        x, q2 = synth.config1_queries(n=20000, seed=32)
+        x[:5] = [1e-8, 0.5, 0.999, 1e-6, -1.0]
+        q2[:5] = [10.0, 1e9, 10.0, 1.0, 10.0]
+        tm = trusted_mask(g, x, q2)
+        out = s.xfxq2(dev(x), dev(q2), len(g.pids)).cpu().numpy()
+        ref = pdfmi.xfxq2_f32(m, g.pids, dev(x), dev(q2)).cpu().numpy()
+        assert (~tm).sum() > 100
+        a, b = out[~tm], ref[~tm]
+        assert np.array_equal(np.isnan(a), np.isnan(b))
+        assert np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)])
+    finally:
+        s.destroy()
+
+
+def test_training_is_deterministic_across_checkpoint(cfg1, tmp_path):
+    g, m = cfg1
+    x, q2 = synth.config1_queries(n=32768, seed=33)
+    xd, qd = dev(x), dev(q2)
+    a = pdfmi.Surrogate(m, seed=5)
+    b = pdfmi.Surrogate(m, seed=5)
+    try:
+        a.set_data(xd, qd)
+        b.set_data(xd, qd)
+        inp = dev(normalise(g, x[:256], q2[:256]), np.float32)
+        tgt = torch.zeros((256, 16), dtype=torch.float32, device=DEV)
+        a.train(60, 512, 3e-3, 3e-4, 60)
+        b.train(30, 512, 3e-3, 3e-4, 60)
+        path = tmp_path / "sur.ckpt"
+        b.save(path)
+        c = pdfmi.Surrogate(m, seed=99)
+        try:
+            c.set_data(xd, qd)
+            c.load(path)
+            c.train(30, 512, 3e-3, 3e-4, 60)
+            assert np.array_equal(a.params(), c.params())
+        finally:
+            c.destroy()
+        # the checkpoint rejects corruption
+        raw = bytearray(path.read_bytes())
+        raw[40] ^= 1
+        path.write_bytes(bytes(raw))
+        with pytest.raises(pdfmi.PdfError):
+            b.load(path)
+        del inp, tgt
+    finally:
+        a.destroy()
+        b.destroy()
+
+
+def _rel_err(out, ora, floor=1e-8):
+    ok = np.abs(ora) > floor
+    return (np.abs(out - ora) / (np.abs(ora) + 1e-16))[ok]
+
+
+def test_trained_surrogate_gain(cfg1):
+    """Train on 2e6 interpolator samples; report the error against the FP64
+    oracle and the speed against the FP32 interpolator on 1e6 points."""
+    g, m = cfg1
+    xt, qt = synth.config1_queries(n=2_000_000, seed=40)
+    s = pdfmi.Surrogate(m, seed=3)
+    try:
+        s.set_data(dev(xt), dev(qt))
+        steps = int(os.environ.get("PDFMI_SUR_STEPS", "4000"))
+        t0 = time.perf_counter()
+        s.train(steps, 4096, 3e-3, 3e-5, steps)
+        torch.cuda.synchronize()
+        ttrain = time.perf_counter() - t0
+        x, q2 = synth.config1_queries(n=1_000_000, seed=41)
+        xd, qd = dev(x), dev(q2)
+        P = len(g.pids)
+        out = s.xfxq2(xd, qd, P)
+        ref = torch.empty_like(out)
+        for _ in range(2):
+            s.xfxq2(xd, qd, P, out=out)
+            pdfmi.xfxq2_f32(m, g.pids, xd, qd, out=ref)
+        torch.cuda.synchronize()
+
+        def ktime(fn, reps=5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        t_sur = ktime(lambda: s.xfxq2(xd, qd, P, out=out))
+        t_int = ktime(lambda: pdfmi.xfxq2_f32(m, g.pids, xd, qd, out=ref))
+        idx = np.random.default_rng(0).choice(len(x), 20000, replace=False)
+        ora = oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, g.values, g.pids), g.pids, x[idx], q2[idx])
+        o = out.cpu().numpy()[idx].astype(np.float64)
+        tm = trusted_mask(g, x[idx], q2[idx])
+        e_all = _rel_err(o, ora)
+        e_tr = _rel_err(o[tm], ora[tm])
+        print("surrogate: train %.2f s (%d steps); infer %.3f ms vs FP32 interpolator %.3f ms (gain %.2fx); "
+              "rel err (|xf|>1e-8) median %.2e p99 %.2e max %.2e, trusted region median %.2e; fallback %.1f%%"
+              % (ttrain, steps, t_sur, t_int, t_int / t_sur, np.median(e_all), np.percentile(e_all, 99),
+                 e_all.max(), np.median(e_tr), 100 * (1 - tm.mean())))
+        assert np.all(np.isfinite(o))
+        assert np.median(e_tr) < 5e-2
+    finally:
+        s.destroy()
