@@ -1,21 +1,30 @@
 """Benchmark: PDF evaluations per second on one MI355X.
 
-Workload (one "step" = one pass of the hot path over one batch): 1e7 query
-points of the three-sub-grid, 13-flavour synthetic set (196 x knots, 3 x 17
-Q^2 knots split at the 1.51 / 4.92 GeV thresholds, 1% of the points outside
-the grid), all flavours at every point in FP64 (pdf_xfxq2) plus alpha_s at
-every point (pdf_alphas_q2).  Inputs are resident in device memory before the
-timed region.  `value` counts PDF evaluations (points x flavours) only.
+Workload of the headline line (one "step" = one pass of the hot path over one
+batch): 1e7 query points of the three-sub-grid, 13-flavour synthetic set (196
+x knots, 3 x 17 Q^2 knots split at the 1.51 / 4.92 GeV thresholds, 1% of the
+points outside the grid), all flavours at every point in FP64 (pdf_xfxq2) plus
+alpha_s at every point (pdf_alphas_q2).  Inputs are resident in device memory
+before the timed region.  `value` counts PDF evaluations (points x flavours).
 
-The FP32-arithmetic variant (pdf_xfxq2_f32) is timed the same way and reported
-under "variants".  The dominant kernel's roofline uses its algorithmic bytes
-(16 B of (x, Q^2) in + 8 B per output value) over its average duration
-measured with HIP events on the launch stream.  cpu_baseline times the FP64
-oracle on the host cores over a bounded sample of the same points.
+"variants" reports, on the same clock:
+  f32        FP32 bulk arithmetic on the headline workload (pdf_xfxq2_f32)
+  small      the 1e5-point one-sub-grid workload (latency-bound), FP64
+  batched    101 members, 200 requests (log-normal sizes, random flavour
+             subsets), one persistent hipGraph-replayed launch with autotuned
+             tiles, FP32 arithmetic; speed-up over per-request FP64 calls
+  surrogate  MLP surrogate trained on 2e6 interpolator samples, inference on
+             1e7 points with interpolator fallback; error vs the FP64 oracle
+  mc         1e8 Monte-Carlo-style points (two lookups at a shared scale,
+             alpha_s, FP64 fixed-order chunk sums), FP64 / FP32 / surrogate
+The dominant kernel's roofline uses its algorithmic bytes (16 B of (x, Q^2) in
++ 8 B per output value) over its average duration measured with HIP events on
+the launch stream.  cpu_baseline times the FP64 oracle on the host cores.
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -28,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "pdfmi.cpp", "pdfmi_dev.h"):
+    for f in ("kernels.hip", "interp_dev.h", "pdfmi.cpp", "pdfmi_dev.h"):
         with open(os.path.join(ROOT, "paper_2009_06635_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -47,21 +56,8 @@ def measured_traffic(kernel_key):
     return d.get(kernel_key)
 
 
-def cpu_baseline(grid, x, q2, sample):
-    import numpy as np
-
-    import oracle
-    og = oracle.Grid(grid.xknots, grid.q2knots, grid.values, grid.pids)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    cores = max(1, min(cores, os.cpu_count() or 1))
-    xs, qs = np.ascontiguousarray(x[:sample]), np.ascontiguousarray(q2[:sample])
-    oracle.xfxq2(og, grid.pids, xs[:1000], qs[:1000], n_threads=cores)   # warm
-    t0 = time.perf_counter()
-    oracle.xfxq2(og, grid.pids, xs, qs, n_threads=cores)
-    dt = time.perf_counter() - t0
-    return {"value": sample * len(grid.pids) / dt, "unit": "PDF evals/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d of the %d workload points, all %d flavours, FP64 oracle (OpenMP over points), "
-                      "%.1f s wall" % (sample, len(x), len(grid.pids), dt)}
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def main():
@@ -72,10 +68,15 @@ def main():
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-headline", action="store_true", help="skip the variants")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--sur-steps", type=int, default=2000)
+    ap.add_argument("--mc-chunks", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(query points shard with no exchange; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: query points shard across GPUs with no exchange, "
+              "and this build runs and reports the single-GPU path only.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -84,6 +85,46 @@ def main():
     from paper_2009_06635_amd import pdfmi, synth
 
     dev = "cuda:0"
+    torch.cuda.init()
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, steps, warmup):
+        """(wall seconds per step, mean kernel ms between fn's own events)."""
+        for _ in range(warmup):
+            fn(None)
+        evs = [(ev(), ev()) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e in evs:
+            fn(e)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        kern = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+        return wall, kern
+
+    def dtime(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # ---------------------------------------------------------------- headline
+    log("headline workload: generating 1e7 points")
     g = synth.config2_grid()
     x, q2 = synth.config2_queries(n=args.n)
     member = pdfmi.load_synth(g)
@@ -96,19 +137,6 @@ def main():
     out32 = torch.empty((args.n, P), dtype=torch.float32, device=dev)
     aout = torch.empty(args.n, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
-
-    def timed(fn, steps, warmup):
-        for _ in range(warmup):
-            fn(None)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for e in evs:
-            fn(e)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        kern = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
-        return wall, kern
 
     def step64(e):
         if e:
@@ -126,23 +154,22 @@ def main():
             e[1].record()
         pdfmi.alphas_q2(qd, out=aout)
 
+    log("timing FP64 / FP32")
     wall64, k64 = timed(step64, args.steps, args.warmup)
     wall32, k32 = timed(step32, args.steps, args.warmup)
     evals = args.n * P
     bytes64 = args.n * (16 + 8 * P)
     bytes32 = args.n * (16 + 4 * P)
-    ms64 = wall64 / args.steps * 1e3
     ach64 = bytes64 / (k64 * 1e-3) / 1e9
     ach32 = bytes32 / (k32 * 1e-3) / 1e9
-    t64 = measured_traffic("xfxq2_f64")
     res = {
         "metric": "PDF evals/s (points x flavours), FP64 log-bicubic interpolation",
-        "value": evals / (wall64 / args.steps),
+        "value": evals / wall64,
         "unit": "PDF evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms64,
+        "ms_per_step": wall64 * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -152,19 +179,181 @@ def main():
                                "1e7 points, 1% outside the grid", "n_points": args.n, "n_flavours": P,
                    "subgrids": 3, "x_knots": 196, "q2_knots_per_subgrid": 17},
         "roofline": {"bound": "hbm", "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach64 / HBM_PEAK_GBS,
-                     "traffic": t64,
+                     "frac": ach64 / HBM_PEAK_GBS, "traffic": measured_traffic("xfxq2_f64"),
                      "kernel": "k_xfxq2<double> (pdf_xfxq2)", "kernel_ms": k64,
                      "algorithmic_bytes_per_launch": bytes64},
         "variants": {
-            "f32": {"value": evals / (wall32 / args.steps), "ms_per_step": wall32 / args.steps * 1e3,
-                    "kernel_ms": k32, "achieved_GBs": ach32, "frac": ach32 / HBM_PEAK_GBS,
-                    "algorithmic_bytes_per_launch": bytes32, "kernel_evals_per_s": evals / (k32 * 1e-3)},
             "f64_kernel_evals_per_s": evals / (k64 * 1e-3),
+            "f32": {"value": evals / wall32, "ms_per_step": wall32 * 1e3, "kernel_ms": k32,
+                    "kernel_evals_per_s": evals / (k32 * 1e-3), "achieved_GBs": ach32,
+                    "frac": ach32 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes32,
+                    "speedup_vs_f64_kernel": k64 / k32},
         },
     }
+    V = res["variants"]
+    del out32
+
+    if not args.only_headline:
+        import oracle
+
+        def rel_stats(o, ora, floor=1e-8):
+            ok = np.abs(ora) > floor
+            r = (np.abs(o - ora) / np.abs(ora))[ok]
+            return {"median_rel": float(np.median(r)), "p99_rel": float(np.percentile(r, 99)),
+                    "max_rel": float(r.max()), "frac_le_1e-3": float((r <= 1e-3).mean())}
+
+        # ---------------------------------------------------------- small (1e5)
+        log("small workload")
+        g1 = synth.config1_grid()
+        m1 = pdfmi.load_synth(g1)
+        x1, q1 = synth.config1_queries()
+        x1d, q1d = torch.from_numpy(x1).to(dev), torch.from_numpy(q1).to(dev)
+        o1 = torch.empty((len(x1), len(g1.pids)), dtype=torch.float64, device=dev)
+        ks = dtime(lambda: pdfmi.xfxq2(m1, g1.pids, x1d, q1d, out=o1), reps=20)
+        V["small"] = {"n_points": len(x1), "n_flavours": len(g1.pids), "kernel_ms": ks,
+                      "evals_per_s": len(x1) * len(g1.pids) / (ks * 1e-3)}
+
+        # ---------------------------------------------------------- batched
+        log("batched workload: 101 members, 200 requests")
+        members = synth.config3_members()
+        mids = [pdfmi.load_synth(mg) for mg in members]
+        reqs_h = synth.config3_requests()
+        reqs = []
+        for r in reqs_h:
+            xr = torch.from_numpy(r["x"]).to(dev)
+            qr = torch.from_numpy(r["q2"]).to(dev)
+            orr = torch.empty((len(r["x"]), len(r["pids"])), dtype=torch.float32, device=dev)
+            reqs.append((mids[r["member"]], r["pids"], xr, qr, orr))
+        plan = pdfmi.BatchPlan(reqs)
+        tile, vec = plan.autotune(reps=2)
+        plan.configure(tile_points=tile, vector_cols=vec, use_graph=1)
+        tb = dtime(plan.run, reps=10)
+        npts = sum(len(r["x"]) for r in reqs_h)
+        nev = sum(len(r["x"]) * len(r["pids"]) for r in reqs_h)
+        o64 = [torch.empty((t[2].shape[0], len(t[1])), dtype=torch.float64, device=dev) for t in reqs]
+
+        def per_request_f64():
+            for t, o in zip(reqs, o64):
+                pdfmi.xfxq2(t[0], t[1], t[2], t[3], out=o)
+        tp = dtime(per_request_f64, reps=3)
+        # error of the batched FP32 output vs the FP64 oracle on a sample of requests
+        errs = []
+        for i in range(0, len(reqs_h), 25):
+            r = reqs_h[i]
+            mg = members[r["member"]]
+            k = min(2000, len(r["x"]))
+            ora = oracle.xfxq2(oracle.Grid(mg.xknots, mg.q2knots, mg.values, mg.pids), r["pids"], r["x"][:k],
+                               r["q2"][:k])
+            errs.append((reqs[i][4][:k].cpu().numpy().astype(np.float64), ora))
+        V["batched"] = {"members": len(mids), "requests": len(reqs), "points": npts, "evals": nev,
+                        "tile_points": tile, "vector_cols": vec, "graph": True, "ms": tb,
+                        "evals_per_s": nev / (tb * 1e-3), "per_request_f64_ms": tp,
+                        "speedup_vs_per_request_f64": tp / tb,
+                        "error_vs_oracle": rel_stats(np.concatenate([e[0].ravel() for e in errs]),
+                                                     np.concatenate([e[1].ravel() for e in errs]))}
+        plan.destroy()
+        del reqs, o64
+        for m_ in mids:
+            pdfmi.unload(m_)
+
+        # ---------------------------------------------------------- surrogate
+        log("surrogate: training on 2e6 samples")
+        xt, qt = synth.config1_queries(n=2_000_000, seed=40)
+        sur = pdfmi.Surrogate(m1, seed=3)
+        sur.set_data(torch.from_numpy(xt).to(dev), torch.from_numpy(qt).to(dev))
+        t0 = time.perf_counter()
+        sur.train(args.sur_steps, 4096, 3e-3, 3e-5, args.sur_steps)
+        torch.cuda.synchronize()
+        ttrain = time.perf_counter() - t0
+        xs, qs = synth.config1_queries(n=10_000_000, seed=41)
+        xsd, qsd = torch.from_numpy(xs).to(dev), torch.from_numpy(qs).to(dev)
+        P1 = len(g1.pids)
+        so = torch.empty((len(xs), P1), dtype=torch.float32, device=dev)
+        ref64 = torch.empty((len(xs), P1), dtype=torch.float64, device=dev)
+        ref32 = torch.empty((len(xs), P1), dtype=torch.float32, device=dev)
+        t_sur = dtime(lambda: sur.xfxq2(xsd, qsd, P1, out=so))
+        t_i64 = dtime(lambda: pdfmi.xfxq2(m1, g1.pids, xsd, qsd, out=ref64))
+        t_i32 = dtime(lambda: pdfmi.xfxq2_f32(m1, g1.pids, xsd, qsd, out=ref32))
+        idx = np.random.default_rng(0).choice(len(xs), 20000, replace=False)
+        ora = oracle.xfxq2(oracle.Grid(g1.xknots, g1.q2knots, g1.values, g1.pids), g1.pids, xs[idx], qs[idx])
+        idx_t = torch.from_numpy(idx).to(dev)
+        V["surrogate"] = {"n_points": len(xs), "n_flavours": P1, "train_s": ttrain, "train_steps": args.sur_steps,
+                          "ms": t_sur, "evals_per_s": len(xs) * P1 / (t_sur * 1e-3),
+                          "interp_f64_ms": t_i64, "interp_f32_ms": t_i32,
+                          "speedup_vs_f64_interp": t_i64 / t_sur, "speedup_vs_f32_interp": t_i32 / t_sur,
+                          "error_vs_oracle": rel_stats(so[idx_t].cpu().numpy().astype(np.float64), ora)}
+        del ref32
+
+        # ---------------------------------------------------------- Monte-Carlo load
+        nchunk = args.mc_chunks
+        log("mc workload: %d chunks of 1e6 points" % nchunk)
+        qk1, a1 = synth.config1_alphas()
+        pdfmi.load_alphas(qk1, a1)
+        ch = [synth.config5_chunk(c) for c in range(nchunk)]
+        X1 = [torch.from_numpy(c[0]).to(dev) for c in ch]
+        X2 = [torch.from_numpy(c[1]).to(dev) for c in ch]
+        Q = [torch.from_numpy(c[2]).to(dev) for c in ch]
+        PIDS = synth.PIDS_13
+        n_c = len(ch[0][0])
+        f1_64 = torch.empty((n_c, 13), dtype=torch.float64, device=dev)
+        f2_64 = torch.empty_like(f1_64)
+        f1_32 = torch.empty((n_c, 13), dtype=torch.float32, device=dev)
+        f2_32 = torch.empty_like(f1_32)
+        s1 = torch.empty((n_c, P1), dtype=torch.float32, device=dev)
+        s2 = torch.empty_like(s1)
+        al = torch.empty(n_c, dtype=torch.float64, device=dev)
+        ws = pdfmi.mc_workspace(n_c, dev)
+        sums = {k: torch.empty(nchunk, dtype=torch.float64, device=dev) for k in ("f64", "f32", "sur")}
+
+        def run_mc(kind):
+            for c in range(nchunk):
+                pdfmi.alphas_q2(Q[c], out=al)
+                if kind == "f64":
+                    pdfmi.xfxq2(m1, PIDS, X1[c], Q[c], out=f1_64)
+                    pdfmi.xfxq2(m1, PIDS, X2[c], Q[c], out=f2_64)
+                    pdfmi.mc_chunk_sum(f1_64, f2_64, al, workspace=ws, out=sums[kind][c:c + 1])
+                elif kind == "f32":
+                    pdfmi.xfxq2_f32(m1, PIDS, X1[c], Q[c], out=f1_32)
+                    pdfmi.xfxq2_f32(m1, PIDS, X2[c], Q[c], out=f2_32)
+                    pdfmi.mc_chunk_sum(f1_32, f2_32, al, workspace=ws, out=sums[kind][c:c + 1])
+                else:   # surrogate gives the stored flavours; absent ones are zero and add nothing
+                    sur.xfxq2(X1[c], Q[c], P1, out=s1)
+                    sur.xfxq2(X2[c], Q[c], P1, out=s2)
+                    pdfmi.mc_chunk_sum(s1, s2, al, workspace=ws, out=sums[kind][c:c + 1])
+        mc = {"points": nchunk * n_c, "chunks": nchunk, "evals_per_point": 26}
+        for kind in ("f64", "f32", "sur"):
+            ms = dtime(lambda: run_mc(kind), reps=1)
+            mc[kind] = {"ms": ms, "evals_per_s": nchunk * n_c * 26 / (ms * 1e-3)}
+        tot = {k: float(sums[k].sum().item()) for k in sums}
+        # chunk 0 against the oracle
+        og1 = oracle.Grid(g1.xknots, g1.q2knots, g1.values, g1.pids)
+        th = max(1, min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1))
+        oc1 = oracle.xfxq2(og1, PIDS, ch[0][0], ch[0][2], n_threads=th)
+        oc2 = oracle.xfxq2(og1, PIDS, ch[0][1], ch[0][2], n_threads=th)
+        oa = oracle.alphas_q2(qk1, a1, ch[0][2])
+        s0 = math.fsum(oa * np.sum(oc1 * oc2, axis=1))
+        for kind in ("f64", "f32", "sur"):
+            mc[kind]["chunk0_rel_err_vs_oracle"] = abs(float(sums[kind][0].item()) - s0) / abs(s0)
+            mc[kind]["total"] = tot[kind]
+            mc[kind]["speedup_vs_f64"] = mc["f64"]["ms"] / mc[kind]["ms"]
+        V["mc"] = mc
+        sur.destroy()
+        del X1, X2, Q
+
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(g, x, q2, min(args.cpu_sample, args.n))
+        log("cpu baseline (oracle)")
+        import oracle
+        og = oracle.Grid(g.xknots, g.q2knots, g.values, g.pids)
+        cores = max(1, min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1))
+        sample = min(args.cpu_sample, args.n)
+        xs_, qs_ = np.ascontiguousarray(x[:sample]), np.ascontiguousarray(q2[:sample])
+        oracle.xfxq2(og, g.pids, xs_[:1000], qs_[:1000], n_threads=cores)
+        t0 = time.perf_counter()
+        oracle.xfxq2(og, g.pids, xs_, qs_, n_threads=cores)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": sample * P / dt, "unit": "PDF evals/s", "cores": cores, "kind": "oracle",
+                               "sample": "first %d of the %d headline points, all %d flavours, FP64 oracle "
+                                         "(OpenMP over points), %.1f s wall" % (sample, args.n, P, dt)}
     print(json.dumps(res), flush=True)
 
 

@@ -281,6 +281,10 @@ int pdf_mc_workspace_bytes(int64_t n, int64_t* bytes_out);
 int pdf_mc_chunk_sum(const double* xf1, const double* xf2, int32_t n_pids,
                      const double* alphas, int64_t n, double* workspace,
                      double* sum_out, pdf_stream_t stream);
+/* The same sum over FP32 PDF values (products and sums in FP64). */
+int pdf_mc_chunk_sum_f32(const float* xf1, const float* xf2, int32_t n_pids,
+                         const double* alphas, int64_t n, double* workspace,
+                         double* sum_out, pdf_stream_t stream);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* pdf_last_error(void);

@@ -366,7 +366,8 @@ __device__ __forceinline__ double block_tree_sum(double v, double* sh) {
   return sh[0];
 }
 
-__global__ __launch_bounds__(kMcThreads) void k_mc_partial(const double* __restrict__ xf1, const double* __restrict__ xf2,
+template <typename T>
+__global__ __launch_bounds__(kMcThreads) void k_mc_partial(const T* __restrict__ xf1, const T* __restrict__ xf2,
                                                            int P, const double* __restrict__ as, int64_t n,
                                                            double* __restrict__ partial) {
   __shared__ double sh[kMcThreads];
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(kMcThreads) void k_mc_partial(const double* __restr
   double acc = 0.0;
   for (int64_t i = beg + threadIdx.x; i < end; i += kMcThreads) {
     double lum = 0.0;
-    for (int j = 0; j < P; ++j) lum = fma(xf1[i * P + j], xf2[i * P + j], lum);
+    for (int j = 0; j < P; ++j) lum = fma((double)xf1[i * P + j], (double)xf2[i * P + j], lum);
     acc = fma(as[i], lum, acc);
   }
   const double s = block_tree_sum(acc, sh);
@@ -393,14 +394,19 @@ __global__ __launch_bounds__(kMcThreads) void k_mc_final(const double* __restric
 
 int64_t mc_partials(int64_t n) { return (n + kMcBlock - 1) / kMcBlock; }
 
-hipError_t launch_mc_sum(const double* xf1, const double* xf2, int P, const double* as, int64_t n, double* partial,
+template <typename T>
+hipError_t launch_mc_sum(const T* xf1, const T* xf2, int P, const double* as, int64_t n, double* partial,
                          double* sum_out, hipStream_t s) {
   const int64_t np = mc_partials(n);
   if (np > 0)
-    hipLaunchKernelGGL(k_mc_partial, dim3((unsigned)np), dim3(kMcThreads), 0, s, xf1, xf2, P, as, n, partial);
+    hipLaunchKernelGGL(k_mc_partial<T>, dim3((unsigned)np), dim3(kMcThreads), 0, s, xf1, xf2, P, as, n, partial);
   hipLaunchKernelGGL(k_mc_final, dim3(1), dim3(kMcThreads), 0, s, partial, np, sum_out);
   return hipGetLastError();
 }
+template hipError_t launch_mc_sum<double>(const double*, const double*, int, const double*, int64_t, double*, double*,
+                                          hipStream_t);
+template hipError_t launch_mc_sum<float>(const float*, const float*, int, const double*, int64_t, double*, double*,
+                                         hipStream_t);
 
 }  // namespace pdfmi
 

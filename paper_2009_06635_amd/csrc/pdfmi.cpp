@@ -43,7 +43,8 @@ hipError_t sur_prep(const SurDev& S, const double* x, const double* q2, const do
                     float* T, hipStream_t s);
 hipError_t sur_infer(const SurDev& S, const MemberDev& m, const SurBufs& b, const double* x, const double* q2,
                      int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu, hipStream_t s);
-hipError_t launch_mc_sum(const double*, const double*, int, const double*, int64_t, double*, double*, hipStream_t);
+template <typename T>
+hipError_t launch_mc_sum(const T*, const T*, int, const double*, int64_t, double*, double*, hipStream_t);
 }  // namespace pdfmi
 
 using namespace pdfmi;
@@ -1266,17 +1267,28 @@ extern "C" int pdf_mc_workspace_bytes(int64_t n, int64_t* bytes_out) {
   return PDF_OK;
 }
 
-extern "C" int pdf_mc_chunk_sum(const double* xf1, const double* xf2, int32_t n_pids, const double* alphas, int64_t n,
-                                double* workspace, double* sum_out, pdf_stream_t stream) {
+template <typename T>
+static int mc_sum_impl(const T* xf1, const T* xf2, int32_t n_pids, const double* alphas, int64_t n, double* workspace,
+                       double* sum_out, pdf_stream_t stream) {
   if (n < 0 || n_pids < 1 || n_pids > kMaxReq) return fail(PDF_ERR_ARG, "bad n or n_pids");
   if (!sum_out || !workspace) return fail(PDF_ERR_ARG, "null output or workspace");
   if (n > 0 && (!xf1 || !xf2 || !alphas)) return fail(PDF_ERR_ARG, "null input");
   std::lock_guard<std::mutex> lock(g_mu);
   int rc = ensure_init();
   if (rc != PDF_OK) return rc;
-  hipError_t e = launch_mc_sum(xf1, xf2, n_pids, alphas, n, workspace, sum_out, (hipStream_t)stream);
+  hipError_t e = launch_mc_sum<T>(xf1, xf2, n_pids, alphas, n, workspace, sum_out, (hipStream_t)stream);
   if (e != hipSuccess) return fail_hip(e, "launch mc sum");
   return PDF_OK;
+}
+
+extern "C" int pdf_mc_chunk_sum(const double* xf1, const double* xf2, int32_t n_pids, const double* alphas, int64_t n,
+                                double* workspace, double* sum_out, pdf_stream_t stream) {
+  return mc_sum_impl<double>(xf1, xf2, n_pids, alphas, n, workspace, sum_out, stream);
+}
+
+extern "C" int pdf_mc_chunk_sum_f32(const float* xf1, const float* xf2, int32_t n_pids, const double* alphas,
+                                    int64_t n, double* workspace, double* sum_out, pdf_stream_t stream) {
+  return mc_sum_impl<float>(xf1, xf2, n_pids, alphas, n, workspace, sum_out, stream);
 }
 
 extern "C" int pdf_set_lds_policy(int32_t policy) {

@@ -37,6 +37,7 @@ _SIGS = {
     "pdf_get_tuning": [_i32, _P],
     "pdf_mc_workspace_bytes": [_i64, _P],
     "pdf_mc_chunk_sum": [_P, _P, _i32, _P, _i64, _P, _P, _P],
+    "pdf_mc_chunk_sum_f32": [_P, _P, _i32, _P, _i64, _P, _P, _P],
     "pdf_batch_create": [_P, _i32, _i32, _P],
     "pdf_batch_configure": [_i32, _i32, _i32, _i32],
     "pdf_batch_run": [_i32, _P],
@@ -222,15 +223,19 @@ def mc_workspace(n, device="cuda"):
 def mc_chunk_sum(xf1, xf2, alphas, workspace=None, out=None, stream=None):
     """FP64 sum_i alphas[i] * sum_j xf1[i,j] * xf2[i,j] (fixed order); returns a
     one-element device tensor."""
-    for t, nm in ((xf1, "xf1"), (xf2, "xf2"), (alphas, "alphas")):
-        _dev_f64(t, nm)
+    _dev_f64(alphas, "alphas")
+    f32 = xf1.dtype == torch.float32
+    for t in (xf1, xf2):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == xf1.dtype and t.dtype in (torch.float32, torch.float64)):
+            raise TypeError("xf1, xf2 must be contiguous CUDA tensors of one float dtype")
     n, P = xf1.shape
     if workspace is None:
         workspace = mc_workspace(n, xf1.device)
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=xf1.device)
-    _check(_lib.pdf_mc_chunk_sum(_P(xf1.data_ptr()), _P(xf2.data_ptr()), P, _P(alphas.data_ptr()), n,
-                                 _P(workspace.data_ptr()), _P(out.data_ptr()), _stream(stream)))
+    fn = _lib.pdf_mc_chunk_sum_f32 if f32 else _lib.pdf_mc_chunk_sum
+    _check(fn(_P(xf1.data_ptr()), _P(xf2.data_ptr()), P, _P(alphas.data_ptr()), n, _P(workspace.data_ptr()),
+              _P(out.data_ptr()), _stream(stream)))
     return out
 
 
