@@ -88,7 +88,8 @@ int pdf_unload(int32_t member);
  * Load the alpha_s table (section 2.3: nodes from the set's metadata).
  * q2_knots non-decreasing, > 0; a value repeated once starts a new segment
  * (flavour threshold) and a Q^2 equal to it uses the upper segment; every
- * segment has >= 2 knots.  alphas finite.  Replaces any previous table.
+ * segment has >= 2 knots; at most 256 knots.  alphas finite.  Replaces any
+ * previous table.
  */
 int pdf_load_alphas(int32_t n_knots, const double* q2_knots, const double* alphas);
 

@@ -232,33 +232,46 @@ __global__ __launch_bounds__(256) void k_locate(MemberDev m, const double* __res
 
 // alpha_s(Q^2) (paper section 2.3): segment (repeated knot = threshold, the
 // upper segment owns it), FP64 knot search, cubic Hermite in ln Q^2 with
-// one-sided slopes at segment ends, constant outside the knots.
+// one-sided slopes at segment ends, constant outside the knots.  The table
+// (knots, values, cell coefficients) is staged in LDS once per workgroup.
+constexpr int kAlphasMaxKnots = 256;
+
 __global__ __launch_bounds__(256) void k_alphas(AlphasDev A, const double* __restrict__ Q2, int64_t n,
                                                 double* __restrict__ out, unsigned long long* __restrict__ nerr) {
+  __shared__ double sk[kAlphasMaxKnots];
+  __shared__ double sv[kAlphasMaxKnots];
+  __shared__ CellCoef sc[kAlphasMaxKnots];
+  for (int i = threadIdx.x; i < A.n; i += 256) {
+    sk[i] = A.knots[i];
+    sv[i] = A.vals[i];
+    sc[i] = A.cells[i];
+  }
+  __syncthreads();
+  const double qlo = sk[0], qhi = sk[A.n - 1], alo = sv[0], ahi = sv[A.n - 1];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double q2 = Q2[i];
     const bool valid = q2 > 0.0 && q2 < INFINITY;
     double r;
     if (!valid) {
       r = NAN;
-    } else if (q2 < A.knots[0]) {
-      r = A.vals[0];
-    } else if (q2 > A.knots[A.n - 1]) {
-      r = A.vals[A.n - 1];
+    } else if (q2 < qlo) {
+      r = alo;
+    } else if (q2 > qhi) {
+      r = ahi;
     } else {
       int s = 0;
       for (int j = 1; j < A.nseg; ++j)
         if (A.seg_first[j] <= q2) s = j;
       const int lo = A.seg_lo[s], hi = A.seg_hi[s];
       const int m = hi - lo + 1;
-      const int c = lo + find_cell(A.knots + lo, m, q2);
-      const CellCoef cc = A.cells[c];
+      const int c = lo + find_cell(sk + lo, m, q2);
+      const CellCoef cc = sc[c];
       const int m4 = m < 4 ? m : 4;
       const int st = min(max(c - 1, lo), hi - m4 + 1);
       double w[4];
       stencil_weights<double>(cell_u(q2, cc), cc, c - st, w);
-      double acc = w[0] * A.vals[st];
-      for (int a = 1; a < m4; ++a) acc = fma(w[a], A.vals[st + a], acc);
+      double acc = w[0] * sv[st];
+      for (int a = 1; a < m4; ++a) acc = fma(w[a], sv[st + a], acc);
       r = acc;
     }
     const unsigned long long bal = __ballot(!valid);
@@ -337,7 +350,7 @@ hipError_t launch_locate(const MemberDev& m, const double* x, const double* q2, 
 
 hipError_t launch_alphas(const AlphasDev& A, const double* q2, int64_t n, double* out, unsigned long long* nerr,
                          int n_cu, hipStream_t s) {
-  const int64_t nb = min((n + 255) / 256, (int64_t)n_cu * 16);
+  const int64_t nb = min((n + 255) / 256, (int64_t)n_cu * 8);
   hipLaunchKernelGGL(k_alphas, dim3((unsigned)nb), dim3(256), 0, s, A, q2, n, out, nerr);
   return hipGetLastError();
 }

@@ -372,7 +372,7 @@ extern "C" int pdf_unload(int32_t member) {
 
 extern "C" int pdf_validate_alphas(int32_t n, const double* q2k, const double* a) {
   if (!q2k || !a) return fail(PDF_ERR_ARG, "null pointer");
-  if (n < 2) return fail(PDF_ERR_GRID, "alpha_s table needs >= 2 knots");
+  if (n < 2 || n > 256) return fail(PDF_ERR_GRID, "alpha_s table needs 2..256 knots");
   int seg_len = 1, nseg = 1;
   for (int i = 0; i < n; ++i) {
     if (!std::isfinite(q2k[i]) || !(q2k[i] > 0.0) || !std::isfinite(a[i]))
