@@ -70,7 +70,9 @@ typedef void* pdf_stream_t;
  *                  first and last x knot; the last Q^2 knot of sub-grid k equals
  *                  the first of sub-grid k+1 (the threshold is repeated)
  *   values         for each sub-grid: x*f as [ix][iq][column] (column fastest),
- *                  finite, concatenated over sub-grids
+ *                  finite, concatenated over sub-grids; at most 8192 knots in
+ *                  total, and the device copy (each sub-grid padded to >= 4
+ *                  knots per axis, columns to an even count, FP64) within 2 GiB
  *   member_out     receives the member id (>= 0)
  * Errors: PDF_ERR_ARG (null pointers), PDF_ERR_GRID (shape/knots/values),
  * PDF_ERR_PID, PDF_ERR_NOMEM, PDF_ERR_DEVICE.  Synchronous: the grid is

@@ -35,6 +35,55 @@ struct VecOf<double, 2> { using type = double2; };
 template <>
 struct VecOf<float, 4> { using type = float4; };
 
+// Buffer resource over [base, base + bytes): loads and stores through it take
+// a 32-bit per-lane byte offset plus a uniform (scalar) byte offset, so the
+// stencil gathers need no 64-bit address arithmetic; the hardware returns
+// zero for loads past `bytes` and drops stores past it.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// G consecutive elements of T (G * sizeof(T) in {4, 8, 16} bytes).
+template <typename T, int G>
+__device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff, T* dst) {
+  constexpr int kBytes = G * (int)sizeof(T);
+  if constexpr (kBytes == 16) {
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    const unsigned int u[4] = {q.x, q.y, q.z, q.w};
+    __builtin_memcpy(dst, u, 16);
+  } else if constexpr (kBytes == 8) {
+    const u32x2 q = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    const unsigned int u[2] = {q.x, q.y};
+    __builtin_memcpy(dst, u, 8);
+  } else {
+    static_assert(kBytes == 4, "unsupported gather width");
+    const unsigned int u = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    __builtin_memcpy(dst, &u, 4);
+  }
+}
+
+template <typename T, int G>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int voff, const T* src) {
+  constexpr int kBytes = G * (int)sizeof(T);
+  if constexpr (kBytes == 16) {
+    unsigned int u[4];
+    __builtin_memcpy(u, src, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{u[0], u[1], u[2], u[3]}, r, voff, 0, 0);
+  } else if constexpr (kBytes == 8) {
+    unsigned int u[2];
+    __builtin_memcpy(u, src, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2{u[0], u[1]}, r, voff, 0, 0);
+  } else {
+    static_assert(kBytes == 4, "unsupported store width");
+    unsigned int u;
+    __builtin_memcpy(&u, src, 4);
+    __builtin_amdgcn_raw_buffer_store_b32(u, r, voff, 0, 0);
+  }
+}
+
 // x*f for a set of flavours; see file header.  out is point-major [n][R].
 // Each wave works on its own 64-point tiles with no workgroup barrier after
 // the initial staging, so the knot searches and log transforms of some waves
@@ -43,28 +92,44 @@ struct VecOf<float, 4> { using type = float4; };
 // afterwards, one point at a time across the wave.
 constexpr int kWave = 64;
 
+// Per-point record of phase 1, read back by the wave's own lanes in phase 2.
+struct PointInfo {
+  int boff;  // byte offset of the stencil origin f[sx][sq][0] in the member's values
+  int sab;   // byte stride between consecutive x knots
+  int mode;  // region bits (see locate_point)
+  int pad;
+};
+
 template <typename T>
 __host__ __device__ constexpr size_t wave_record_bytes() {
-  return (size_t)kWave * (8 * sizeof(T) + 16 + 12);
+  return (size_t)kWave * (8 * sizeof(T) + 16 + sizeof(PointInfo));
 }
 
-// One wave's 64-point tile [pbeg, pbeg + tp): phase 1 (one lane per point)
-// into the wave's LDS record, then the in-grid outputs (one lane per entry),
-// then the extrapolated points.  obase = output row of point pbeg.
-template <typename T, bool kLdsGrid, int G>
+// One wave's 64-point tile [pbeg, pbeg + tp): phase 1 (one lane per point,
+// (xv, qv) = this lane's point) into the wave's LDS record, then the in-grid
+// outputs, then the extrapolated points.  obase = output row of point pbeg.
+//
+// Phase 2 walks the tile's outputs with consecutive lanes on consecutive
+// output addresses: one lane per (point, flavour) for a flavour subset
+// (G = 1), or per (point, group of G stored columns) when every stored column
+// is requested in order (G * sizeof(T) = 16 bytes).  Reading the grid from
+// global memory, groups start at min(G*j, R - G): the last group of a point
+// overlaps the one before it and every store is full width (the shared
+// column gets the same value twice).  Reading it from LDS, groups start at
+// G*j (16-byte aligned LDS reads; rows are zero-padded to a multiple of G)
+// and the last group stores only the columns below R.
+template <typename T, bool kLdsGrid, int G, bool kOverlap = !kLdsGrid>
 __device__ __forceinline__ void wave_tile(const MemberDev& m, const double* sknots, const int* scol, int R,
-                                          const T* sgrid, const T* __restrict__ gvals,
-                                          const double* __restrict__ X, const double* __restrict__ Q2,
-                                          int64_t pbeg, int tp, T* __restrict__ obase,
+                                          const T* sgrid, const T* __restrict__ gvals, uint32_t gbytes,
+                                          double xv, double qv, int tp, T* __restrict__ obase,
                                           unsigned long long* __restrict__ nerr, double invL01,
                                           unsigned char* rec, int lane) {
   T* sw = reinterpret_cast<T*>(rec);                       // [64][4]
   T* sv = sw + kWave * 4;                                  // [64][4]
   double* sp = reinterpret_cast<double*>(sv + kWave * 4);  // [64][2]
-  int* sbase = reinterpret_cast<int*>(sp + 2 * kWave);
-  int* ssa = sbase + kWave;
-  int* smode = ssa + kWave;
+  PointInfo* sinfo = reinterpret_cast<PointInfo*>(sp + 2 * kWave);
   const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
+  const int rowb = Pp * (int)sizeof(T);  // bytes between consecutive Q^2 knots
   constexpr int kSlow = kLowX | kLowQ | kHighQ;
   // lane -> (point, flavour) or (point, column group) walk of the tile's outputs
   const int NE = G == 1 ? R : (R + G - 1) / G;
@@ -73,7 +138,7 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const double* skno
   bool bad = false, slow = false;
   if (lane < tp) {
     T w[4], v[4];
-    const PointLoc L = locate_point<T>(m, sknots, X[pbeg + lane], Q2[pbeg + lane], w, v);
+    const PointLoc L = locate_point<T>(m, sknots, xv, qv, w, v);
     bad = L.mode & kInvalid;
     slow = L.mode & kSlow;
 #pragma unroll
@@ -83,9 +148,7 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const double* skno
     }
     sp[2 * lane] = L.p0;
     sp[2 * lane + 1] = L.p1;
-    sbase[lane] = L.base;
-    ssa[lane] = L.sa;
-    smode[lane] = L.mode;
+    sinfo[lane] = PointInfo{L.base * (int)sizeof(T), L.sa * (int)sizeof(T), L.mode, 0};
   }
   const unsigned long long bal = __ballot(bad);
   if (bal && lane == 0) atomicAdd(nerr, (unsigned long long)__popcll(bal));
@@ -95,62 +158,70 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const double* skno
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+  const __amdgpu_buffer_rsrc_t gr = buffer_rsrc(gvals, gbytes);
+  const __amdgpu_buffer_rsrc_t orr = buffer_rsrc(obase, (uint32_t)(tp * R * (int)sizeof(T)));
   const int nev = tp * NE;
   int p = e_p0, j = e_j0;
   for (int e = lane; e < nev; e += kWave) {
-    const int mode = smode[p];
-    if (!(mode & kSlow)) {
+    const PointInfo pi = sinfo[p];
+    if (!(pi.mode & kSlow)) {
       T w[4], v[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         w[a] = sw[p * 4 + a];
         v[a] = sv[p * 4 + a];
       }
-      const int base = sbase[p], sa = ssa[p];
-      const bool inv = mode & kInvalid;
+      const bool inv = pi.mode & kInvalid;
+      int c0;       // first output column of this entry
+      int ccol;     // its stored column (-1: flavour absent from the grid)
       if constexpr (G == 1) {
-        const int col = scol[j];
-        T val = (T)0;
-        if (inv) {
-          val = (T)NAN;
-        } else if (col >= 0) {
-          T F[4][4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const int o = base + col + a * sa;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) F[a][b] = kLdsGrid ? sgrid[o + b * Pp] : gvals[o + b * Pp];
-          }
-          val = interp_stencil<T>(F, w, v);
-        }
-        obase[e] = val;
+        c0 = j;
+        ccol = scol[j];
       } else {
-        using V = typename VecOf<T, G>::type;
-        T res[G];
-        if (inv) {
+        c0 = kOverlap ? min(G * j, R - G) : G * j;
+        ccol = c0;
+      }
+      T res[G];
+      if (inv) {
 #pragma unroll
-          for (int i = 0; i < G; ++i) res[i] = (T)NAN;
-        } else {
-          T F[G][4][4];
+        for (int i = 0; i < G; ++i) res[i] = (T)NAN;
+      } else if (ccol < 0) {
 #pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const int o = base + G * j + a * sa;
+        for (int i = 0; i < G; ++i) res[i] = (T)0;
+      } else {
+        const int o0 = pi.boff + ccol * (int)sizeof(T);
+        T F[G][4][4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              const V q = kLdsGrid ? *reinterpret_cast<const V*>(sgrid + o + b * Pp)
-                                   : *reinterpret_cast<const V*>(gvals + o + b * Pp);
-              const T* qs = reinterpret_cast<const T*>(&q);
+        for (int a = 0; a < 4; ++a) {
+          const int oa = o0 + a * pi.sab;
 #pragma unroll
-              for (int i = 0; i < G; ++i) F[i][a][b] = qs[i];
+          for (int b = 0; b < 4; ++b) {
+            T q[G];
+            if constexpr (kLdsGrid) {
+              const T* s = reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(sgrid) + oa + b * rowb);
+              if constexpr (G > 1) {
+                using V = typename VecOf<T, G>::type;  // 16-byte aligned: groups start at multiples of G
+                const V vq = *reinterpret_cast<const V*>(s);
+                __builtin_memcpy(q, &vq, sizeof(V));
+              } else {
+                q[0] = s[0];
+              }
+            } else {
+              buf_load<T, G>(gr, oa, b * rowb, q);
             }
+#pragma unroll
+            for (int i = 0; i < G; ++i) F[i][a][b] = q[i];
           }
-#pragma unroll
-          for (int i = 0; i < G; ++i) res[i] = interp_stencil<T>(F[i], w, v);
         }
-        T* o = obase + p * R + G * j;
 #pragma unroll
-        for (int i = 0; i < G; ++i)
-          if (G * j + i < R) o[i] = res[i];
+        for (int i = 0; i < G; ++i) res[i] = interp_stencil<T>(F[i], w, v);
+      }
+      const int ob = (p * R + c0) * (int)sizeof(T);
+      if (kOverlap || G * j + G <= R) {
+        buf_store<T, G>(orr, ob, res);
+      } else {
+        // last group of a point without overlap: only the columns below R
+        for (int i = 0; i < R - G * j; ++i) buf_store<T, 1>(orr, ob + i * (int)sizeof(T), res + i);
       }
     }
     p += e_dp;
@@ -164,15 +235,16 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const double* skno
   while (slow_mask) {
     const int q = __builtin_ctzll(slow_mask);
     slow_mask &= slow_mask - 1;
-    const int mode = smode[q];
+    const PointInfo pi = sinfo[q];
     const Wts wt{(double)sw[q * 4], (double)sw[q * 4 + 1], (double)sw[q * 4 + 2], (double)sw[q * 4 + 3],
                  (double)sv[q * 4], (double)sv[q * 4 + 1], (double)sv[q * 4 + 2], (double)sv[q * 4 + 3]};
     for (int jj = lane; jj < R; jj += kWave) {
-      const int col = scol[jj];
+      const int col = G == 1 ? scol[jj] : jj;
       T val = (T)0;
       if (col >= 0) {
-        const T* f = (kLdsGrid ? (const T*)sgrid : gvals) + sbase[q] + col;
-        val = (T)extrap_entry<T>(f, ssa[q], Pp, mode, wt, sp[2 * q], sp[2 * q + 1], invL01);
+        const T* f = reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(kLdsGrid ? sgrid : gvals) +
+                                                pi.boff) + col;
+        val = (T)extrap_entry<T>(f, pi.sab / (int)sizeof(T), Pp, pi.mode, wt, sp[2 * q], sp[2 * q + 1], invL01);
       }
       obase[q * R + jj] = val;
     }
@@ -182,11 +254,14 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const double* skno
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+#ifndef PDFMI_WAVES_PER_EU
+#define PDFMI_WAVES_PER_EU 1
+#endif
+
 template <typename T, bool kLdsGrid, int G, int BS>
-__global__ __launch_bounds__(BS) void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X,
-                                              const double* __restrict__ Q2, int64_t n, T* __restrict__ out,
-                                              unsigned long long* __restrict__ nerr, int lds_grid_elems,
-                                              double invL01) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PDFMI_WAVES_PER_EU)))
+void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X, const double* __restrict__ Q2, int64_t n,
+             T* __restrict__ out, unsigned long long* __restrict__ nerr, int lds_grid_elems, double invL01) {
   constexpr int kWaves = BS / kWave;
   extern __shared__ __align__(16) unsigned char smem[];
   double* sknots = reinterpret_cast<double*>(smem);                       // [nknots_pad]
@@ -197,21 +272,38 @@ __global__ __launch_bounds__(BS) void k_xfxq2(MemberDev m, ReqCols rc, const dou
   for (int i = threadIdx.x; i < m.nknots; i += BS) sknots[i] = m.knots[i];
   for (int i = threadIdx.x; i < rc.n; i += BS) scol[i] = rc.col[i];
   const T* __restrict__ gvals = member_values<T>(m);
+  const uint32_t gbytes = (uint32_t)((sizeof(T) == 8 ? m.elems64 : m.elems32) * (int64_t)sizeof(T));
   if constexpr (kLdsGrid) {
     for (int i = threadIdx.x; i < lds_grid_elems; i += BS) sgrid[i] = gvals[i];
   }
   __syncthreads();
 
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   unsigned char* rec = srec + wv * wave_record_bytes<T>();
   const int R = rc.n;
   const int64_t ntiles = (n + kWave - 1) / kWave;
-  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wv; tile < ntiles; tile += (int64_t)gridDim.x * kWaves) {
+  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  int64_t tile = (int64_t)blockIdx.x * kWaves + wv;
+  // the next tile's (x, Q^2) are loaded before the current tile is processed
+  double xc = 0.0, qc = 0.0;
+  if (tile < ntiles && tile * kWave + lane < n) {
+    xc = X[tile * kWave + lane];
+    qc = Q2[tile * kWave + lane];
+  }
+  for (; tile < ntiles; tile += stride) {
     const int64_t pbeg = tile * kWave;
     const int tp = (int)min((int64_t)kWave, n - pbeg);
-    wave_tile<T, kLdsGrid, G>(m, sknots, scol, R, sgrid, gvals, X, Q2, pbeg, tp, out + pbeg * R, nerr, invL01, rec,
-                              lane);
+    const int64_t nxt = pbeg + stride * kWave + lane;
+    double xn = 0.0, qn = 0.0;
+    if (nxt < n) {
+      xn = X[nxt];
+      qn = Q2[nxt];
+    }
+    wave_tile<T, kLdsGrid, G>(m, sknots, scol, R, sgrid, gvals, gbytes, xc, qc, tp, out + pbeg * R, nerr, invL01,
+                              rec, lane);
+    xc = xn;
+    qc = qn;
   }
 }
 
@@ -318,8 +410,9 @@ static hipError_t launch_xfxq2_g(const MemberDev& m, const ReqCols& rc, const do
 }
 
 // The vectorised kernel serves requests for every stored column in load order.
-static bool all_columns(const MemberDev& m, const ReqCols& rc) {
-  if (rc.n != m.P) return false;
+// Its groups of G columns need at least G of them.
+static bool all_columns(const MemberDev& m, const ReqCols& rc, int G) {
+  if (rc.n != m.P || rc.n < G) return false;
   for (int j = 0; j < rc.n; ++j)
     if (rc.col[j] != j) return false;
   return true;
@@ -328,7 +421,7 @@ static bool all_columns(const MemberDev& m, const ReqCols& rc) {
 hipError_t launch_xfxq2_f64(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2, int64_t n,
                             double* out, unsigned long long* nerr, int lds_grid_elems, double invL01,
                             const LaunchCfg& cfg, hipStream_t s) {
-  if (cfg.vector_cols && all_columns(m, rc))
+  if (cfg.vector_cols && all_columns(m, rc, 2))
     return launch_xfxq2_g<double, 2>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
   return launch_xfxq2_g<double, 1>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
 }
@@ -336,7 +429,7 @@ hipError_t launch_xfxq2_f64(const MemberDev& m, const ReqCols& rc, const double*
 hipError_t launch_xfxq2_f32(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2, int64_t n,
                             float* out, unsigned long long* nerr, int lds_grid_elems, double invL01,
                             const LaunchCfg& cfg, hipStream_t s) {
-  if (cfg.vector_cols && all_columns(m, rc))
+  if (cfg.vector_cols && all_columns(m, rc, 4))
     return launch_xfxq2_g<float, 4>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
   return launch_xfxq2_g<float, 1>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
 }
@@ -453,19 +546,20 @@ __global__ __launch_bounds__(kBatchBS) void k_batched(const BatchReq* __restrict
   unsigned char* srec = reinterpret_cast<unsigned char*>(scol + kMaxReq);  // per-wave records
   T* sgrid = reinterpret_cast<T*>(srec + kWaves * wave_record_bytes<T>());
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   unsigned char* rec = srec + wv * wave_record_bytes<T>();
   if (threadIdx.x == 0) s_member = -1;
   for (;;) {
     __syncthreads();  // previous tile finished by every wave before the LDS is reused
     if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
     __syncthreads();
-    const int t = s_tile;
+    const int t = __builtin_amdgcn_readfirstlane(s_tile);
     if (t >= ntiles) break;
     const BatchTile tl = tiles[t];
     const BatchReq rq = reqs[tl.req];
     const MemberDev& m = members[rq.member];
     const T* __restrict__ gvals = member_values<T>(m);
+    const uint32_t gbytes = (uint32_t)((sizeof(T) == 8 ? m.elems64 : m.elems32) * (int64_t)sizeof(T));
     if (rq.member != s_member) {
       for (int i = threadIdx.x; i < m.nknots; i += kBatchBS) sknots[i] = m.knots[i];
       if constexpr (kLdsGrid) {
@@ -481,12 +575,15 @@ __global__ __launch_bounds__(kBatchBS) void k_batched(const BatchReq* __restrict
     for (int w0 = wv * kWave; w0 < tl.count; w0 += kWaves * kWave) {
       const int64_t pbeg = tl.start + w0;
       const int tp = min(kWave, tl.count - w0);
-      if (vector_cols && rq.all_cols)
-        wave_tile<T, kLdsGrid, 16 / sizeof(T)>(m, sknots, scol, rq.R, sgrid, gvals, rq.x, rq.q2, pbeg, tp,
-                                               out + pbeg * rq.R, nerr, invL01, rec, lane);
+      constexpr int G = 16 / sizeof(T);
+      const double xv = lane < tp ? rq.x[pbeg + lane] : 0.0;
+      const double qv = lane < tp ? rq.q2[pbeg + lane] : 0.0;
+      if (vector_cols && rq.all_cols && rq.R >= G)
+        wave_tile<T, kLdsGrid, G>(m, sknots, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp, out + pbeg * rq.R, nerr,
+                                  invL01, rec, lane);
       else
-        wave_tile<T, kLdsGrid, 1>(m, sknots, scol, rq.R, sgrid, gvals, rq.x, rq.q2, pbeg, tp, out + pbeg * rq.R,
-                                  nerr, invL01, rec, lane);
+        wave_tile<T, kLdsGrid, 1>(m, sknots, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp, out + pbeg * rq.R, nerr,
+                                  invL01, rec, lane);
     }
   }
 }

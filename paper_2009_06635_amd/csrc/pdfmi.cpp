@@ -239,7 +239,11 @@ extern "C" int pdf_validate_grid(int32_t K, const int32_t* shape, int32_t P, con
     ko += nx + nq;
     vo += nv;
   }
-  if (vo > ((int64_t)1 << 31) / 2) return fail(PDF_ERR_GRID, "grid too large");
+  // the kernels address a member's padded FP64 values with 32-bit byte offsets
+  int64_t padded_bytes = 0;
+  for (int k = 0; k < K; ++k)
+    padded_bytes += (int64_t)std::max(shape[2 * k], 4) * std::max(shape[2 * k + 1], 4) * ((P + 1) & ~1) * 8;
+  if (padded_bytes > INT32_MAX) return fail(PDF_ERR_GRID, "grid values exceed 2 GiB");
   if (ko > 8192) return fail(PDF_ERR_GRID, "more than 8192 knots in total (they are staged in LDS)");
   return PDF_OK;
 }
