@@ -289,6 +289,37 @@ int pdf_mc_chunk_sum_f32(const float* xf1, const float* xf2, int32_t n_pids,
                          const double* alphas, int64_t n, double* workspace,
                          double* sum_out, pdf_stream_t stream);
 
+/*
+ * LHAPDF6 data files (section 2: the set folders are loaded directly, with
+ * the same layout as LHAPDF).  Host-only parsing; no device work except the
+ * final pdf_load_grid / pdf_load_alphas of the load calls.
+ *
+ * Member file ("lhagrid1"): a header of "key: value" lines ended by "---",
+ * then per sub-grid a block ended by "---": the x knots, the Q knots and the
+ * flavour ids on one line each, then nx*nq lines of one value per flavour,
+ * the Q index running fastest.  Q knots are squared (FP64) on reading.
+ *
+ * pdf_lhapdf_read(path, sizes, shape, pids, knots, values):
+ *   sizes[4] receives {K, P, knot count, value count}.  With all four arrays
+ *   NULL only the sizes are returned; otherwise all four must be non-NULL and
+ *   hold shape[2K], pids[P], knots[knot count], values[value count], filled
+ *   in pdf_load_grid's argument layout.  Errors: PDF_ERR_ARG (null pointers,
+ *   unreadable file), PDF_ERR_GRID (malformed file: the message names the
+ *   sub-grid and line).  Nothing is validated beyond the layout: a load call
+ *   applies pdf_validate_grid.
+ * pdf_load_lhapdf(path, member_out): read and pdf_load_grid in one call.
+ * pdf_lhapdf_read_alphas(info_path, n_out, q2_knots, alphas): the AlphaS_Qs
+ *   (squared) and AlphaS_Vals lists of a set's .info file; with both arrays
+ *   NULL only *n_out is set, otherwise both must hold *n_out entries.
+ * pdf_load_lhapdf_alphas(info_path): read and pdf_load_alphas in one call.
+ */
+int pdf_lhapdf_read(const char* path, int64_t* sizes, int32_t* shape, int32_t* pids,
+                    double* knots, double* values);
+int pdf_load_lhapdf(const char* path, int32_t* member_out);
+int pdf_lhapdf_read_alphas(const char* info_path, int32_t* n_out, double* q2_knots,
+                           double* alphas);
+int pdf_load_lhapdf_alphas(const char* info_path);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* pdf_last_error(void);
 

@@ -22,6 +22,33 @@ __device__ __forceinline__ int find_cell(const double* __restrict__ t, int n, do
   return i;
 }
 
+// Same index as find_cell, from the table's bucket hints (see HintAxis):
+// one hint read, then two independent knot comparisons.  v > 0.
+__device__ __forceinline__ int find_cell_hint(const double* __restrict__ t, int n, double v, const HintAxis& h,
+                                              const short* __restrict__ hints) {
+  if (h.off < 0) return find_cell(t, n, v);
+  const int last = n - 2;
+  const unsigned key = (unsigned)((unsigned long long)__double_as_longlong(v) >> h.shift);
+  const int b = min(max((int)(key - h.key0), 0), h.n - 1);
+  const int i = hints[h.off + b];
+  const int i1 = min(i + 1, last), i2 = min(i + 2, last);
+  return i + ((i + 1 <= last && t[i1] <= v) ? 1 : 0) + ((i + 2 <= last && t[i2] <= v) ? 1 : 0);
+}
+
+// Point-location tables as a kernel reads them: from LDS (staged copy of the
+// member's table block) or from global memory.
+struct Tables {
+  const double* knots;
+  const CellCoef* cells;
+  const short* hints;
+  const SubDesc* subs;
+};
+
+__device__ __forceinline__ Tables tables_at(const unsigned char* base, const MemberDev& m) {
+  return Tables{reinterpret_cast<const double*>(base), reinterpret_cast<const CellCoef*>(base + m.cells_off),
+                reinterpret_cast<const short*>(base + m.hints_off), reinterpret_cast<const SubDesc*>(base + m.subs_off)};
+}
+
 // Hermite weights of knots i-1..i+2 re-based onto the stencil that starts at
 // knot i - d (d = 0 left edge, 1 interior, 2 right edge).
 template <typename T>
@@ -58,8 +85,8 @@ struct PointLoc {
 
 // Phase 1: everything that depends on the point only.
 template <typename T>
-__device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const double* __restrict__ knots, double x,
-                                                 double q2, T w[4], T v[4]) {
+__device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const Tables& tb, double x, double q2, T w[4],
+                                                 T v[4]) {
   PointLoc L;
   L.p0 = 0.0;
   L.p1 = 0.0;
@@ -79,11 +106,11 @@ __device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const doubl
   int k = 0;
   for (int j = 1; j < m.K; ++j)
     if (m.sub[j].qfirst <= q2) k = j;
-  const SubDesc& S = m.sub[k];
-  const int ix = find_cell(knots + S.xk_off, S.nx, x);
-  const int iq = find_cell(knots + S.qk_off, S.nq, q2);
-  const CellCoef cx = m.cells[S.xc_off + ix];
-  const CellCoef cq = m.cells[S.qc_off + iq];
+  const SubDesc S = tb.subs[k];
+  const int ix = find_cell_hint(tb.knots + S.xk_off, S.nx, x, S.xh, tb.hints);
+  const int iq = find_cell_hint(tb.knots + S.qk_off, S.nq, q2, S.qh, tb.hints);
+  const CellCoef cx = tb.cells[S.xc_off + ix];
+  const CellCoef cq = tb.cells[S.qc_off + iq];
   const int sx = min(max(ix - 1, 0), S.nxp - 4);
   const int sq = min(max(iq - 1, 0), S.nqp - 4);
   if (!(mode & kLowX)) {
@@ -216,10 +243,10 @@ __device__ __noinline__ double extrap_entry(const T* f, int sa, int Pp, int mode
 // Value of one stored column at one point (location, weights, stencil and,
 // outside the grid, the extrapolation formula); NaN for an invalid point.
 template <typename T>
-__device__ __forceinline__ T interp_point(const MemberDev& m, const double* knots, double x, double q2, int col,
+__device__ __forceinline__ T interp_point(const MemberDev& m, const Tables& tb, double x, double q2, int col,
                                           double invL01) {
   T w[4], v[4];
-  const PointLoc L = locate_point<T>(m, knots, x, q2, w, v);
+  const PointLoc L = locate_point<T>(m, tb, x, q2, w, v);
   if (L.mode & kInvalid) return (T)NAN;
   const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
   const T* f = member_values<T>(m) + L.base + col;

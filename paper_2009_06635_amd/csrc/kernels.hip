@@ -119,7 +119,7 @@ __host__ __device__ constexpr size_t wave_record_bytes() {
 // G*j (16-byte aligned LDS reads; rows are zero-padded to a multiple of G)
 // and the last group stores only the columns below R.
 template <typename T, bool kLdsGrid, int G, bool kOverlap = !kLdsGrid>
-__device__ __forceinline__ void wave_tile(const MemberDev& m, const double* sknots, const int* scol, int R,
+__device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, const int* scol, int R,
                                           const T* sgrid, const T* __restrict__ gvals, uint32_t gbytes,
                                           double xv, double qv, int tp, T* __restrict__ obase,
                                           unsigned long long* __restrict__ nerr, double invL01,
@@ -138,7 +138,7 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const double* skno
   bool bad = false, slow = false;
   if (lane < tp) {
     T w[4], v[4];
-    const PointLoc L = locate_point<T>(m, sknots, xv, qv, w, v);
+    const PointLoc L = locate_point<T>(m, tb, xv, qv, w, v);
     bad = L.mode & kInvalid;
     slow = L.mode & kSlow;
 #pragma unroll
@@ -185,7 +185,7 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const double* skno
       if (inv) {
 #pragma unroll
         for (int i = 0; i < G; ++i) res[i] = (T)NAN;
-      } else if (ccol < 0) {
+      } else if (G == 1 && ccol < 0) {
 #pragma unroll
         for (int i = 0; i < G; ++i) res[i] = (T)0;
       } else {
@@ -258,18 +258,25 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const double* skno
 #define PDFMI_WAVES_PER_EU 1
 #endif
 
-template <typename T, bool kLdsGrid, int G, int BS>
+// LDS layout of k_xfxq2 and k_batched: [location tables][column map][per-wave
+// records][grid values], the tables only when they are staged (kLdsTables)
+// and the grid only when it is staged (kLdsGrid, which implies kLdsTables).
+template <typename T, bool kLdsGrid, int G, int BS, bool kLdsTables>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PDFMI_WAVES_PER_EU)))
 void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X, const double* __restrict__ Q2, int64_t n,
              T* __restrict__ out, unsigned long long* __restrict__ nerr, int lds_grid_elems, double invL01) {
+  static_assert(kLdsTables || !kLdsGrid, "a staged grid needs staged tables");
   constexpr int kWaves = BS / kWave;
   extern __shared__ __align__(16) unsigned char smem[];
-  double* sknots = reinterpret_cast<double*>(smem);                       // [nknots_pad]
-  int* scol = reinterpret_cast<int*>(sknots + m.nknots_pad);              // [kMaxReq]
-  unsigned char* srec = reinterpret_cast<unsigned char*>(scol + kMaxReq);  // per-wave records
+  unsigned char* stbl = smem;
+  int* scol = reinterpret_cast<int*>(smem + (kLdsTables ? m.tbl_bytes : 0));
+  unsigned char* srec = reinterpret_cast<unsigned char*>(scol + kMaxReq);
   T* sgrid = reinterpret_cast<T*>(srec + kWaves * wave_record_bytes<T>());
 
-  for (int i = threadIdx.x; i < m.nknots; i += BS) sknots[i] = m.knots[i];
+  if constexpr (kLdsTables) {
+    const uint4* src = reinterpret_cast<const uint4*>(m.tables);
+    for (int i = threadIdx.x; i < m.tbl_bytes / 16; i += BS) reinterpret_cast<uint4*>(stbl)[i] = src[i];
+  }
   for (int i = threadIdx.x; i < rc.n; i += BS) scol[i] = rc.col[i];
   const T* __restrict__ gvals = member_values<T>(m);
   const uint32_t gbytes = (uint32_t)((sizeof(T) == 8 ? m.elems64 : m.elems32) * (int64_t)sizeof(T));
@@ -277,6 +284,7 @@ void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X, const double
     for (int i = threadIdx.x; i < lds_grid_elems; i += BS) sgrid[i] = gvals[i];
   }
   __syncthreads();
+  const Tables tb = kLdsTables ? tables_at(stbl, m) : Tables{m.knots, m.cells, m.hints, m.subs};
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -300,8 +308,8 @@ void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X, const double
       xn = X[nxt];
       qn = Q2[nxt];
     }
-    wave_tile<T, kLdsGrid, G>(m, sknots, scol, R, sgrid, gvals, gbytes, xc, qc, tp, out + pbeg * R, nerr, invL01,
-                              rec, lane);
+    wave_tile<T, kLdsGrid, G>(m, tb, scol, R, sgrid, gvals, gbytes, xc, qc, tp, out + pbeg * R, nerr, invL01, rec,
+                              lane);
     xc = xn;
     qc = qn;
   }
@@ -314,7 +322,7 @@ __global__ __launch_bounds__(256) void k_locate(MemberDev m, const double* __res
                                                 int32_t* __restrict__ iqo, int8_t* __restrict__ rego) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double w[4], v[4];
-    const PointLoc L = locate_point<double>(m, m.knots, X[i], Q2[i], w, v);
+    const PointLoc L = locate_point<double>(m, Tables{m.knots, m.cells, m.hints, m.subs}, X[i], Q2[i], w, v);
     ko[i] = L.k;
     ixo[i] = L.ix;
     iqo[i] = L.iq;
@@ -375,38 +383,57 @@ __global__ __launch_bounds__(256) void k_alphas(AlphasDev A, const double* __res
 // ---------------------------------------------------------------------------------------
 // Launchers (host side, called by pdfmi.cpp)
 
+// Location tables up to this size are staged in LDS (typical sets need
+// 10-40 KB: a few hundred knots of 8 bytes plus 80 bytes of coefficients per
+// cell); larger ones are read from global memory.
+constexpr size_t kMaxLdsTables = 56 * 1024;
+static bool tables_fit(const MemberDev& m) { return (size_t)m.tbl_bytes <= kMaxLdsTables; }
+
 // LDS bytes of k_xfxq2 other than the staged grid, for a block of bs threads.
-static size_t shared_bytes(const MemberDev& m, bool f32, int bs) {
-  return (size_t)m.nknots_pad * 8 + kMaxReq * 4 +
+static size_t shared_bytes(const MemberDev& m, bool f32, int bs, bool tables) {
+  return (tables ? (size_t)m.tbl_bytes : 0) + kMaxReq * 4 +
          (bs / kWave) * (f32 ? wave_record_bytes<float>() : wave_record_bytes<double>());
 }
-constexpr int kBlockGlobal = 256;   // grid read from global memory
-constexpr int kBlockLds = 1024;     // grid staged once per workgroup in LDS
-size_t xfxq2_shared_bytes(const MemberDev& m, bool f32) { return shared_bytes(m, f32, kBlockLds); }
+constexpr int kBlockGlobal = 256;   // tables and grid read from global memory
+constexpr int kBlockTables = 512;   // tables staged in LDS, grid read from global memory
+constexpr int kBlockLds = 1024;     // tables and grid staged once per workgroup in LDS
+size_t xfxq2_shared_bytes(const MemberDev& m, bool f32) { return shared_bytes(m, f32, kBlockLds, true); }
+
+template <typename T, int G, int BS, bool kLdsGrid, bool kLdsTables>
+static hipError_t launch_one(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2, int64_t n,
+                             T* out, unsigned long long* nerr, int lds_grid_elems, double invL01, int64_t nb,
+                             size_t shm, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&k_xfxq2<T, kLdsGrid, G, BS, kLdsTables>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_xfxq2<T, kLdsGrid, G, BS, kLdsTables>), dim3((unsigned)nb), dim3(BS), shm, s, m, rc, x, q2,
+                     n, out, nerr, lds_grid_elems, invL01);
+  return hipGetLastError();
+}
 
 template <typename T, int G>
 static hipError_t launch_xfxq2_g(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2,
                                  int64_t n, T* out, unsigned long long* nerr, int lds_grid_elems,
                                  double invL01, const LaunchCfg& cfg, hipStream_t s) {
   const int n_cu = cfg.n_cu;
+  const bool f32 = sizeof(T) == 4;
   if (lds_grid_elems > 0) {
-    const size_t shm = shared_bytes(m, sizeof(T) == 4, kBlockLds) + (size_t)lds_grid_elems * sizeof(T);
+    const size_t shm = shared_bytes(m, f32, kBlockLds, true) + (size_t)lds_grid_elems * sizeof(T);
     const int per_cu = (int)(160 * 1024 / shm) > 0 ? (int)(160 * 1024 / shm) : 1;
     const int64_t ntiles = (n + kBlockLds - 1) / kBlockLds;
     const int64_t nb = min(ntiles, (int64_t)n_cu * per_cu);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xfxq2<T, true, G, kBlockLds>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_xfxq2<T, true, G, kBlockLds>), dim3((unsigned)nb), dim3(kBlockLds), shm, s, m, rc, x, q2,
-                       n, out, nerr, lds_grid_elems, invL01);
-  } else {
-    const size_t shm = shared_bytes(m, sizeof(T) == 4, kBlockGlobal);
-    const int64_t ntiles = (n + kBlockGlobal - 1) / kBlockGlobal;
-    const int64_t nb = min(ntiles, (int64_t)n_cu * cfg.blocks_per_cu);
-    hipLaunchKernelGGL((k_xfxq2<T, false, G, kBlockGlobal>), dim3((unsigned)nb), dim3(kBlockGlobal), shm, s, m, rc,
-                       x, q2, n, out, nerr, 0, invL01);
+    return launch_one<T, G, kBlockLds, true, true>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, nb, shm, s);
   }
-  return hipGetLastError();
+  if (tables_fit(m)) {
+    const size_t shm = shared_bytes(m, f32, kBlockTables, true);
+    const int64_t ntiles = (n + kBlockTables - 1) / kBlockTables;
+    const int64_t nb = min(ntiles, (int64_t)n_cu * cfg.blocks_per_cu);
+    return launch_one<T, G, kBlockTables, false, true>(m, rc, x, q2, n, out, nerr, 0, invL01, nb, shm, s);
+  }
+  const size_t shm = shared_bytes(m, f32, kBlockGlobal, false);
+  const int64_t ntiles = (n + kBlockGlobal - 1) / kBlockGlobal;
+  const int64_t nb = min(ntiles, (int64_t)n_cu * cfg.blocks_per_cu);
+  return launch_one<T, G, kBlockGlobal, false, false>(m, rc, x, q2, n, out, nerr, 0, invL01, nb, shm, s);
 }
 
 // The vectorised kernel serves requests for every stored column in load order.
@@ -531,18 +558,19 @@ __global__ void k_batch_reset(unsigned* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
-template <typename T, bool kLdsGrid>
+template <typename T, bool kLdsGrid, bool kLdsTables>
 __global__ __launch_bounds__(kBatchBS) void k_batched(const BatchReq* __restrict__ reqs, const int* __restrict__ cols,
                                                       const BatchTile* __restrict__ tiles, int ntiles,
                                                       const MemberDev* __restrict__ members,
                                                       const double* __restrict__ invL01s, unsigned* counter,
-                                                      unsigned long long* __restrict__ nerr, int max_knots,
+                                                      unsigned long long* __restrict__ nerr, int max_tbl,
                                                       int vector_cols) {
+  static_assert(kLdsTables || !kLdsGrid, "a staged grid needs staged tables");
   constexpr int kWaves = kBatchBS / kWave;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_tile, s_member;
-  double* sknots = reinterpret_cast<double*>(smem);                        // [max_knots]
-  int* scol = reinterpret_cast<int*>(sknots + max_knots);                  // [kMaxReq]
+  unsigned char* stbl = smem;                                              // [max_tbl] if staged
+  int* scol = reinterpret_cast<int*>(smem + (kLdsTables ? max_tbl : 0));  // [kMaxReq]
   unsigned char* srec = reinterpret_cast<unsigned char*>(scol + kMaxReq);  // per-wave records
   T* sgrid = reinterpret_cast<T*>(srec + kWaves * wave_record_bytes<T>());
   const int lane = threadIdx.x & (kWave - 1);
@@ -561,7 +589,10 @@ __global__ __launch_bounds__(kBatchBS) void k_batched(const BatchReq* __restrict
     const T* __restrict__ gvals = member_values<T>(m);
     const uint32_t gbytes = (uint32_t)((sizeof(T) == 8 ? m.elems64 : m.elems32) * (int64_t)sizeof(T));
     if (rq.member != s_member) {
-      for (int i = threadIdx.x; i < m.nknots; i += kBatchBS) sknots[i] = m.knots[i];
+      if constexpr (kLdsTables) {
+        const uint4* src = reinterpret_cast<const uint4*>(m.tables);
+        for (int i = threadIdx.x; i < m.tbl_bytes / 16; i += kBatchBS) reinterpret_cast<uint4*>(stbl)[i] = src[i];
+      }
       if constexpr (kLdsGrid) {
         const int64_t ne = sizeof(T) == 8 ? m.elems64 : m.elems32;
         for (int64_t i = threadIdx.x; i < ne; i += kBatchBS) sgrid[i] = gvals[i];
@@ -570,6 +601,7 @@ __global__ __launch_bounds__(kBatchBS) void k_batched(const BatchReq* __restrict
     for (int i = threadIdx.x; i < rq.R; i += kBatchBS) scol[i] = cols[rq.col_off + i];
     __syncthreads();
     if (threadIdx.x == 0) s_member = rq.member;
+    const Tables tb = kLdsTables ? tables_at(stbl, m) : Tables{m.knots, m.cells, m.hints, m.subs};
     const double invL01 = invL01s[rq.member];
     T* out = reinterpret_cast<T*>(rq.out);
     for (int w0 = wv * kWave; w0 < tl.count; w0 += kWaves * kWave) {
@@ -579,34 +611,41 @@ __global__ __launch_bounds__(kBatchBS) void k_batched(const BatchReq* __restrict
       const double xv = lane < tp ? rq.x[pbeg + lane] : 0.0;
       const double qv = lane < tp ? rq.q2[pbeg + lane] : 0.0;
       if (vector_cols && rq.all_cols && rq.R >= G)
-        wave_tile<T, kLdsGrid, G>(m, sknots, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp, out + pbeg * rq.R, nerr,
+        wave_tile<T, kLdsGrid, G>(m, tb, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp, out + pbeg * rq.R, nerr,
                                   invL01, rec, lane);
       else
-        wave_tile<T, kLdsGrid, 1>(m, sknots, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp, out + pbeg * rq.R, nerr,
+        wave_tile<T, kLdsGrid, 1>(m, tb, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp, out + pbeg * rq.R, nerr,
                                   invL01, rec, lane);
     }
   }
 }
 
-size_t batch_shared_bytes(int max_knots, bool f32) {
-  return (size_t)max_knots * 8 + kMaxReq * 4 +
+// Location tables are staged when the largest member's fit (always when the
+// grid is staged too).
+static bool batch_tables(bool lds, int max_tbl) { return lds || (size_t)max_tbl <= kMaxLdsTables; }
+
+size_t batch_shared_bytes(int max_tbl, bool f32, bool lds) {
+  return (batch_tables(lds, max_tbl) ? (size_t)max_tbl : 0) + kMaxReq * 4 +
          (kBatchBS / kWave) * (f32 ? wave_record_bytes<float>() : wave_record_bytes<double>());
 }
 
 // Kernel node parameters of one batched run: the counter reset and the
 // persistent kernel (used for direct launches and for building a hipGraph).
 
-BatchLaunch batch_launch_params(bool f32, bool lds, int max_knots, int64_t max_elems, int n_cu, int blocks_per_cu,
+template <typename T>
+static const void* batch_fn(bool lds, bool tables) {
+  if (lds) return reinterpret_cast<const void*>(&k_batched<T, true, true>);
+  return tables ? reinterpret_cast<const void*>(&k_batched<T, false, true>)
+                : reinterpret_cast<const void*>(&k_batched<T, false, false>);
+}
+
+BatchLaunch batch_launch_params(bool f32, bool lds, int max_tbl, int64_t max_elems, int n_cu, int blocks_per_cu,
                                 int ntiles) {
   BatchLaunch L{};
   L.reset_fn = reinterpret_cast<const void*>(&k_batch_reset);
-  L.shm = batch_shared_bytes(max_knots, f32) + (lds ? (size_t)max_elems * (f32 ? 4 : 8) : 0);
-  if (f32)
-    L.main_fn = lds ? reinterpret_cast<const void*>(&k_batched<float, true>)
-                    : reinterpret_cast<const void*>(&k_batched<float, false>);
-  else
-    L.main_fn = lds ? reinterpret_cast<const void*>(&k_batched<double, true>)
-                    : reinterpret_cast<const void*>(&k_batched<double, false>);
+  L.shm = batch_shared_bytes(max_tbl, f32, lds) + (lds ? (size_t)max_elems * (f32 ? 4 : 8) : 0);
+  const bool tables = batch_tables(lds, max_tbl);
+  L.main_fn = f32 ? batch_fn<float>(lds, tables) : batch_fn<double>(lds, tables);
   const int64_t g = min((int64_t)ntiles, (int64_t)n_cu * blocks_per_cu);
   L.grid = (unsigned)max((int64_t)1, g);
   return L;

@@ -28,8 +28,8 @@ hipError_t launch_locate(const MemberDev&, const double*, const double*, int64_t
                          int8_t*, int, hipStream_t);
 hipError_t launch_alphas(const AlphasDev&, const double*, int64_t, double*, unsigned long long*, int, hipStream_t);
 int64_t mc_partials(int64_t n);
-size_t batch_shared_bytes(int max_knots, bool f32);
-BatchLaunch batch_launch_params(bool f32, bool lds, int max_knots, int64_t max_elems, int n_cu, int blocks_per_cu,
+size_t batch_shared_bytes(int max_tbl, bool f32, bool lds);
+BatchLaunch batch_launch_params(bool f32, bool lds, int max_tbl, int64_t max_elems, int n_cu, int blocks_per_cu,
                                 int ntiles);
 hipError_t batch_prepare(const BatchLaunch& L);
 hipError_t batch_launch(const BatchLaunch& L, void** args, unsigned* counter, hipStream_t s);
@@ -66,6 +66,15 @@ int fail(int code, const char* fmt, ...) {
 int fail_hip(hipError_t e, const char* what) {
   return fail(e == hipErrorOutOfMemory ? PDF_ERR_NOMEM : PDF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace
+
+namespace pdfmi {
+// Error reporting for the library's other host sources (same thread-local message).
+int report_error(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace pdfmi
+
+namespace {
 
 struct Member {
   bool used = false;
@@ -153,6 +162,49 @@ bool strictly_increasing(const double* t, int n) {
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bucket hints of a strictly increasing table of positive knots (HintAxis):
+// the coarsest buckets (largest shift) with at most two knots strictly
+// inside any of them, provided the list stays within kMaxHintsPerAxis;
+// otherwise no list (the kernels binary search that table).
+constexpr int kMaxHintsPerAxis = 4096;
+
+uint64_t double_bits(double v) {
+  uint64_t u;
+  std::memcpy(&u, &v, 8);
+  return u;
+}
+
+HintAxis build_hints(const double* t, int n, std::vector<short>& hints) {
+  HintAxis h{-1, 0, 0, 0u};
+  if (n < 4) return h;
+  const int last = n - 2;
+  for (int shift = 52; shift >= 32; --shift) {
+    const uint64_t k0 = double_bits(t[0]) >> shift, k1 = double_bits(t[n - 1]) >> shift;
+    const uint64_t nb = k1 - k0 + 1;
+    if (nb > (uint64_t)kMaxHintsPerAxis) break;  // finer buckets only make the list longer
+    std::vector<int> inside(nb, 0);
+    const uint64_t low_mask = (1ull << shift) - 1;
+    for (int i = 0; i < n; ++i) {
+      const uint64_t u = double_bits(t[i]);
+      if (u & low_mask) ++inside[(u >> shift) - k0];  // above the bucket's smallest value
+    }
+    if (*std::max_element(inside.begin(), inside.end()) > 2) continue;
+    h.off = (int)hints.size();
+    h.n = (int)nb;
+    h.shift = shift;
+    h.key0 = (unsigned)k0;
+    for (uint64_t b = 0; b < nb; ++b) {
+      const uint64_t lo_bits = (k0 + b) << shift;
+      double lo;
+      std::memcpy(&lo, &lo_bits, 8);
+      const int i = (int)(std::upper_bound(t, t + n, lo) - t) - 1;  // largest i with t[i] <= lo
+      hints.push_back((short)std::min(std::max(i, 0), last));
+    }
+    return h;
+  }
+  return h;
+}
 
 int check_stream_args(const void* a, const void* b, int64_t n) {
   if (n < 0) return fail(PDF_ERR_ARG, "n < 0");
@@ -242,7 +294,7 @@ extern "C" int pdf_validate_grid(int32_t K, const int32_t* shape, int32_t P, con
   // the kernels address a member's padded FP64 values with 32-bit byte offsets
   int64_t padded_bytes = 0;
   for (int k = 0; k < K; ++k)
-    padded_bytes += (int64_t)std::max(shape[2 * k], 4) * std::max(shape[2 * k + 1], 4) * ((P + 1) & ~1) * 8;
+    padded_bytes += (int64_t)std::max(shape[2 * k], 4) * std::max(shape[2 * k + 1], 4) * ((P + 15) & ~15) * 8;
   if (padded_bytes > INT32_MAX) return fail(PDF_ERR_GRID, "grid values exceed 2 GiB");
   if (ko > 8192) return fail(PDF_ERR_GRID, "more than 8192 knots in total (they are staged in LDS)");
   return PDF_OK;
@@ -272,10 +324,9 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
   MemberDev& d = M.dev;
   d.K = K;
   d.P = P;
-  // host staging of knots, cells and padded values
-  std::vector<double> hk;
-  std::vector<CellCoef> hc;
-  const int P64 = (P + 1) & ~1, P32 = (P + 3) & ~3;
+  // FP64 rows are whole 64- or 128-byte lines (fewer cache lines per
+  // stencil), FP32 rows a multiple of 16 bytes
+  const int P64 = P <= 4 ? 4 : (P <= 8 ? 8 : (P + 15) & ~15), P32 = (P + 3) & ~3;
   d.P64 = P64;
   d.P32 = P32;
   int64_t n64 = 0, n32 = 0;
@@ -293,6 +344,11 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
   }
   d.elems64 = n64;
   d.elems32 = n32;
+  // location tables: knots, cells and hints per axis; sub-grids whose x knots
+  // equal sub-grid 0's share its x tables
+  std::vector<double> hk;
+  std::vector<CellCoef> hc;
+  std::vector<short> hh;
   std::vector<double> hv((size_t)n64, 0.0);
   std::vector<float> hf((size_t)n32, 0.0f);
   int64_t ko = 0, vo = 0;
@@ -300,16 +356,25 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
     SubDesc& S = d.sub[k];
     const double* xk = knots + ko;
     const double* qk = knots + ko + S.nx;
-    S.xk_off = (int)hk.size();
-    hk.insert(hk.end(), xk, xk + S.nx);
+    const SubDesc& S0 = d.sub[0];
+    if (k > 0 && S.nx == S0.nx && std::memcmp(xk, knots, sizeof(double) * S.nx) == 0) {
+      S.xk_off = S0.xk_off;
+      S.xc_off = S0.xc_off;
+      S.xh = S0.xh;
+    } else {
+      S.xk_off = (int)hk.size();
+      hk.insert(hk.end(), xk, xk + S.nx);
+      S.xc_off = (int)hc.size();
+      hc.resize(hc.size() + S.nx - 1);
+      cell_coefs(xk, S.nx, &hc[S.xc_off]);
+      S.xh = build_hints(xk, S.nx, hh);
+    }
     S.qk_off = (int)hk.size();
     hk.insert(hk.end(), qk, qk + S.nq);
-    S.xc_off = (int)hc.size();
-    hc.resize(hc.size() + S.nx - 1);
-    cell_coefs(xk, S.nx, &hc[S.xc_off]);
     S.qc_off = (int)hc.size();
     hc.resize(hc.size() + S.nq - 1);
     cell_coefs(qk, S.nq, &hc[S.qc_off]);
+    S.qh = build_hints(qk, S.nq, hh);
     S.qfirst = qk[0];
     for (int ix = 0; ix < S.nx; ++ix)
       for (int iq = 0; iq < S.nq; ++iq)
@@ -329,15 +394,21 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
   d.qmax = hk[d.sub[K - 1].qk_off + d.sub[K - 1].nq - 1];
   M.invL01 = hc[d.sub[0].qc_off].invD;
 
-  const size_t bk = align_up(hk.size() * sizeof(double), 256);
-  const size_t bc = align_up(hc.size() * sizeof(CellCoef), 256);
+  // table block: [knots][cells][hints][sub-grid descriptors], 16-byte aligned parts
+  d.cells_off = d.nknots_pad * 8;
+  d.hints_off = d.cells_off + (int)(hc.size() * sizeof(CellCoef));
+  d.subs_off = d.hints_off + (int)align_up(hh.size() * sizeof(short), 16);
+  d.tbl_bytes = d.subs_off + (int)align_up((size_t)K * sizeof(SubDesc), 16);
+  const size_t bt = align_up((size_t)d.tbl_bytes, 256);
   const size_t b64 = align_up((size_t)n64 * sizeof(double), 256);
   const size_t b32 = align_up((size_t)n32 * sizeof(float), 256);
-  std::vector<unsigned char> blob(bk + bc + b64 + b32, 0);
+  std::vector<unsigned char> blob(bt + b64 + b32, 0);
   std::memcpy(blob.data(), hk.data(), hk.size() * sizeof(double));
-  std::memcpy(blob.data() + bk, hc.data(), hc.size() * sizeof(CellCoef));
-  std::memcpy(blob.data() + bk + bc, hv.data(), (size_t)n64 * sizeof(double));
-  std::memcpy(blob.data() + bk + bc + b64, hf.data(), (size_t)n32 * sizeof(float));
+  std::memcpy(blob.data() + d.cells_off, hc.data(), hc.size() * sizeof(CellCoef));
+  if (!hh.empty()) std::memcpy(blob.data() + d.hints_off, hh.data(), hh.size() * sizeof(short));
+  std::memcpy(blob.data() + d.subs_off, d.sub, (size_t)K * sizeof(SubDesc));
+  std::memcpy(blob.data() + bt, hv.data(), (size_t)n64 * sizeof(double));
+  std::memcpy(blob.data() + bt + b64, hf.data(), (size_t)n32 * sizeof(float));
 
   hipError_t e = hipMalloc(&M.dmem, blob.size());
   if (e != hipSuccess) return fail_hip(e, "hipMalloc(grid)");
@@ -347,10 +418,13 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
     return fail_hip(e, "hipMemcpy(grid)");
   }
   unsigned char* base = static_cast<unsigned char*>(M.dmem);
+  d.tables = base;
   d.knots = reinterpret_cast<const double*>(base);
-  d.cells = reinterpret_cast<const CellCoef*>(base + bk);
-  d.v64 = reinterpret_cast<const double*>(base + bk + bc);
-  d.v32 = reinterpret_cast<const float*>(base + bk + bc + b64);
+  d.cells = reinterpret_cast<const CellCoef*>(base + d.cells_off);
+  d.hints = reinterpret_cast<const short*>(base + d.hints_off);
+  d.subs = reinterpret_cast<const SubDesc*>(base + d.subs_off);
+  d.v64 = reinterpret_cast<const double*>(base + bt);
+  d.v32 = reinterpret_cast<const float*>(base + bt + b64);
 
   for (size_t i = 0; i < g_members.size(); ++i) {
     if (!g_members[i].used) {
@@ -562,7 +636,7 @@ struct Plan {
   int vector_cols = 1;
   int use_graph = 0;
   bool lds = false;
-  int max_knots = 0;
+  int max_tbl = 0;   // bytes of the largest member's location tables
   int64_t max_elems = 0;
   std::vector<BatchReq> reqs;
   std::vector<int> cols;
@@ -580,7 +654,7 @@ struct Plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // kernel argument storage (addresses handed to hipLaunchKernel / graph nodes)
-  int a_ntiles = 0, a_max_knots = 0, a_vec = 0;
+  int a_ntiles = 0, a_max_tbl = 0, a_vec = 0;
   void* args[10];
 };
 
@@ -627,12 +701,12 @@ int plan_tiles(Plan& P) {
 }
 
 BatchLaunch plan_params(const Plan& P) {
-  return batch_launch_params(!P.out_f64, P.lds, P.max_knots, P.max_elems, g_ncu, P.blocks_per_cu, P.ntiles);
+  return batch_launch_params(!P.out_f64, P.lds, P.max_tbl, P.max_elems, g_ncu, P.blocks_per_cu, P.ntiles);
 }
 
 void plan_args(Plan& P) {
   P.a_ntiles = P.ntiles;
-  P.a_max_knots = P.max_knots;
+  P.a_max_tbl = P.max_tbl;
   P.a_vec = P.vector_cols;
   P.args[0] = &P.d_reqs;
   P.args[1] = &P.d_cols;
@@ -642,7 +716,7 @@ void plan_args(Plan& P) {
   P.args[5] = &P.d_invL01;
   P.args[6] = &P.d_counter;
   P.args[7] = &g_nerr;
-  P.args[8] = &P.a_max_knots;
+  P.args[8] = &P.a_max_tbl;
   P.args[9] = &P.a_vec;
 }
 
@@ -723,7 +797,7 @@ extern "C" int pdf_batch_create(const pdf_request* reqs, int32_t n_req, int32_t 
       slot[q.member] = (int)P.members.size();
       P.members.push_back(M->dev);
       P.invL01.push_back(M->invL01);
-      P.max_knots = std::max(P.max_knots, M->dev.nknots_pad);
+      P.max_tbl = std::max(P.max_tbl, M->dev.tbl_bytes);
       P.max_elems = std::max(P.max_elems, P.out_f64 ? M->dev.elems64 : M->dev.elems32);
     }
     BatchReq b{};
@@ -741,9 +815,8 @@ extern "C" int pdf_batch_create(const pdf_request* reqs, int32_t n_req, int32_t 
     b.n = q.n;
     P.reqs.push_back(b);
   }
-  const size_t fixed = batch_shared_bytes(P.max_knots, !P.out_f64);
-  P.lds = fixed + (size_t)P.max_elems * (P.out_f64 ? 8 : 4) <= kLdsBytes - 1024;
-  if (!P.lds && fixed > kLdsBytes - 1024) return fail(PDF_ERR_GRID, "too many knots for the batched kernel");
+  P.lds = batch_shared_bytes(P.max_tbl, !P.out_f64, true) + (size_t)P.max_elems * (P.out_f64 ? 8 : 4) <=
+          kLdsBytes - 1024;
   P.blocks_per_cu = 1;
   const size_t br = align_up(sizeof(BatchReq) * std::max<size_t>(1, P.reqs.size()), 256);
   const size_t bc = align_up(sizeof(int) * std::max<size_t>(1, P.cols.size()), 256);

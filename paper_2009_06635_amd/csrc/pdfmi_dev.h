@@ -31,27 +31,50 @@ struct CellCoef {
   double b0, b1, b2;
 };
 
+// Knot search by bucket hints: positive doubles order like their IEEE-754
+// bit patterns, so the key (bits >> shift) of a query selects a bucket of a
+// 1D knot table; the bucket's hint is the largest cell index whose knot is
+// <= the bucket's smallest value, and at most two more knots lie inside any
+// bucket.  The cell of v is then the hint advanced over the next two knots
+// that are <= v -- the same index as a binary search with the same raw FP64
+// comparisons.  A table with no hint list (off < 0) is binary searched.
+struct HintAxis {
+  int off;        // first hint in MemberDev::hints, -1 for none
+  int n;          // buckets
+  int shift;      // key = (unsigned)(bits(v) >> shift)
+  unsigned key0;  // key of the first knot
+};
+
 struct SubDesc {
   int nx, nq;        // knot counts
   int nxp, nqp;      // storage extents (>= 4; rows beyond the knots are zero)
   int xk_off, qk_off;  // knot offsets (doubles) into MemberDev::knots
   int xc_off, qc_off;  // cell offsets into MemberDev::cells
+  HintAxis xh, qh;     // knot-search hints of the two axes
   int64_t val_off64;   // element offset of values[ix][iq][c] into v64 (row stride P64)
   int64_t val_off32;   // element offset into v32 (row stride P32)
   double qfirst;       // first Q^2 knot
 };
 
+// The point-location tables of a member (knots, cell coefficients, search
+// hints, sub-grid descriptors) are one contiguous device block of tbl_bytes,
+// copied whole into LDS by the kernels when it fits there.
 struct MemberDev {
   int K;                 // sub-grids
   int P;                 // stored columns
-  int P64, P32;          // row strides of v64 / v32: P rounded up to 2 / 4 (zero padding)
+  int P64, P32;          // row strides of v64 / v32 (zero padding; FP64 rows are whole 64/128-byte lines)
   int64_t elems64, elems32;  // value elements (padded) of v64 / v32
-  int nknots;            // total knots (all sub-grids, x then Q^2 each)
-  int nknots_pad;        // nknots rounded up to an even count (16-byte LDS alignment)
+  int nknots;            // total knots (all sub-grids, x then Q^2 each; shared x tables stored once)
+  int nknots_pad;        // nknots rounded up to an even count
+  int tbl_bytes;         // bytes of the location-table block (multiple of 16)
+  int cells_off, hints_off, subs_off;  // byte offsets of cells, hints and sub-grid descriptors in it
   double xmin, xmax;     // x range (shared by all sub-grids)
   double qmin, qmax;     // Q^2 range (first knot of sub-grid 0, last of K-1)
-  const double* knots;   // device
-  const CellCoef* cells; // device
+  const unsigned char* tables;  // device, the location-table block
+  const double* knots;   // device, = tables
+  const CellCoef* cells; // device, = tables + cells_off
+  const short* hints;    // device, = tables + hints_off
+  const SubDesc* subs;   // device, = tables + subs_off
   const double* v64;     // device, FP64 values
   const float* v32;      // device, FP32-rounded values
   SubDesc sub[kMaxSub];

@@ -337,7 +337,7 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
       fm &= fm - 1;
       const double xp = __shfl(xr, pt), qp = __shfl(qr, pt);
       if (l < S.P) {
-        const float v2 = interp_point<float>(m, m.knots, xp, qp, l, invL01);
+        const float v2 = interp_point<float>(m, Tables{m.knots, m.cells, m.hints, m.subs}, xp, qp, l, invL01);
         out[(p0 + pt) * S.P + l] = v2;
       }
       if (l == 0 && !((xp > 0.0) && (xp <= m.xmax) && (qp > 0.0) && (qp < INFINITY))) atomicAdd(nerr, 1ull);

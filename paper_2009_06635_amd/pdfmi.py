@@ -55,6 +55,10 @@ _SIGS = {
     "pdf_surrogate_save": [_i32, ctypes.c_char_p],
     "pdf_surrogate_load": [_i32, ctypes.c_char_p],
     "pdf_shutdown": [],
+    "pdf_lhapdf_read": [ctypes.c_char_p, _P, _P, _P, _P, _P],
+    "pdf_load_lhapdf": [ctypes.c_char_p, _P],
+    "pdf_lhapdf_read_alphas": [ctypes.c_char_p, _P, _P, _P],
+    "pdf_load_lhapdf_alphas": [ctypes.c_char_p],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -135,6 +139,52 @@ def unload(member):
 def load_alphas(q2knots, alphas):
     k, a = _np(q2knots, np.float64), _np(alphas, np.float64)
     _check(_lib.pdf_load_alphas(len(k), _ptr(k), _ptr(a)))
+
+
+def read_lhapdf(path):
+    """Parse an LHAPDF6 member file (lhagrid1) on the host: returns
+    (xknots, q2knots, values, pids) per sub-grid, Q knots squared."""
+    sizes = np.zeros(4, np.int64)
+    bpath = str(path).encode()
+    _check(_lib.pdf_lhapdf_read(bpath, _ptr(sizes), None, None, None, None))
+    K, P, nk, nv = (int(v) for v in sizes)
+    shape = np.zeros(2 * K, np.int32)
+    pids = np.zeros(P, np.int32)
+    knots = np.zeros(nk, np.float64)
+    vals = np.zeros(nv, np.float64)
+    _check(_lib.pdf_lhapdf_read(bpath, _ptr(sizes), _ptr(shape), _ptr(pids), _ptr(knots), _ptr(vals)))
+    xk, qk, vs = [], [], []
+    ko = vo = 0
+    for k in range(K):
+        nx, nq = int(shape[2 * k]), int(shape[2 * k + 1])
+        xk.append(knots[ko:ko + nx].copy())
+        qk.append(knots[ko + nx:ko + nx + nq].copy())
+        vs.append(vals[vo:vo + nx * nq * P].reshape(nx, nq, P).copy())
+        ko += nx + nq
+        vo += nx * nq * P
+    return xk, qk, vs, pids.tolist()
+
+
+def load_lhapdf(path):
+    """Read an LHAPDF6 member file and load it; returns the member id."""
+    mid = ctypes.c_int32(-1)
+    _check(_lib.pdf_load_lhapdf(str(path).encode(), ctypes.byref(mid)))
+    return mid.value
+
+
+def read_lhapdf_alphas(info_path):
+    """(Q^2 knots, alpha_s values) of a set's .info file."""
+    n = ctypes.c_int32(0)
+    bpath = str(info_path).encode()
+    _check(_lib.pdf_lhapdf_read_alphas(bpath, ctypes.byref(n), None, None))
+    q2 = np.zeros(n.value, np.float64)
+    a = np.zeros(n.value, np.float64)
+    _check(_lib.pdf_lhapdf_read_alphas(bpath, ctypes.byref(n), _ptr(q2), _ptr(a)))
+    return q2, a
+
+
+def load_lhapdf_alphas(info_path):
+    _check(_lib.pdf_load_lhapdf_alphas(str(info_path).encode()))
 
 
 def _stream(stream):
