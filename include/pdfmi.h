@@ -320,6 +320,40 @@ int pdf_lhapdf_read_alphas(const char* info_path, int32_t* n_out, double* q2_kno
                            double* alphas);
 int pdf_load_lhapdf_alphas(const char* info_path);
 
+/*
+ * Fused Monte-Carlo chunk sum (section 4.1 integrand load, one kernel): for
+ * points (x1[i], x2[i], q2[i]) of a member and the loaded alpha_s table,
+ *   S = sum_i alpha_s(q2[i]) * sum_j xf(x1[i], q2[i])_j * xf(x2[i], q2[i])_j
+ * over the requested flavours (pids as in pdf_xfxq2; NULL = all stored),
+ * without writing the PDF values: the result is bit-identical to pdf_xfxq2
+ * (x1), pdf_xfxq2 (x2), pdf_alphas_q2 and pdf_mc_chunk_sum on the same
+ * inputs (same per-value arithmetic, same summation order).  The _f32 form
+ * matches pdf_xfxq2_f32 + pdf_mc_chunk_sum_f32.  x1, x2, q2: device [n];
+ * workspace: device, pdf_mc_workspace_bytes(n); sum_out: device double.
+ * Invalid points count in the error counter as in the unfused calls.
+ * Errors: PDF_ERR_ARG, PDF_ERR_MEMBER, PDF_ERR_PID, PDF_ERR_STATE (no
+ * alpha_s table), PDF_ERR_GRID (location tables beyond LDS), PDF_ERR_DEVICE.
+ * Asynchronous on stream.
+ */
+int pdf_mc_fused(int32_t member, const int32_t* pids, int32_t n_pids,
+                 const double* x1, const double* x2, const double* q2, int64_t n,
+                 double* workspace, double* sum_out, pdf_stream_t stream);
+int pdf_mc_fused_f32(int32_t member, const int32_t* pids, int32_t n_pids,
+                     const double* x1, const double* x2, const double* q2, int64_t n,
+                     double* workspace, double* sum_out, pdf_stream_t stream);
+
+/*
+ * FastKernel-style contraction of PDF members (section 4.3: predictions are
+ * convolutions of FK tables with PDFs on an x grid, for many members at once):
+ *   out[r][d] = sum_k pdf[r][k] * fk[d][k]      (FP64, fixed summation order)
+ * pdf: device [nrep][K] (member r's values flattened, e.g. [x point][flavour]
+ * as pdf_xfxq2 writes them), fk: device [ndat][K] in the same k order, out:
+ * device [nrep][ndat].  K = 0 gives zeros.  Errors: PDF_ERR_ARG (negative
+ * sizes, nrep > 2^22, null pointers), PDF_ERR_DEVICE.  Asynchronous on stream.
+ */
+int pdf_fk_contract(const double* pdf, const double* fk, int32_t nrep, int32_t ndat, int64_t K,
+                    double* out, pdf_stream_t stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* pdf_last_error(void);
 

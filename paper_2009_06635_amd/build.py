@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdfmi.so")
-SOURCES = ["kernels.hip", "surrogate.hip", "pdfmi.cpp", "lhapdf_io.cpp"]
+SOURCES = ["kernels.hip", "surrogate.hip", "fk.hip", "pdfmi.cpp", "lhapdf_io.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,95 @@
+// FastKernel-style contraction of PDF members with a kernel table (paper
+// section 4.3: theory predictions are convolutions of FK tables with PDFs
+// evaluated on an x grid; the multi-member form evaluates many replicas at
+// once):
+//   T[r][d] = sum_k F[r][k] * FK[d][k],   k = (x point i, flavour a) flattened,
+// a dense FP64 contraction of the replica matrix F [nrep][K] with the table
+// [ndat][K], on the FP64 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// Tiling: a workgroup of 4 waves computes a 64 x 64 tile of T; each wave a
+// 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16.  K is walked in steps of 32
+// staged in LDS (rows padded to 33 doubles so that the 16 rows read by one
+// MFMA operand fall in different banks), with the next step's global loads
+// issued before the current step's MFMAs.  Out-of-range rows and k read as
+// zero; the summation order over k is fixed (deterministic results).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdfmi {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kFkBM = 64, kFkBN = 64, kFkBK = 32, kFkLd = kFkBK + 1, kFkThreads = 256;
+
+__global__ __launch_bounds__(kFkThreads) void k_fk_contract(const double* __restrict__ F, const double* __restrict__ FK,
+                                                            int nrep, int ndat, int64_t K, double* __restrict__ T) {
+  __shared__ double sa[kFkBM * kFkLd];
+  __shared__ double sb[kFkBN * kFkLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // wave quarter of the 64 x 64 tile
+  const int m0 = blockIdx.y * kFkBM, n0 = blockIdx.x * kFkBN;
+  // cooperative loads: thread -> (row, 8 consecutive k) of each 64 x 32 tile
+  const int lrow = tid >> 2, lk = (tid & 3) * 8;
+  const bool arow_ok = m0 + lrow < nrep, brow_ok = n0 + lrow < ndat;
+  const double* ap = F + (int64_t)(m0 + lrow) * K;
+  const double* bp = FK + (int64_t)(n0 + lrow) * K;
+  double ra[8], rb[8];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t k = k0 + lk + i;
+      ra[i] = (arow_ok && k < K) ? ap[k] : 0.0;
+      rb[i] = (brow_ok && k < K) ? bp[k] : 0.0;
+    }
+  };
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int r16 = lane & 15, kq = lane >> 4;
+  fetch(0);
+  for (int64_t k0 = 0; k0 < K; k0 += kFkBK) {
+    __syncthreads();  // previous step's operands consumed
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      sa[lrow * kFkLd + lk + i] = ra[i];
+      sb[lrow * kFkLd + lk + i] = rb[i];
+    }
+    __syncthreads();
+    if (k0 + kFkBK < K) fetch(k0 + kFkBK);
+#pragma unroll
+    for (int kk = 0; kk < kFkBK; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = sa[(wm * 32 + t * 16 + r16) * kFkLd + kk + kq];  // A operand: row r16, k = kq
+        b[t] = sb[(wn * 32 + t * 16 + r16) * kFkLd + kk + kq];  // B operand: column r16, k = kq
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // accumulator layout: lane holds rows 4 (lane / 16) + v, column lane % 16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm * 32 + i * 16 + 4 * kq + v;
+        const int n = n0 + wn * 32 + j * 16 + r16;
+        if (m < nrep && n < ndat) T[(int64_t)m * ndat + n] = acc[i][j][v];
+      }
+}
+
+hipError_t launch_fk_contract(const double* F, const double* FK, int nrep, int ndat, int64_t K, double* T,
+                              hipStream_t s) {
+  const dim3 grid((unsigned)((ndat + kFkBN - 1) / kFkBN), (unsigned)((nrep + kFkBM - 1) / kFkBM));
+  hipLaunchKernelGGL(k_fk_contract, grid, dim3(kFkThreads), 0, s, F, FK, nrep, ndat, K, T);
+  return hipGetLastError();
+}
+
+}  // namespace pdfmi

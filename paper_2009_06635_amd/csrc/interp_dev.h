@@ -78,6 +78,7 @@ __device__ __forceinline__ double cell_u(double v, const CellCoef& c) {
 struct PointLoc {
   int mode;      // region bits | kXHigh | (anchor row << 8) for high Q^2
   int k, ix, iq;
+  int sx, sq;    // stencil origin (first x and Q^2 knot of the 4x4 stencil)
   int base;      // element offset of f[sx][sq][0]
   int sa;        // element stride between x knots
   double p0, p1; // extrapolation parameters
@@ -94,6 +95,7 @@ __device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const Table
   if (!valid) {
     L.mode = kInvalid;
     L.k = L.ix = L.iq = -1;
+    L.sx = L.sq = 0;
     L.base = 0;
     L.sa = 0;
     for (int a = 0; a < 4; ++a) w[a] = v[a] = (T)0;
@@ -137,6 +139,8 @@ __device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const Table
   L.k = k;
   L.ix = ix;
   L.iq = iq;
+  L.sx = sx;
+  L.sq = sq;
   const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
   L.sa = S.nqp * Pp;
   L.base = (int)((sizeof(T) == 8 ? S.val_off64 : S.val_off32) + (int64_t)(sx * S.nqp + sq) * Pp);

@@ -336,6 +336,30 @@ __global__ __launch_bounds__(256) void k_locate(MemberDev m, const double* __res
 // (knots, values, cell coefficients) is staged in LDS once per workgroup.
 constexpr int kAlphasMaxKnots = 256;
 
+// alpha_s at one Q^2 from the table (knots sk, values sv, cells sc); NaN for
+// Q^2 <= 0 or non-finite.
+__device__ __forceinline__ double alphas_point(const AlphasDev& A, const double* sk, const double* sv,
+                                               const CellCoef* sc, double q2) {
+  const bool valid = q2 > 0.0 && q2 < INFINITY;
+  if (!valid) return NAN;
+  if (q2 < sk[0]) return sv[0];
+  if (q2 > sk[A.n - 1]) return sv[A.n - 1];
+  int s = 0;
+  for (int j = 1; j < A.nseg; ++j)
+    if (A.seg_first[j] <= q2) s = j;
+  const int lo = A.seg_lo[s], hi = A.seg_hi[s];
+  const int m = hi - lo + 1;
+  const int c = lo + find_cell(sk + lo, m, q2);
+  const CellCoef cc = sc[c];
+  const int m4 = m < 4 ? m : 4;
+  const int st = min(max(c - 1, lo), hi - m4 + 1);
+  double w[4];
+  stencil_weights<double>(cell_u(q2, cc), cc, c - st, w);
+  double acc = w[0] * sv[st];
+  for (int a = 1; a < m4; ++a) acc = fma(w[a], sv[st + a], acc);
+  return acc;
+}
+
 __global__ __launch_bounds__(256) void k_alphas(AlphasDev A, const double* __restrict__ Q2, int64_t n,
                                                 double* __restrict__ out, unsigned long long* __restrict__ nerr) {
   __shared__ double sk[kAlphasMaxKnots];
@@ -347,33 +371,10 @@ __global__ __launch_bounds__(256) void k_alphas(AlphasDev A, const double* __res
     sc[i] = A.cells[i];
   }
   __syncthreads();
-  const double qlo = sk[0], qhi = sk[A.n - 1], alo = sv[0], ahi = sv[A.n - 1];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double q2 = Q2[i];
     const bool valid = q2 > 0.0 && q2 < INFINITY;
-    double r;
-    if (!valid) {
-      r = NAN;
-    } else if (q2 < qlo) {
-      r = alo;
-    } else if (q2 > qhi) {
-      r = ahi;
-    } else {
-      int s = 0;
-      for (int j = 1; j < A.nseg; ++j)
-        if (A.seg_first[j] <= q2) s = j;
-      const int lo = A.seg_lo[s], hi = A.seg_hi[s];
-      const int m = hi - lo + 1;
-      const int c = lo + find_cell(sk + lo, m, q2);
-      const CellCoef cc = sc[c];
-      const int m4 = m < 4 ? m : 4;
-      const int st = min(max(c - 1, lo), hi - m4 + 1);
-      double w[4];
-      stencil_weights<double>(cell_u(q2, cc), cc, c - st, w);
-      double acc = w[0] * sv[st];
-      for (int a = 1; a < m4; ++a) acc = fma(w[a], sv[st + a], acc);
-      r = acc;
-    }
+    const double r = alphas_point(A, sk, sv, sc, q2);
     const unsigned long long bal = __ballot(!valid);
     if (bal && (threadIdx.x & 63) == 0) atomicAdd(nerr, (unsigned long long)__popcll(bal));
     out[i] = r;
@@ -536,6 +537,208 @@ hipError_t launch_mc_sum(const T* xf1, const T* xf2, int P, const double* as, in
   hipLaunchKernelGGL(k_mc_final, dim3(1), dim3(kMcThreads), 0, s, partial, np, sum_out);
   return hipGetLastError();
 }
+// Fused Monte-Carlo chunk sum: the same S as xfxq2(x1) + xfxq2(x2) +
+// alpha_s + the chunk sum above, without writing the PDF values out (24 bytes
+// of input per point instead of 24 + 2 R sizeof(T) out and back in).  Each
+// 256-thread quarter of a workgroup takes one kMcBlock-point block of the
+// chunk, each thread its points beg + t + 256 k in increasing k: one lane per
+// point locates x1 and x2, evaluates every requested flavour of both with the
+// same device functions as k_xfxq2, forms sum_j xf1_j xf2_j in flavour order
+// and accumulates alpha_s times it -- the summation order of k_mc_partial, so
+// both paths give bit-identical sums.  The grid is staged in LDS with row
+// stride P when it fits (kLdsGrid), else read from global memory.
+constexpr int kMcFusedBS = 4 * kMcThreads;
+
+// One flavour of one located point, the value k_xfxq2 writes for it: NaN for
+// an invalid point, 0 for a flavour absent from the grid, the stencil sum
+// inside the grid, the extrapolation formula outside.  g points at the
+// stencil origin's entry of the flavour's column; sa, P are the x and Q^2
+// strides of the values read.
+template <typename T, bool kMaySlow>
+__device__ __forceinline__ T mc_value(const T* g, const PointLoc& L, const T w[4], const T v[4], int sa, int P,
+                                      int col, double invL01) {
+  if (L.mode & kInvalid) return (T)NAN;
+  if (col < 0) return (T)0;
+  if (!kMaySlow || !(L.mode & (kLowX | kLowQ | kHighQ))) {
+    T F[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) F[a][b] = g[a * sa + b * P];
+    return interp_stencil<T>(F, w, v);
+  }
+  const Wts wt{(double)w[0], (double)w[1], (double)w[2], (double)w[3],
+               (double)v[0], (double)v[1], (double)v[2], (double)v[3]};
+  return (T)extrap_entry<T>(g, sa, P, L.mode, wt, L.p0, L.p1, invL01);
+}
+
+// Location of a point in the values read by k_mc_fused: element offset of
+// the stencil origin and stride between x knots (Q^2 stride P).
+__device__ __forceinline__ void mc_origin(const Tables& tb, const int* soff, const PointLoc& L, int P, int& base,
+                                          int& sa) {
+  const int k = max(L.k, 0);
+  const int nqp = tb.subs[k].nqp;
+  sa = nqp * P;
+  base = soff[k] + (L.sx * nqp + L.sq) * P;
+}
+
+template <typename T, bool kLdsGrid>
+__global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc, AlphasDev A,
+                                                         const double* __restrict__ X1,
+                                                         const double* __restrict__ X2,
+                                                         const double* __restrict__ Q2, int64_t n,
+                                                         double* __restrict__ partial,
+                                                         unsigned long long* __restrict__ nerr, double invL01) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int an2 = (A.n + 1) & ~1;
+  unsigned char* stbl = smem;
+  double* ask = reinterpret_cast<double*>(smem + m.tbl_bytes);
+  double* asv = ask + an2;
+  CellCoef* asc = reinterpret_cast<CellCoef*>(asv + an2);
+  double* tree = reinterpret_cast<double*>(asc + an2);  // [4][256]
+  int* scol = reinterpret_cast<int*>(tree + kMcFusedBS);  // [kMaxReq]
+  int* soff = scol + kMaxReq;                             // [kMaxSub] staged sub-grid offsets
+  T* sgrid = reinterpret_cast<T*>(soff + kMaxSub);        // 16-byte aligned: kMaxReq + kMaxSub ints
+
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(m.tables);
+    for (int i = threadIdx.x; i < m.tbl_bytes / 16; i += kMcFusedBS) reinterpret_cast<uint4*>(stbl)[i] = src[i];
+  }
+  for (int i = threadIdx.x; i < A.n; i += kMcFusedBS) {
+    ask[i] = A.knots[i];
+    asv[i] = A.vals[i];
+    asc[i] = A.cells[i];
+  }
+  for (int i = threadIdx.x; i < rc.n; i += kMcFusedBS) scol[i] = rc.col[i];
+  const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
+  const T* __restrict__ gvals = member_values<T>(m);
+  const int P = kLdsGrid ? m.P : Pp;  // row stride of the values read below
+  if (threadIdx.x == 0) {
+    int off = 0;
+    for (int k = 0; k < m.K; ++k) {
+      soff[k] = kLdsGrid ? off : (int)(sizeof(T) == 8 ? m.sub[k].val_off64 : m.sub[k].val_off32);
+      off += m.sub[k].nxp * m.sub[k].nqp * m.P;
+    }
+  }
+  if constexpr (kLdsGrid) {
+    int off = 0;
+    for (int k = 0; k < m.K; ++k) {
+      const SubDesc& S = m.sub[k];
+      const int rows = S.nxp * S.nqp;
+      const T* src = gvals + (sizeof(T) == 8 ? S.val_off64 : S.val_off32);
+      for (int e = threadIdx.x; e < rows * m.P; e += kMcFusedBS) {
+        const int r = e / m.P, c = e - r * m.P;
+        sgrid[off + e] = src[(int64_t)r * Pp + c];
+      }
+      off += rows * m.P;
+    }
+  }
+  __syncthreads();
+  const Tables tb = tables_at(stbl, m);
+  const T* grid = kLdsGrid ? sgrid : gvals;
+
+  const int q = threadIdx.x / kMcThreads, t = threadIdx.x % kMcThreads;
+  const int R = rc.n;
+  const int64_t nmb = (n + kMcBlock - 1) / kMcBlock;
+  for (int64_t mb0 = (int64_t)blockIdx.x * 4; mb0 < nmb; mb0 += (int64_t)gridDim.x * 4) {
+    const int64_t mb = mb0 + q;
+    const int64_t beg = mb * kMcBlock, end = min(beg + (int64_t)kMcBlock, n);
+    double acc = 0.0;
+    for (int k = 0; k < kMcBlock / kMcThreads; ++k) {
+      const int64_t i = beg + t + (int64_t)kMcThreads * k;
+      const bool live = mb < nmb && i < end;
+      double x1 = 0.5, x2 = 0.5, q2 = 10.0;
+      if (live) {
+        x1 = X1[i];
+        x2 = X2[i];
+        q2 = Q2[i];
+      }
+      T w1[4], v1[4], w2[4], v2[4];
+      const PointLoc L1 = locate_point<T>(m, tb, x1, q2, w1, v1);
+      const PointLoc L2 = locate_point<T>(m, tb, x2, q2, w2, v2);
+      const double as = alphas_point(A, ask, asv, asc, q2);
+      const bool bad1 = live && (L1.mode & kInvalid), bad2 = live && (L2.mode & kInvalid);
+      const bool bada = live && !(q2 > 0.0 && q2 < INFINITY);
+      const unsigned long long nb = __popcll(__ballot(bad1)) + __popcll(__ballot(bad2)) + __popcll(__ballot(bada));
+      if (nb && (threadIdx.x & 63) == 0) atomicAdd(nerr, nb);
+      int b1, sa1, b2, sa2;
+      mc_origin(tb, soff, L1, P, b1, sa1);
+      mc_origin(tb, soff, L2, P, b2, sa2);
+      double lum = 0.0;
+      if (!((L1.mode | L2.mode) & (kLowX | kLowQ | kHighQ))) {
+        for (int j = 0; j < R; ++j) {
+          const int col = scol[j];
+          const T f1 = mc_value<T, false>(grid + b1 + col, L1, w1, v1, sa1, P, col, invL01);
+          const T f2 = mc_value<T, false>(grid + b2 + col, L2, w2, v2, sa2, P, col, invL01);
+          lum = fma((double)f1, (double)f2, lum);
+        }
+      } else {
+        // at least one side extrapolated (rare): the same loop with the
+        // extrapolation formulas
+        for (int j = 0; j < R; ++j) {
+          const int col = scol[j];
+          const T f1 = mc_value<T, true>(grid + b1 + col, L1, w1, v1, sa1, P, col, invL01);
+          const T f2 = mc_value<T, true>(grid + b2 + col, L2, w2, v2, sa2, P, col, invL01);
+          lum = fma((double)f1, (double)f2, lum);
+        }
+      }
+      if (live) acc = fma(as, lum, acc);
+    }
+    // the tree of block_tree_sum, per quarter
+    double* sh = tree + q * kMcThreads;
+    sh[t] = acc;
+    __syncthreads();
+    for (int st = kMcThreads / 2; st > 0; st >>= 1) {
+      if (t < st) sh[t] += sh[t + st];
+      __syncthreads();
+    }
+    if (t == 0 && mb < nmb) partial[mb] = sh[0];
+    __syncthreads();
+  }
+}
+
+// LDS bytes of k_mc_fused (grid_elems > 0: the grid staged with row stride P).
+size_t mc_fused_shared_bytes(const MemberDev& m, const AlphasDev& A, int64_t grid_elems, bool f32) {
+  const size_t an2 = (size_t)((A.n + 1) & ~1);
+  return (size_t)m.tbl_bytes + an2 * (8 + 8 + sizeof(CellCoef)) + kMcFusedBS * 8 + (kMaxReq + kMaxSub) * 4 +
+         (size_t)grid_elems * (f32 ? 4 : 8);
+}
+
+template <typename T>
+hipError_t launch_mc_fused(const MemberDev& m, const ReqCols& rc, const AlphasDev& A, const double* x1,
+                           const double* x2, const double* q2, int64_t n, double* partial, double* sum_out,
+                           unsigned long long* nerr, double invL01, int n_cu, hipStream_t s) {
+  const int64_t np = mc_partials(n);
+  if (np > 0) {
+    int64_t elems = 0;
+    for (int k = 0; k < m.K; ++k) elems += (int64_t)m.sub[k].nxp * m.sub[k].nqp * m.P;
+    const bool f32 = sizeof(T) == 4;
+    const size_t lds_all = mc_fused_shared_bytes(m, A, elems, f32);
+    const bool lds = lds_all <= 160 * 1024;
+    const size_t shm = lds ? lds_all : mc_fused_shared_bytes(m, A, 0, f32);
+    const void* fn = lds ? reinterpret_cast<const void*>(&k_mc_fused<T, true>)
+                         : reinterpret_cast<const void*>(&k_mc_fused<T, false>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    const int per_cu = max(1, (int)(160 * 1024 / shm));
+    const int64_t nb = min((np + 3) / 4, (int64_t)n_cu * per_cu);
+    if (lds)
+      hipLaunchKernelGGL((k_mc_fused<T, true>), dim3((unsigned)nb), dim3(kMcFusedBS), shm, s, m, rc, A, x1, x2, q2, n,
+                         partial, nerr, invL01);
+    else
+      hipLaunchKernelGGL((k_mc_fused<T, false>), dim3((unsigned)nb), dim3(kMcFusedBS), shm, s, m, rc, A, x1, x2, q2,
+                         n, partial, nerr, invL01);
+  }
+  hipLaunchKernelGGL(k_mc_final, dim3(1), dim3(kMcThreads), 0, s, partial, np, sum_out);
+  return hipGetLastError();
+}
+template hipError_t launch_mc_fused<double>(const MemberDev&, const ReqCols&, const AlphasDev&, const double*,
+                                            const double*, const double*, int64_t, double*, double*,
+                                            unsigned long long*, double, int, hipStream_t);
+template hipError_t launch_mc_fused<float>(const MemberDev&, const ReqCols&, const AlphasDev&, const double*,
+                                           const double*, const double*, int64_t, double*, double*,
+                                           unsigned long long*, double, int, hipStream_t);
+
 template hipError_t launch_mc_sum<double>(const double*, const double*, int, const double*, int64_t, double*, double*,
                                           hipStream_t);
 template hipError_t launch_mc_sum<float>(const float*, const float*, int, const double*, int64_t, double*, double*,

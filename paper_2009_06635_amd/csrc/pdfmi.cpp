@@ -45,6 +45,12 @@ hipError_t sur_infer(const SurDev& S, const MemberDev& m, const SurBufs& b, cons
                      int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu, hipStream_t s);
 template <typename T>
 hipError_t launch_mc_sum(const T*, const T*, int, const double*, int64_t, double*, double*, hipStream_t);
+template <typename T>
+hipError_t launch_mc_fused(const MemberDev&, const ReqCols&, const AlphasDev&, const double*, const double*,
+                           const double*, int64_t, double*, double*, unsigned long long*, double, int, hipStream_t);
+size_t mc_fused_shared_bytes(const MemberDev& m, const AlphasDev& A, int64_t grid_elems, bool f32);
+hipError_t launch_fk_contract(const double* F, const double* FK, int nrep, int ndat, int64_t K, double* T,
+                              hipStream_t s);
 }  // namespace pdfmi
 
 using namespace pdfmi;
@@ -1366,6 +1372,53 @@ extern "C" int pdf_mc_chunk_sum(const double* xf1, const double* xf2, int32_t n_
 extern "C" int pdf_mc_chunk_sum_f32(const float* xf1, const float* xf2, int32_t n_pids, const double* alphas,
                                     int64_t n, double* workspace, double* sum_out, pdf_stream_t stream) {
   return mc_sum_impl<float>(xf1, xf2, n_pids, alphas, n, workspace, sum_out, stream);
+}
+
+template <typename T>
+static int mc_fused_impl(int32_t member, const int32_t* pids, int32_t n_pids, const double* x1, const double* x2,
+                         const double* q2, int64_t n, double* workspace, double* sum_out, pdf_stream_t stream) {
+  if (n < 0) return fail(PDF_ERR_ARG, "n < 0");
+  if (!sum_out || !workspace) return fail(PDF_ERR_ARG, "null output or workspace");
+  if (n > 0 && (!x1 || !x2 || !q2)) return fail(PDF_ERR_ARG, "null input");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int rc = ensure_init();
+  if (rc != PDF_OK) return rc;
+  Member* M = get_member(member);
+  if (!M) return fail(PDF_ERR_MEMBER, "unknown member %d", member);
+  if (!g_has_alphas) return fail(PDF_ERR_STATE, "no alpha_s table loaded");
+  ReqCols rcols{};
+  if ((rc = build_req(*M, pids, n_pids, rcols)) != PDF_OK) return rc;
+  if (mc_fused_shared_bytes(M->dev, g_alphas, 0, sizeof(T) == 4) > kLdsBytes)
+    return fail(PDF_ERR_GRID, "location tables too large for the fused kernel; use pdf_xfxq2 + pdf_mc_chunk_sum");
+  hipError_t e = launch_mc_fused<T>(M->dev, rcols, g_alphas, x1, x2, q2, n, workspace, sum_out, g_nerr, M->invL01,
+                                    g_ncu, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "launch fused mc sum");
+  return PDF_OK;
+}
+
+extern "C" int pdf_mc_fused(int32_t member, const int32_t* pids, int32_t n_pids, const double* x1, const double* x2,
+                            const double* q2, int64_t n, double* workspace, double* sum_out, pdf_stream_t stream) {
+  return mc_fused_impl<double>(member, pids, n_pids, x1, x2, q2, n, workspace, sum_out, stream);
+}
+
+extern "C" int pdf_mc_fused_f32(int32_t member, const int32_t* pids, int32_t n_pids, const double* x1,
+                                const double* x2, const double* q2, int64_t n, double* workspace, double* sum_out,
+                                pdf_stream_t stream) {
+  return mc_fused_impl<float>(member, pids, n_pids, x1, x2, q2, n, workspace, sum_out, stream);
+}
+
+extern "C" int pdf_fk_contract(const double* pdf, const double* fk, int32_t nrep, int32_t ndat, int64_t K,
+                               double* out, pdf_stream_t stream) {
+  if (nrep < 0 || ndat < 0 || K < 0) return fail(PDF_ERR_ARG, "negative size");
+  if (nrep > (1 << 22)) return fail(PDF_ERR_ARG, "nrep above 4194304");
+  if (nrep > 0 && ndat > 0 && (!out || (K > 0 && (!pdf || !fk)))) return fail(PDF_ERR_ARG, "null device pointer");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int rc = ensure_init();
+  if (rc != PDF_OK) return rc;
+  if (nrep == 0 || ndat == 0) return PDF_OK;
+  hipError_t e = launch_fk_contract(pdf, fk, nrep, ndat, K, out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "launch fk contraction");
+  return PDF_OK;
 }
 
 extern "C" int pdf_set_lds_policy(int32_t policy) {

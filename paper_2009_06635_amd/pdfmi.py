@@ -55,6 +55,9 @@ _SIGS = {
     "pdf_surrogate_save": [_i32, ctypes.c_char_p],
     "pdf_surrogate_load": [_i32, ctypes.c_char_p],
     "pdf_shutdown": [],
+    "pdf_mc_fused": [_i32, _P, _i32, _P, _P, _P, _i64, _P, _P, _P],
+    "pdf_mc_fused_f32": [_i32, _P, _i32, _P, _P, _P, _i64, _P, _P, _P],
+    "pdf_fk_contract": [_P, _P, _i32, _i32, _i64, _P, _P],
     "pdf_lhapdf_read": [ctypes.c_char_p, _P, _P, _P, _P, _P],
     "pdf_load_lhapdf": [ctypes.c_char_p, _P],
     "pdf_lhapdf_read_alphas": [ctypes.c_char_p, _P, _P, _P],
@@ -286,6 +289,45 @@ def mc_chunk_sum(xf1, xf2, alphas, workspace=None, out=None, stream=None):
     fn = _lib.pdf_mc_chunk_sum_f32 if f32 else _lib.pdf_mc_chunk_sum
     _check(fn(_P(xf1.data_ptr()), _P(xf2.data_ptr()), P, _P(alphas.data_ptr()), n, _P(workspace.data_ptr()),
               _P(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def mc_fused(member, pids, x1, x2, q2, f32=False, workspace=None, out=None, stream=None):
+    """The chunk sum of mc_chunk_sum(xfxq2(x1), xfxq2(x2), alphas_q2(q2)) in
+    one kernel without materialising the PDF values (bit-identical result);
+    f32 evaluates the PDFs as xfxq2_f32 does.  Returns a one-element device
+    tensor."""
+    for t, nm in ((x1, "x1"), (x2, "x2"), (q2, "q2")):
+        _dev_f64(t, nm)
+    n = x1.shape[0]
+    if x2.shape[0] != n or q2.shape[0] != n:
+        raise ValueError("x1, x2, q2 must have the same length")
+    arr, npid = _pid_arg(pids)
+    if workspace is None:
+        workspace = mc_workspace(n, x1.device)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x1.device)
+    fn = _lib.pdf_mc_fused_f32 if f32 else _lib.pdf_mc_fused
+    _check(fn(int(member), _ptr(arr) if arr is not None else None, npid, _P(x1.data_ptr()), _P(x2.data_ptr()),
+              _P(q2.data_ptr()), n, _P(workspace.data_ptr()), _P(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def fk_contract(pdf, fk, out=None, stream=None):
+    """out[r][d] = sum_k pdf[r][k] fk[d][k] (FP64 matrix cores); pdf [nrep][K]
+    and fk [ndat][K] contiguous float64 CUDA tensors (2-D, or more dimensions
+    flattened after the first)."""
+    for t, nm in ((pdf, "pdf"), (fk, "fk")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise TypeError("%s must be a contiguous float64 CUDA tensor" % nm)
+    nrep, ndat = pdf.shape[0], fk.shape[0]
+    K = pdf[0].numel() if nrep else (fk[0].numel() if ndat else 0)
+    if (nrep and pdf[0].numel() != K) or (ndat and fk[0].numel() != K):
+        raise ValueError("pdf and fk rows differ in length")
+    if out is None:
+        out = torch.empty((nrep, ndat), dtype=torch.float64, device=pdf.device)
+    _check(_lib.pdf_fk_contract(_P(pdf.data_ptr()), _P(fk.data_ptr()), nrep, ndat, K, _P(out.data_ptr()),
+                                _stream(stream)))
     return out
 
 

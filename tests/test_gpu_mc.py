@@ -76,3 +76,84 @@ def test_mc_full_chunk_sampled():
         assert abs(s - so) <= 1e-11 * sabs, (s, so)
     finally:
         pdfmi.unload(m)
+
+
+def _mixed_chunk(n, seed):
+    """config-5 points with a share moved outside the grid in x and Q^2 (all
+    extrapolation regions) and a few invalid points."""
+    x1, x2, q2 = synth.config5_chunk(1, n=n)
+    x1, x2, q2 = x1.copy(), x2.copy(), q2.copy()
+    rng = np.random.default_rng(seed)
+    k = max(1, n // 20)
+    idx = rng.choice(n, size=min(n, 4 * k), replace=False)
+    a, b, c, d = np.array_split(idx, 4)
+    x1[a] = np.exp(rng.uniform(np.log(1e-8), np.log(1e-6), len(a)))   # below x_min
+    q2[b] = np.exp(rng.uniform(np.log(0.5), np.log(2.0), len(b)))     # below Q^2_min
+    q2[c] = np.exp(rng.uniform(np.log(2e8), np.log(1e10), len(c)))    # above Q^2_max
+    x2[d] = np.exp(rng.uniform(np.log(1e-8), np.log(1e-6), len(d)))   # corner with some of the above
+    q2[d] = np.exp(rng.uniform(np.log(0.5), np.log(2.0), len(d)))
+    if n > 10:
+        x1[3], q2[5], x2[7] = -1.0, np.nan, 1.5
+    return x1, x2, q2
+
+
+@pytest.mark.parametrize("n", [1, 4095, 4097, 16385, 200_000, 1_000_000])
+@pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("pids", ["p13", "all"])
+def test_fused_equals_unfused(n, f32, mixed, pids):
+    g = synth.config1_grid()
+    qk, a = synth.config1_alphas()
+    m = pdfmi.load_synth(g)
+    pdfmi.load_alphas(qk, a)
+    plist = PIDS if pids == "p13" else list(g.pids)
+    try:
+        x1, x2, q2 = _mixed_chunk(n, 9) if mixed else synth.config5_chunk(2, n=n)
+        d1, d2, dq = dev(x1), dev(x2), dev(q2)
+        ev = pdfmi.xfxq2_f32 if f32 else pdfmi.xfxq2
+        pdfmi.error_count(reset=True)
+        f1 = ev(m, plist, d1, dq)
+        f2 = ev(m, plist, d2, dq)
+        s_ref = pdfmi.mc_chunk_sum(f1, f2, pdfmi.alphas_q2(dq)).cpu().numpy()
+        e_ref = pdfmi.error_count(reset=True)
+        s = pdfmi.mc_fused(m, plist, d1, d2, dq, f32=f32).cpu().numpy()
+        e = pdfmi.error_count(reset=True)
+        assert s.view(np.uint64)[0] == s_ref.view(np.uint64)[0], (s, s_ref)
+        assert e == e_ref
+    finally:
+        pdfmi.unload(m)
+
+
+def test_fused_matches_oracle_and_empty():
+    g = synth.config1_grid()
+    qk, a = synth.config1_alphas()
+    m = pdfmi.load_synth(g)
+    pdfmi.load_alphas(qk, a)
+    try:
+        x1, x2, q2 = synth.config5_chunk(4, n=100_000)
+        s = pdfmi.mc_fused(m, PIDS, dev(x1), dev(x2), dev(q2)).item()
+        so, sabs = oracle_chunk(g, qk, a, x1, x2, q2)
+        assert abs(s - so) <= 1e-11 * sabs, (s, so)
+        e = torch.empty(0, dtype=torch.float64, device=DEV)
+        assert pdfmi.mc_fused(m, PIDS, e, e, e).item() == 0.0
+    finally:
+        pdfmi.unload(m)
+
+
+def test_fused_large_grid_reads_global():
+    """config-2 grid: too large for LDS, the fused kernel reads it from global memory."""
+    g = synth.config2_grid()
+    qk, a = synth.config2_alphas()
+    m = pdfmi.load_synth(g)
+    pdfmi.load_alphas(qk, a)
+    try:
+        x, q2 = synth.config2_queries(n=60_000, seed=12)
+        x2 = np.roll(x, 7)
+        d1, d2, dq = dev(x), dev(x2), dev(q2)
+        for f32 in (False, True):
+            ev = pdfmi.xfxq2_f32 if f32 else pdfmi.xfxq2
+            s_ref = pdfmi.mc_chunk_sum(ev(m, g.pids, d1, dq), ev(m, g.pids, d2, dq), pdfmi.alphas_q2(dq)).cpu().numpy()
+            s = pdfmi.mc_fused(m, g.pids, d1, d2, dq, f32=f32).cpu().numpy()
+            assert s.view(np.uint64)[0] == s_ref.view(np.uint64)[0], (f32, s, s_ref)
+    finally:
+        pdfmi.unload(m)
