@@ -16,7 +16,12 @@ before the timed region.  `value` counts PDF evaluations (points x flavours).
   surrogate  MLP surrogate trained on 2e6 interpolator samples, inference on
              1e7 points with interpolator fallback; error vs the FP64 oracle
   mc         1e8 Monte-Carlo-style points (two lookups at a shared scale,
-             alpha_s, FP64 fixed-order chunk sums), FP64 / FP32 / surrogate
+             alpha_s, FP64 fixed-order chunk sums), FP64 / FP32 / surrogate,
+             and the fused one-kernel forms (bit-identical sums)
+  members_fk 10..400 members evaluated on a 2415-point x grid at Q = 1.65
+             (13 flavours, FP64, one batched launch; the paper's Table 2
+             shape, its GPU seconds quoted as context), then the FP64
+             matrix-core contraction with a 1024-row synthetic FK table
 The dominant kernel's roofline uses its algorithmic bytes (16 B of (x, Q^2) in
 + 8 B per output value) over its average duration measured with HIP events on
 the launch stream.  cpu_baseline times the FP64 oracle on the host cores.
@@ -320,9 +325,17 @@ def main():
                     sur.xfxq2(X1[c], Q[c], P1, out=s1)
                     sur.xfxq2(X2[c], Q[c], P1, out=s2)
                     pdfmi.mc_chunk_sum(s1, s2, al, workspace=ws, out=sums[kind][c:c + 1])
+        sums["f64_fused"] = torch.empty(nchunk, dtype=torch.float64, device=dev)
+        sums["f32_fused"] = torch.empty(nchunk, dtype=torch.float64, device=dev)
+
+        def run_fused(kind):
+            for c in range(nchunk):
+                pdfmi.mc_fused(m1, PIDS, X1[c], X2[c], Q[c], f32=(kind == "f32_fused"), workspace=ws,
+                               out=sums[kind][c:c + 1])
         mc = {"points": nchunk * n_c, "chunks": nchunk, "evals_per_point": 26}
-        for kind in ("f64", "f32", "sur"):
-            ms = dtime(lambda: run_mc(kind), reps=1)
+        for kind in ("f64", "f32", "sur", "f64_fused", "f32_fused"):
+            fn = (lambda: run_fused(kind)) if kind.endswith("_fused") else (lambda: run_mc(kind))
+            ms = dtime(fn, reps=1)
             mc[kind] = {"ms": ms, "evals_per_s": nchunk * n_c * 26 / (ms * 1e-3)}
         tot = {k: float(sums[k].sum().item()) for k in sums}
         # chunk 0 against the oracle
@@ -332,13 +345,45 @@ def main():
         oc2 = oracle.xfxq2(og1, PIDS, ch[0][1], ch[0][2], n_threads=th)
         oa = oracle.alphas_q2(qk1, a1, ch[0][2])
         s0 = math.fsum(oa * np.sum(oc1 * oc2, axis=1))
-        for kind in ("f64", "f32", "sur"):
+        for kind in ("f64", "f32", "sur", "f64_fused", "f32_fused"):
             mc[kind]["chunk0_rel_err_vs_oracle"] = abs(float(sums[kind][0].item()) - s0) / abs(s0)
             mc[kind]["total"] = tot[kind]
             mc[kind]["speedup_vs_f64"] = mc["f64"]["ms"] / mc[kind]["ms"]
+        mc["fused_bit_identical"] = {
+            "f64": bool(torch.equal(sums["f64"].view(torch.int64), sums["f64_fused"].view(torch.int64))),
+            "f32": bool(torch.equal(sums["f32"].view(torch.int64), sums["f32_fused"].view(torch.int64)))}
         V["mc"] = mc
         sur.destroy()
         del X1, X2, Q
+
+        # ---------------------------------------------------------- multi-member x grid + FK contraction
+        log("multi-member evaluation on a 2415-point x grid and FK contraction")
+        nx_fk, ndat = 2415, 1024
+        fk_members = synth.config3_members(n_members=400)
+        fk_ids = [pdfmi.load_synth(mg) for mg in fk_members]
+        xg = torch.from_numpy(np.exp(np.linspace(np.log(2e-6), np.log(0.95), nx_fk))).to(dev)
+        qg = torch.full((nx_fk,), 1.65 ** 2, dtype=torch.float64, device=dev)
+        table = torch.from_numpy(np.random.default_rng(11).normal(size=(ndat, nx_fk * 13))).to(dev)
+        paper_gpu_s = {10: 0.07, 50: 0.35, 100: 0.69, 200: 1.46, 300: 1.29, 400: 1.69}
+        fkv = {"x_points": nx_fk, "flavours": 13, "q": 1.65, "ndat": ndat, "rows": []}
+        for nrep in (10, 50, 100, 200, 300, 400):
+            F = torch.empty((nrep, nx_fk, 13), dtype=torch.float64, device=dev)
+            plan = pdfmi.BatchPlan([(fk_ids[r], synth.PIDS_13, xg, qg, F[r]) for r in range(nrep)], out_f64=True)
+            plan.configure(tile_points=2048, vector_cols=1, use_graph=1)
+            t_eval = dtime(plan.run, reps=5)
+            Fm = F.reshape(nrep, -1)
+            T = torch.empty((nrep, ndat), dtype=torch.float64, device=dev)
+            t_fk = dtime(lambda: pdfmi.fk_contract(Fm, table, out=T), reps=5)
+            flops = 2.0 * nrep * ndat * nx_fk * 13
+            fkv["rows"].append({"nrep": nrep, "eval_ms": t_eval, "evals_per_s": nrep * nx_fk * 13 / (t_eval * 1e-3),
+                                "contract_ms": t_fk, "contract_tflops": flops / (t_fk * 1e-3) / 1e12,
+                                "contract_frac_fp64_peak": flops / (t_fk * 1e-3) / 78.6e12,
+                                "paper_table2_gpu_s_context": paper_gpu_s[nrep]})
+            plan.destroy()
+            del F, T
+        V["members_fk"] = fkv
+        for m_ in fk_ids:
+            pdfmi.unload(m_)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -72,14 +72,15 @@ __global__ __launch_bounds__(kFkThreads) void k_fk_contract(const double* __rest
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
-  // accumulator layout: lane holds rows 4 (lane / 16) + v, column lane % 16
+  // accumulator layout of the FP64 16x16x4 form: value v of a lane is row
+  // lane / 16 + 4 v, column lane % 16
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm * 32 + i * 16 + 4 * kq + v;
+        const int m = m0 + wm * 32 + i * 16 + kq + 4 * v;
         const int n = n0 + wn * 32 + j * 16 + r16;
         if (m < nrep && n < ndat) T[(int64_t)m * ndat + n] = acc[i][j][v];
       }

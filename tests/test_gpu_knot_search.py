@@ -116,7 +116,11 @@ def test_knot_search_bit_exact(case, separate_x):
         assert np.array_equal(reg.cpu().numpy(), oreg)
         ora, scale = oracle.xfxq2(og, g.pids, x, q2, with_scale=True)
         out = pdfmi.xfxq2(m, g.pids, dev(x), dev(q2)).cpu().numpy()
-        ok, _, _ = check_f64(out, ora, scale, grid_L(g))
+        # clustered Q^2 knots make the low-Q^2 exponent overflow: both sides must agree on +-inf/NaN
+        fin = np.isfinite(ora)
+        assert np.array_equal(np.isnan(out), np.isnan(ora))
+        assert np.array_equal(out[np.isinf(ora)], ora[np.isinf(ora)])
+        ok, _, _ = check_f64(np.where(fin, out, 0.0), np.where(fin, ora, 0.0), np.where(fin, scale, 0.0), grid_L(g))
         assert ok.all(), describe_failures(ok, out, ora, x, q2, g.pids)
     finally:
         pdfmi.unload(m)
