@@ -34,6 +34,7 @@ BatchLaunch batch_launch_params(bool f32, bool lds, int max_tbl, int64_t max_ele
 hipError_t batch_prepare(const BatchLaunch& L);
 hipError_t batch_launch(const BatchLaunch& L, void** args, unsigned* counter, hipStream_t s);
 int sur_nparams();
+constexpr int kSurMaxEnvKnots = 1024;  // the inference kernel stages the envelope in LDS
 int sur_out_width();
 int sur_hidden();
 hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s);
@@ -1131,6 +1132,22 @@ extern "C" int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_
   S.sd.ilx = 1.0 / (std::log(M->dev.xmax) - std::log(M->dev.xmin));
   S.sd.lq0 = std::log(M->dev.qmin);
   S.sd.ilq = 1.0 / (std::log(M->dev.qmax) - std::log(M->dev.qmin));
+  if (nx0 > kSurMaxEnvKnots)
+    return fail(PDF_ERR_GRID, "surrogate envelope supports at most %d x knots", kSurMaxEnvKnots);
+  {
+    int64_t o = 0;
+    for (int k = 0; k < K; ++k) {
+      const int nx = M->h_shape[2 * k], nq = M->h_shape[2 * k + 1];
+      const double* xk = M->h_knots.data() + o;
+      const double* qk = xk + nx;
+      S.sd.trust[k] = nx >= 4 && nq >= 4;
+      S.sd.txlo[k] = S.sd.trust[k] ? xk[1] : 0.0;
+      S.sd.txhi[k] = S.sd.trust[k] ? xk[nx - 2] : 0.0;
+      S.sd.tqlo[k] = S.sd.trust[k] ? qk[1] : 0.0;
+      S.sd.tqhi[k] = S.sd.trust[k] ? qk[nq - 2] : 0.0;
+      o += nx + nq;
+    }
+  }
   const size_t bp = align_up((size_t)NP * 4, 256), bpb = align_up((size_t)NP * 2, 256);
   const size_t be = align_up(env.size() * 4, 256), bl = align_up(lxk.size() * 4, 256);
   hipError_t e = hipMalloc(&S.pmem, 4 * bp + bpb + be + bl + 2048);

@@ -142,6 +142,10 @@ struct SurDev {
   double lq0, ilq;    // v = 2 (ln Q^2 - lq0) * ilq - 1
   const float* lxk;   // [nx] ln of the envelope knots
   const float* env;   // [nx][16] envelope values
+  // inference trusts the network inside sub-grid k for txlo[k] <= x < txhi[k]
+  // and tqlo[k] <= Q^2 < tqhi[k] (second to second-last knots) when trust[k]
+  int trust[kMaxSub];
+  double txlo[kMaxSub], txhi[kMaxSub], tqlo[kMaxSub], tqhi[kMaxSub];
 };
 
 // Surrogate device buffers (parameters, Adam moments, gradients, batch activations).

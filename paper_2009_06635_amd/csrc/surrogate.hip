@@ -41,10 +41,12 @@ __device__ __forceinline__ float bf16_float(unsigned short b) {
   return __uint_as_float(((unsigned)b) << 16);
 }
 
-// tanh from one exp and one division; relative error far below BF16 rounding.
+// tanh(|z|) = 1 - 2 / (exp(2|z|) + 1) from the hardware exp2 and reciprocal
+// (relative error ~1e-6 near 0 and far smaller elsewhere: well below the
+// BF16 rounding of the activations).
 __device__ __forceinline__ float tanh_f(float z) {
-  const float t = __expf(-2.0f * fabsf(z));
-  const float r = (1.0f - t) / (1.0f + t);
+  const float e = __builtin_amdgcn_exp2f(fminf(2.8853900817779268f * fabsf(z), 64.0f));  // 2|z| log2(e)
+  const float r = fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
   return copysignf(r, z);
 }
 
@@ -179,18 +181,6 @@ __device__ __forceinline__ void envelope(const SurDev& S, float lx, float e[kO])
   for (int c = 0; c < kO; ++c) e[c] = S.env[lo * kO + c] + t * (S.env[(lo + 1) * kO + c] - S.env[lo * kO + c]);
 }
 
-// Envelope of one column c at ln x.
-__device__ __forceinline__ float envelope_col(const SurDev& S, float lx, int c) {
-  int lo = 0, hi = S.nx - 2;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (S.lxk[mid] <= lx) lo = mid; else hi = mid - 1;
-  }
-  const float t = fminf(fmaxf((lx - S.lxk[lo]) / (S.lxk[lo + 1] - S.lxk[lo]), 0.0f), 1.0f);
-  const float e0 = S.env[lo * kO + c], e1 = S.env[(lo + 1) * kO + c];
-  return e0 + t * (e1 - e0);
-}
-
 __global__ void k_prep_samples(SurDev S, const double* __restrict__ X, const double* __restrict__ Q2,
                                const double* __restrict__ XF, int64_t n, float* __restrict__ in,
                                float* __restrict__ T) {
@@ -220,16 +210,18 @@ __global__ void k_prep_samples(SurDev S, const double* __restrict__ X, const dou
 // the same wave (one lane per flavour).
 constexpr int kSurWaves = 4;
 
-__device__ __forceinline__ bool trusted(const MemberDev& m, double x, double q2) {
+__device__ __forceinline__ bool trusted(const SurDev& S, const MemberDev& m, double x, double q2) {
   if (!(x >= m.xmin && x <= m.xmax && q2 >= m.qmin && q2 <= m.qmax)) return false;
   int k = 0;
   for (int j = 1; j < m.K; ++j)
     if (m.sub[j].qfirst <= q2) k = j;
-  const SubDesc& S = m.sub[k];
-  const double* xk = m.knots + S.xk_off;
-  const double* qk = m.knots + S.qk_off;
-  if (S.nx < 4 || S.nq < 4) return false;
-  return x >= xk[1] && x < xk[S.nx - 2] && q2 >= qk[1] && q2 < qk[S.nq - 2];
+  return S.trust[k] && x >= S.txlo[k] && x < S.txhi[k] && q2 >= S.tqlo[k] && q2 < S.tqhi[k];
+}
+
+// LDS of k_sur_infer: [nx] ln x knots, [nx][16] envelope, W1 (BF16-rounded),
+// b1, b2, b3, b4, then per wave the point records and the activation tile.
+size_t sur_infer_shared_bytes(int nx) {
+  return (size_t)4 * (nx + nx * kO + 2 * kH + 3 * kH + kO) + (size_t)kSurWaves * (16 * kH * 2 + 16 * 16 + 64 * 4);
 }
 
 __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDev m, const unsigned short* __restrict__ Pb,
@@ -238,10 +230,32 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
                                                              const double* __restrict__ Q2, int64_t n,
                                                              float* __restrict__ out, double invL01,
                                                              unsigned long long* __restrict__ nerr) {
-  __shared__ unsigned short sh[kSurWaves][16 * kH];
-  __shared__ float spt[kSurWaves][16][2];
+  extern __shared__ __align__(16) float sdyn[];
+  float* slxk = sdyn;                         // [nx]
+  float* senv = slxk + S.nx;                  // [nx][kO]
+  float* sw1 = senv + S.nx * kO;              // [kH][2], BF16-rounded
+  float* sb1 = sw1 + 2 * kH;
+  float* sb2 = sb1 + kH;
+  float* sb3 = sb2 + kH;
+  float* sb4 = sb3 + kH;                      // [kO]
+  unsigned short* shs = reinterpret_cast<unsigned short*>(sb4 + kO);             // [waves][16 * kH]
+  float* spt = reinterpret_cast<float*>(shs + kSurWaves * 16 * kH);              // [waves][16][4]
+  int* sfb = reinterpret_cast<int*>(spt + kSurWaves * 64);                        // [waves][64]
+  for (int i = threadIdx.x; i < S.nx; i += 64 * kSurWaves) slxk[i] = S.lxk[i];
+  for (int i = threadIdx.x; i < S.nx * kO; i += 64 * kSurWaves) senv[i] = S.env[i];
+  for (int i = threadIdx.x; i < 2 * kH; i += 64 * kSurWaves) sw1[i] = bf16_float(bf16_bits(Pf[kOffW1 + i]));
+  for (int i = threadIdx.x; i < kH; i += 64 * kSurWaves) {
+    sb1[i] = Pf[kOffB1 + i];
+    sb2[i] = Pf[kOffB2 + i];
+    sb3[i] = Pf[kOffB3 + i];
+  }
+  for (int i = threadIdx.x; i < kO; i += 64 * kSurWaves) sb4[i] = Pf[kOffB4 + i];
+  __syncthreads();
+
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
-  unsigned short* hs = sh[wv];
+  unsigned short* hs = shs + wv * 16 * kH;
+  float* pt4 = spt + wv * 64;   // per point: u, v, envelope t, envelope cell (as int bits)
+  int* fbl = sfb + wv * 64;
   // weight fragments: B operand of layer L, N-tile t, K-step s: lane holds W[n = 16t + r][k = 32s + 8g + i]
   bf16x8 w2[4][2], w3[4][2], w4[2];
 #pragma unroll
@@ -258,52 +272,59 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int i = 0; i < 8; ++i) w4[s][i] = __builtin_bit_cast(__bf16, Pb[kOffW4 + r * kH + 32 * s + 8 * g + i]);
+  const Tables gtb{m.knots, m.cells, m.hints, m.subs};
 
   const int64_t ntiles = (n + 15) / 16;
   for (int64_t tile = (int64_t)blockIdx.x * kSurWaves + wv; tile < ntiles; tile += (int64_t)gridDim.x * kSurWaves) {
     const int64_t p0 = tile * 16;
     const int np = (int)min((int64_t)16, n - p0);
-    // inputs of the wave's 16 points (lanes 0..15), shared through LDS
-    double xr = 0.5, qr = 1.0, lxr = 0.0;
+    // lanes 0..15: the wave's 16 points (inputs, fallback flag, envelope interval)
+    double xr = 0.5, qr = 1.0;
     bool fb = false;
     if (l < np) {
       xr = X[p0 + l];
       qr = Q2[p0 + l];
-      fb = !trusted(m, xr, qr);
+      fb = !trusted(S, m, xr, qr);
       const double lx = log(xr), lq = log(qr);
-      lxr = lx;
-      spt[wv][l][0] = (float)(2.0 * (lx - S.lx0) * S.ilx - 1.0);
-      spt[wv][l][1] = (float)(2.0 * (lq - S.lq0) * S.ilq - 1.0);
+      pt4[4 * l] = (float)(2.0 * (lx - S.lx0) * S.ilx - 1.0);
+      pt4[4 * l + 1] = (float)(2.0 * (lq - S.lq0) * S.ilq - 1.0);
+      const float lxf = (float)lx;
+      int lo = 0, hi = S.nx - 2;
+      while (lo < hi) {  // largest i <= nx-2 with lxk[i] <= ln x
+        const int mid = (lo + hi + 1) >> 1;
+        if (slxk[mid] <= lxf) lo = mid; else hi = mid - 1;
+      }
+      pt4[4 * l + 2] = fminf(fmaxf((lxf - slxk[lo]) / (slxk[lo + 1] - slxk[lo]), 0.0f), 1.0f);
+      pt4[4 * l + 3] = __int_as_float(lo);
     } else if (l < 16) {
-      spt[wv][l][0] = 0.0f;
-      spt[wv][l][1] = 0.0f;
+      pt4[4 * l] = pt4[4 * l + 1] = pt4[4 * l + 2] = 0.0f;
+      pt4[4 * l + 3] = __int_as_float(0);
     }
     const unsigned long long fbmask = __ballot(fb) & 0xFFFFull;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // layer 1 straight into the A layout: lane (r, g) holds h1[r][32 s + 8 g + i]
-    const float u = bf16_float(bf16_bits(spt[wv][r][0])), v = bf16_float(bf16_bits(spt[wv][r][1]));
+    const float u = bf16_float(bf16_bits(pt4[4 * r])), v = bf16_float(bf16_bits(pt4[4 * r + 1]));
     bf16x8 a[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int j = 32 * s + 8 * g + i;
-        const float z = fmaf(bf16_float(bf16_bits(Pf[kOffW1 + 2 * j])), u,
-                             fmaf(bf16_float(bf16_bits(Pf[kOffW1 + 2 * j + 1])), v, Pf[kOffB1 + j]));
+        const float z = fmaf(sw1[2 * j], u, fmaf(sw1[2 * j + 1], v, sb1[j]));
         a[s][i] = __builtin_bit_cast(__bf16, bf16_bits(tanh_f(z)));
       }
     // layers 2 and 3
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
-      const int boff = layer == 0 ? kOffB2 : kOffB3;
+      const float* bl = layer == 0 ? sb2 : sb3;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], layer == 0 ? w2[t][0] : w3[t][0], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], layer == 0 ? w2[t][1] : w3[t][1], acc, 0, 0, 0);
-        const float bn = Pf[boff + 16 * t + r];
+        const float bn = bl[16 * t + r];
 #pragma unroll
         for (int i = 0; i < 4; ++i) hs[(4 * g + i) * kH + 16 * t + r] = bf16_bits(tanh_f(acc[i] + bn));
       }
@@ -318,29 +339,38 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // layer 4: lane (r, g) gets y[point 4 g + i][output r]
+    // layer 4: lane (r, g) gets y[point 4 g + i][output r]; times the envelope
     f32x4 y = {0.f, 0.f, 0.f, 0.f};
     y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], w4[0], y, 0, 0, 0);
     y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], w4[1], y, 0, 0, 0);
-    const float b4 = Pf[kOffB4 + r];
+    const float b4 = sb4[r];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int pt = 4 * g + i;
-      const float lxp = (float)__shfl(lxr, pt);
-      if (pt < np && r < S.P && !((fbmask >> pt) & 1ull))
-        out[(p0 + pt) * S.P + r] = (y[i] + b4) * envelope_col(S, lxp, r);
-    }
-    // fallback points: FP32 interpolator, one lane per stored column
-    unsigned long long fm = fbmask;
-    while (fm) {
-      const int pt = __builtin_ctzll(fm);
-      fm &= fm - 1;
-      const double xp = __shfl(xr, pt), qp = __shfl(qr, pt);
-      if (l < S.P) {
-        const float v2 = interp_point<float>(m, Tables{m.knots, m.cells, m.hints, m.subs}, xp, qp, l, invL01);
-        out[(p0 + pt) * S.P + l] = v2;
+      if (pt < np && r < S.P && !((fbmask >> pt) & 1ull)) {
+        const int lo = __float_as_int(pt4[4 * pt + 3]);
+        const float t = pt4[4 * pt + 2];
+        const float e0 = senv[lo * kO + r], e1 = senv[(lo + 1) * kO + r];
+        out[(p0 + pt) * S.P + r] = (y[i] + b4) * (e0 + t * (e1 - e0));
       }
-      if (l == 0 && !((xp > 0.0) && (xp <= m.xmax) && (qp > 0.0) && (qp < INFINITY))) atomicAdd(nerr, 1ull);
+    }
+    // fallback points: FP32 interpolator, one lane per (point, stored column)
+    if (fbmask) {
+      const int nfb = __popcll(fbmask);
+      if (l < 16 && ((fbmask >> l) & 1ull)) fbl[__popcll(fbmask & ((1ull << l) - 1))] = l;
+      if (l < 16 && ((fbmask >> l) & 1ull) && !((xr > 0.0) && (xr <= m.xmax) && (qr > 0.0) && (qr < INFINITY)))
+        atomicAdd(nerr, 1ull);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int w = l; w < nfb * S.P; w += 64) {
+        const int pt = fbl[w / S.P], c = w - (w / S.P) * S.P;
+        const double xp = X[p0 + pt], qp = Q2[p0 + pt];
+        out[(p0 + pt) * S.P + c] = interp_point<float>(m, gtb, xp, qp, c, invL01);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }
@@ -445,9 +475,14 @@ hipError_t sur_infer(const SurDev& S, const MemberDev& m, const SurBufs& b, cons
                      int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu, hipStream_t s) {
   const int64_t tiles = (n + 15) / 16;
   const int64_t blocks = min((tiles + kSurWaves - 1) / kSurWaves, (int64_t)n_cu * 8);
-  if (blocks > 0)
-    hipLaunchKernelGGL(k_sur_infer, dim3((unsigned)blocks), dim3(64 * kSurWaves), 0, s, S, m, b.Pb, b.P, x, q2, n,
+  if (blocks > 0) {
+    const size_t shm = sur_infer_shared_bytes(S.nx);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sur_infer),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sur_infer, dim3((unsigned)blocks), dim3(64 * kSurWaves), shm, s, S, m, b.Pb, b.P, x, q2, n,
                        out, invL01, nerr);
+  }
   return hipGetLastError();
 }
 
