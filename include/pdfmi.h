@@ -175,7 +175,8 @@ int pdf_set_lds_policy(int32_t policy);
  *                            16-byte group of columns (2 FP64 / 4 FP32);
  *                            0: one lane per (point, flavour)
  *   PDF_TUNE_BLOCKS_PER_CU   workgroups launched per compute unit when the
- *                            grid is read from global memory (1..64)
+ *                            grid is read from global memory (1..4096;
+ *                            capped at one 64-point tile per wave)
  * PDF_ERR_ARG for an unknown knob or value out of range.
  */
 enum { PDF_TUNE_LDS_POLICY = 0, PDF_TUNE_VECTOR_COLUMNS = 1, PDF_TUNE_BLOCKS_PER_CU = 2 };
@@ -348,8 +349,12 @@ int pdf_mc_fused_f32(int32_t member, const int32_t* pids, int32_t n_pids,
  *   out[r][d] = sum_k pdf[r][k] * fk[d][k]      (FP64, fixed summation order)
  * pdf: device [nrep][K] (member r's values flattened, e.g. [x point][flavour]
  * as pdf_xfxq2 writes them), fk: device [ndat][K] in the same k order, out:
- * device [nrep][ndat].  K = 0 gives zeros.  Errors: PDF_ERR_ARG (negative
- * sizes, nrep > 2^22, null pointers), PDF_ERR_DEVICE.  Asynchronous on stream.
+ * device [nrep][ndat].  K = 0 gives zeros.  For long K the sum is split into
+ * slices whose partial sums the library keeps in a workspace it allocates on
+ * first need and reuses (grown, after synchronising the stream, when a
+ * larger one is needed; freed by pdf_shutdown).  Errors: PDF_ERR_ARG
+ * (negative sizes, nrep > 2^22, null pointers), PDF_ERR_NOMEM,
+ * PDF_ERR_DEVICE.  Asynchronous on stream.
  */
 int pdf_fk_contract(const double* pdf, const double* fk, int32_t nrep, int32_t ndat, int64_t K,
                     double* out, pdf_stream_t stream);

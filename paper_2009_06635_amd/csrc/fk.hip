@@ -11,9 +11,13 @@
 // staged in LDS (rows padded to 33 doubles so that the 16 rows read by one
 // MFMA operand fall in different banks), with the next step's global loads
 // issued before the current step's MFMAs.  Out-of-range rows and k read as
-// zero; the summation order over k is fixed (deterministic results).
+// zero.  K is split into S slices (chosen from the sizes and the number of
+// compute units only) whose partial sums are added in slice order, so the
+// summation order is fixed (deterministic results).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 namespace pdfmi {
 
@@ -21,8 +25,13 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFkBM = 64, kFkBN = 64, kFkBK = 32, kFkLd = kFkBK + 1, kFkThreads = 256;
 
+// One (64 x 64 tile, K slice) per workgroup: the slice [blockIdx.z * kslice,
+// min(K, (blockIdx.z + 1) * kslice)) of the sum goes to T + blockIdx.z *
+// nrep * ndat (the partial sums of the slices are added in slice order by
+// k_fk_reduce).
 __global__ __launch_bounds__(kFkThreads) void k_fk_contract(const double* __restrict__ F, const double* __restrict__ FK,
-                                                            int nrep, int ndat, int64_t K, double* __restrict__ T) {
+                                                            int nrep, int ndat, int64_t K, int64_t kslice,
+                                                            double* __restrict__ T) {
   __shared__ double sa[kFkBM * kFkLd];
   __shared__ double sb[kFkBN * kFkLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -33,13 +42,15 @@ __global__ __launch_bounds__(kFkThreads) void k_fk_contract(const double* __rest
   const bool arow_ok = m0 + lrow < nrep, brow_ok = n0 + lrow < ndat;
   const double* ap = F + (int64_t)(m0 + lrow) * K;
   const double* bp = FK + (int64_t)(n0 + lrow) * K;
+  const int64_t kbeg = (int64_t)blockIdx.z * kslice, kend = min(K, kbeg + kslice);
+  T += (int64_t)blockIdx.z * nrep * ndat;
   double ra[8], rb[8];
   auto fetch = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int64_t k = k0 + lk + i;
-      ra[i] = (arow_ok && k < K) ? ap[k] : 0.0;
-      rb[i] = (brow_ok && k < K) ? bp[k] : 0.0;
+      ra[i] = (arow_ok && k < kend) ? ap[k] : 0.0;
+      rb[i] = (brow_ok && k < kend) ? bp[k] : 0.0;
     }
   };
   f64x4 acc[2][2];
@@ -48,8 +59,8 @@ __global__ __launch_bounds__(kFkThreads) void k_fk_contract(const double* __rest
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int r16 = lane & 15, kq = lane >> 4;
-  fetch(0);
-  for (int64_t k0 = 0; k0 < K; k0 += kFkBK) {
+  fetch(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kFkBK) {
     __syncthreads();  // previous step's operands consumed
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -57,7 +68,7 @@ __global__ __launch_bounds__(kFkThreads) void k_fk_contract(const double* __rest
       sb[lrow * kFkLd + lk + i] = rb[i];
     }
     __syncthreads();
-    if (k0 + kFkBK < K) fetch(k0 + kFkBK);
+    if (k0 + kFkBK < kend) fetch(k0 + kFkBK);
 #pragma unroll
     for (int kk = 0; kk < kFkBK; kk += 4) {
       double a[2], b[2];
@@ -86,10 +97,37 @@ __global__ __launch_bounds__(kFkThreads) void k_fk_contract(const double* __rest
       }
 }
 
-hipError_t launch_fk_contract(const double* F, const double* FK, int nrep, int ndat, int64_t K, double* T,
-                              hipStream_t s) {
-  const dim3 grid((unsigned)((ndat + kFkBN - 1) / kFkBN), (unsigned)((nrep + kFkBM - 1) / kFkBM));
-  hipLaunchKernelGGL(k_fk_contract, grid, dim3(kFkThreads), 0, s, F, FK, nrep, ndat, K, T);
+// T[m][n] = sum over slices s = 0..S-1 (in that order) of P[s][m][n].
+__global__ void k_fk_reduce(const double* __restrict__ P, int S, int64_t mn, double* __restrict__ T) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < mn; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = P[i];
+    for (int s = 1; s < S; ++s) acc += P[(int64_t)s * mn + i];
+    T[i] = acc;
+  }
+}
+
+// K slices for a contraction: enough workgroups to cover the compute units
+// about four times, each slice a multiple of the K step and at least 512.
+int fk_slices(int nrep, int ndat, int64_t K, int n_cu) {
+  const int64_t tiles = (int64_t)((ndat + kFkBN - 1) / kFkBN) * ((nrep + kFkBM - 1) / kFkBM);
+  int64_t S = (4 * (int64_t)n_cu + tiles - 1) / std::max<int64_t>(tiles, 1);
+  S = min(S, std::max<int64_t>(1, K / 512));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(S, 64));
+}
+
+// ws: S * nrep * ndat doubles when S > 1 (unused otherwise).
+hipError_t launch_fk_contract(const double* F, const double* FK, int nrep, int ndat, int64_t K, double* T, int S,
+                              double* ws, hipStream_t s) {
+  int64_t kslice = (K + S - 1) / S;
+  kslice = (kslice + kFkBK - 1) / kFkBK * kFkBK;
+  const dim3 grid((unsigned)((ndat + kFkBN - 1) / kFkBN), (unsigned)((nrep + kFkBM - 1) / kFkBM), (unsigned)S);
+  hipLaunchKernelGGL(k_fk_contract, grid, dim3(kFkThreads), 0, s, F, FK, nrep, ndat, K, std::max<int64_t>(kslice, 1),
+                     S > 1 ? ws : T);
+  if (S > 1) {
+    const int64_t mn = (int64_t)nrep * ndat;
+    const int64_t nb = std::min<int64_t>((mn + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fk_reduce, dim3((unsigned)nb), dim3(256), 0, s, ws, S, mn, T);
+  }
   return hipGetLastError();
 }
 

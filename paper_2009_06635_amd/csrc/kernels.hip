@@ -339,7 +339,7 @@ constexpr int kAlphasMaxKnots = 256;
 // alpha_s at one Q^2 from the table (knots sk, values sv, cells sc); NaN for
 // Q^2 <= 0 or non-finite.
 __device__ __forceinline__ double alphas_point(const AlphasDev& A, const double* sk, const double* sv,
-                                               const CellCoef* sc, double q2) {
+                                               const CellCoef* sc, const short* sh, double q2) {
   const bool valid = q2 > 0.0 && q2 < INFINITY;
   if (!valid) return NAN;
   if (q2 < sk[0]) return sv[0];
@@ -349,7 +349,7 @@ __device__ __forceinline__ double alphas_point(const AlphasDev& A, const double*
     if (A.seg_first[j] <= q2) s = j;
   const int lo = A.seg_lo[s], hi = A.seg_hi[s];
   const int m = hi - lo + 1;
-  const int c = lo + find_cell(sk + lo, m, q2);
+  const int c = lo + find_cell_hint(sk + lo, m, q2, A.seg_hint[s], sh);
   const CellCoef cc = sc[c];
   const int m4 = m < 4 ? m : 4;
   const int st = min(max(c - 1, lo), hi - m4 + 1);
@@ -360,24 +360,43 @@ __device__ __forceinline__ double alphas_point(const AlphasDev& A, const double*
   return acc;
 }
 
+// One thread per group of 4 consecutive points (32-byte loads and stores,
+// four independent evaluations in flight per thread).
+constexpr int kAlphasMaxHints = 2048;
+
 __global__ __launch_bounds__(256) void k_alphas(AlphasDev A, const double* __restrict__ Q2, int64_t n,
                                                 double* __restrict__ out, unsigned long long* __restrict__ nerr) {
   __shared__ double sk[kAlphasMaxKnots];
   __shared__ double sv[kAlphasMaxKnots];
   __shared__ CellCoef sc[kAlphasMaxKnots];
+  __shared__ short sh[kAlphasMaxHints];
   for (int i = threadIdx.x; i < A.n; i += 256) {
     sk[i] = A.knots[i];
     sv[i] = A.vals[i];
     sc[i] = A.cells[i];
   }
+  for (int i = threadIdx.x; i < A.nhints; i += 256) sh[i] = A.hints[i];
   __syncthreads();
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double q2 = Q2[i];
-    const bool valid = q2 > 0.0 && q2 < INFINITY;
-    const double r = alphas_point(A, sk, sv, sc, q2);
-    const unsigned long long bal = __ballot(!valid);
-    if (bal && (threadIdx.x & 63) == 0) atomicAdd(nerr, (unsigned long long)__popcll(bal));
-    out[i] = r;
+  const int64_t ngroups = (n + 3) / 4;
+  for (int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gi < ngroups;
+       gi += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i0 = gi * 4;
+    double q[4], r[4];
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = i0 + j < n ? Q2[i0 + j] : 1.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      r[j] = alphas_point(A, sk, sv, sc, sh, q[j]);
+      bad += (i0 + j < n && !(q[j] > 0.0 && q[j] < INFINITY)) ? 1 : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (i0 + j < n) out[i0 + j] = r[j];
+    // lane-summed invalid count, one atomic per wave
+    unsigned long long cnt = 0;
+    for (int b = 1; b <= 4; ++b) cnt += (unsigned long long)b * __popcll(__ballot(bad == b));
+    if (cnt && (threadIdx.x & 63) == 0) atomicAdd(nerr, cnt);
   }
 }
 
@@ -471,7 +490,7 @@ hipError_t launch_locate(const MemberDev& m, const double* x, const double* q2, 
 
 hipError_t launch_alphas(const AlphasDev& A, const double* q2, int64_t n, double* out, unsigned long long* nerr,
                          int n_cu, hipStream_t s) {
-  const int64_t nb = min((n + 255) / 256, (int64_t)n_cu * 8);
+  const int64_t nb = min(((n + 3) / 4 + 255) / 256, (int64_t)n_cu * 8);
   hipLaunchKernelGGL(k_alphas, dim3((unsigned)nb), dim3(256), 0, s, A, q2, n, out, nerr);
   return hipGetLastError();
 }
@@ -488,7 +507,7 @@ namespace pdfmi {
 // order, then a fixed binary tree in LDS); stage 2 sums the partials with the
 // same tree in one workgroup.  Bit-identical across runs.
 constexpr int kMcThreads = 256;
-constexpr int kMcBlock = 4096;
+constexpr int kMcBlock = 1024;  // 4 points per thread: a 1e6-point chunk spans ~1000 blocks
 
 __device__ __forceinline__ double block_tree_sum(double v, double* sh) {
   sh[threadIdx.x] = v;
@@ -500,18 +519,59 @@ __device__ __forceinline__ double block_tree_sum(double v, double* sh) {
   return sh[0];
 }
 
+// Stage 1 when the rows do not fit LDS (many flavours): the same order read
+// straight from global memory.
+template <typename T>
+__global__ __launch_bounds__(kMcThreads) void k_mc_partial_direct(const T* __restrict__ xf1,
+                                                                  const T* __restrict__ xf2, int P,
+                                                                  const double* __restrict__ as, int64_t n,
+                                                                  double* __restrict__ partial) {
+  __shared__ double sh[kMcThreads];
+  const int64_t beg = (int64_t)blockIdx.x * kMcBlock;
+  const int64_t end = min(beg + kMcBlock, n);
+  double acc = 0.0;
+  for (int k = 0; k < kMcBlock / kMcThreads; ++k) {
+    const int64_t i = beg + threadIdx.x + (int64_t)kMcThreads * k;
+    if (i < end) {
+      double lum = 0.0;
+      for (int j = 0; j < P; ++j) lum = fma((double)xf1[i * P + j], (double)xf2[i * P + j], lum);
+      acc = fma(as[i], lum, acc);
+    }
+  }
+  const double s = block_tree_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Stage 1.  The block's points are taken 256 at a time: their xf1 and xf2
+// rows (contiguous in memory) are copied to LDS with coalesced loads, then
+// thread t forms sum_j xf1 xf2 of its point in flavour order and accumulates
+// alpha_s times it -- thread t sees points beg + t + 256 k in increasing k.
 template <typename T>
 __global__ __launch_bounds__(kMcThreads) void k_mc_partial(const T* __restrict__ xf1, const T* __restrict__ xf2,
                                                            int P, const double* __restrict__ as, int64_t n,
                                                            double* __restrict__ partial) {
   __shared__ double sh[kMcThreads];
+  extern __shared__ __align__(16) unsigned char mc_smem[];
+  T* s1 = reinterpret_cast<T*>(mc_smem);  // [256][P]
+  T* s2 = s1 + kMcThreads * P;            // [256][P]
   const int64_t beg = (int64_t)blockIdx.x * kMcBlock;
   const int64_t end = min(beg + kMcBlock, n);
   double acc = 0.0;
-  for (int64_t i = beg + threadIdx.x; i < end; i += kMcThreads) {
-    double lum = 0.0;
-    for (int j = 0; j < P; ++j) lum = fma((double)xf1[i * P + j], (double)xf2[i * P + j], lum);
-    acc = fma(as[i], lum, acc);
+  for (int k = 0; k < kMcBlock / kMcThreads; ++k) {
+    const int64_t p0 = beg + (int64_t)kMcThreads * k;
+    if (p0 >= end) break;  // uniform across the block
+    const int np = (int)min((int64_t)kMcThreads, end - p0);
+    __syncthreads();       // previous step's rows consumed
+    for (int e = threadIdx.x; e < np * P; e += kMcThreads) {
+      s1[e] = xf1[p0 * P + e];
+      s2[e] = xf2[p0 * P + e];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < np) {
+      double lum = 0.0;
+      for (int j = 0; j < P; ++j) lum = fma((double)s1[threadIdx.x * P + j], (double)s2[threadIdx.x * P + j], lum);
+      acc = fma(as[p0 + threadIdx.x], lum, acc);
+    }
   }
   const double s = block_tree_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -532,8 +592,18 @@ template <typename T>
 hipError_t launch_mc_sum(const T* xf1, const T* xf2, int P, const double* as, int64_t n, double* partial,
                          double* sum_out, hipStream_t s) {
   const int64_t np = mc_partials(n);
-  if (np > 0)
-    hipLaunchKernelGGL(k_mc_partial<T>, dim3((unsigned)np), dim3(kMcThreads), 0, s, xf1, xf2, P, as, n, partial);
+  if (np > 0) {
+    const size_t shm = (size_t)2 * kMcThreads * P * sizeof(T);
+    if (shm <= 96 * 1024) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mc_partial<T>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_mc_partial<T>, dim3((unsigned)np), dim3(kMcThreads), shm, s, xf1, xf2, P, as, n, partial);
+    } else {
+      hipLaunchKernelGGL(k_mc_partial_direct<T>, dim3((unsigned)np), dim3(kMcThreads), 0, s, xf1, xf2, P, as, n,
+                         partial);
+    }
+  }
   hipLaunchKernelGGL(k_mc_final, dim3(1), dim3(kMcThreads), 0, s, partial, np, sum_out);
   return hipGetLastError();
 }
@@ -595,7 +665,8 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
   double* ask = reinterpret_cast<double*>(smem + m.tbl_bytes);
   double* asv = ask + an2;
   CellCoef* asc = reinterpret_cast<CellCoef*>(asv + an2);
-  double* tree = reinterpret_cast<double*>(asc + an2);  // [4][256]
+  short* ash = reinterpret_cast<short*>(asc + an2);          // [A.nhints, padded to 8]
+  double* tree = reinterpret_cast<double*>(ash + ((A.nhints + 7) & ~7));  // [4][256]
   int* scol = reinterpret_cast<int*>(tree + kMcFusedBS);  // [kMaxReq]
   int* soff = scol + kMaxReq;                             // [kMaxSub] staged sub-grid offsets
   T* sgrid = reinterpret_cast<T*>(soff + kMaxSub);        // 16-byte aligned: kMaxReq + kMaxSub ints
@@ -609,6 +680,7 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
     asv[i] = A.vals[i];
     asc[i] = A.cells[i];
   }
+  for (int i = threadIdx.x; i < A.nhints; i += kMcFusedBS) ash[i] = A.hints[i];
   for (int i = threadIdx.x; i < rc.n; i += kMcFusedBS) scol[i] = rc.col[i];
   const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
   const T* __restrict__ gvals = member_values<T>(m);
@@ -656,7 +728,7 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
       T w1[4], v1[4], w2[4], v2[4];
       const PointLoc L1 = locate_point<T>(m, tb, x1, q2, w1, v1);
       const PointLoc L2 = locate_point<T>(m, tb, x2, q2, w2, v2);
-      const double as = alphas_point(A, ask, asv, asc, q2);
+      const double as = alphas_point(A, ask, asv, asc, ash, q2);
       const bool bad1 = live && (L1.mode & kInvalid), bad2 = live && (L2.mode & kInvalid);
       const bool bada = live && !(q2 > 0.0 && q2 < INFINITY);
       const unsigned long long nb = __popcll(__ballot(bad1)) + __popcll(__ballot(bad2)) + __popcll(__ballot(bada));
@@ -700,7 +772,8 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
 // LDS bytes of k_mc_fused (grid_elems > 0: the grid staged with row stride P).
 size_t mc_fused_shared_bytes(const MemberDev& m, const AlphasDev& A, int64_t grid_elems, bool f32) {
   const size_t an2 = (size_t)((A.n + 1) & ~1);
-  return (size_t)m.tbl_bytes + an2 * (8 + 8 + sizeof(CellCoef)) + kMcFusedBS * 8 + (kMaxReq + kMaxSub) * 4 +
+  return (size_t)m.tbl_bytes + an2 * (8 + 8 + sizeof(CellCoef)) + (size_t)((A.nhints + 7) & ~7) * 2 +
+         kMcFusedBS * 8 + (kMaxReq + kMaxSub) * 4 +
          (size_t)grid_elems * (f32 ? 4 : 8);
 }
 

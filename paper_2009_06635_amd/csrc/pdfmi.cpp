@@ -35,6 +35,7 @@ hipError_t batch_prepare(const BatchLaunch& L);
 hipError_t batch_launch(const BatchLaunch& L, void** args, unsigned* counter, hipStream_t s);
 int sur_nparams();
 constexpr int kSurMaxEnvKnots = 1024;  // the inference kernel stages the envelope in LDS
+constexpr int kAlphasMaxHints = 2048;  // alpha_s search hints staged in LDS
 int sur_out_width();
 int sur_hidden();
 hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s);
@@ -50,8 +51,9 @@ template <typename T>
 hipError_t launch_mc_fused(const MemberDev&, const ReqCols&, const AlphasDev&, const double*, const double*,
                            const double*, int64_t, double*, double*, unsigned long long*, double, int, hipStream_t);
 size_t mc_fused_shared_bytes(const MemberDev& m, const AlphasDev& A, int64_t grid_elems, bool f32);
-hipError_t launch_fk_contract(const double* F, const double* FK, int nrep, int ndat, int64_t K, double* T,
-                              hipStream_t s);
+hipError_t launch_fk_contract(const double* F, const double* FK, int nrep, int ndat, int64_t K, double* T, int S,
+                              double* ws, hipStream_t s);
+int fk_slices(int nrep, int ndat, int64_t K, int n_cu);
 }  // namespace pdfmi
 
 using namespace pdfmi;
@@ -103,7 +105,9 @@ AlphasDev g_alphas{};
 void* g_alphas_mem = nullptr;
 int g_lds_policy = 0;  // 0 auto, 1 never stage the grid in LDS, 2 whenever it fits
 int g_vector_cols = 1; // serve all-column requests with G-wide vector gathers
-int g_blocks_per_cu = 16;
+int g_blocks_per_cu = 32;
+void* g_fk_ws = nullptr;      // partial sums of the K slices of pdf_fk_contract (grow-only)
+size_t g_fk_ws_bytes = 0;
 constexpr size_t kLdsBytes = 160 * 1024;
 
 int ensure_init() {
@@ -497,11 +501,22 @@ extern "C" int pdf_load_alphas(int32_t n, const double* q2k, const double* a) {
   }
   std::vector<CellCoef> hc((size_t)n);  // cell j valid when j, j+1 share a segment
   for (int s = 0; s < A.nseg; ++s) cell_coefs(q2k + A.seg_lo[s], A.seg_hi[s] - A.seg_lo[s] + 1, &hc[A.seg_lo[s]]);
+  std::vector<short> hh;
+  for (int s = 0; s < A.nseg; ++s) {
+    A.seg_hint[s] = build_hints(q2k + A.seg_lo[s], A.seg_hi[s] - A.seg_lo[s] + 1, hh);
+    if ((int)hh.size() > kAlphasMaxHints) {  // keep the staged list small: binary search this segment
+      hh.resize(A.seg_hint[s].off);
+      A.seg_hint[s].off = -1;
+    }
+  }
+  A.nhints = (int)hh.size();
   const size_t bk = align_up((size_t)n * 8, 256), bv = align_up((size_t)n * 8, 256);
-  std::vector<unsigned char> blob(bk + bv + hc.size() * sizeof(CellCoef), 0);
+  const size_t bc = align_up(hc.size() * sizeof(CellCoef), 256);
+  std::vector<unsigned char> blob(bk + bv + bc + hh.size() * sizeof(short) + 16, 0);
   std::memcpy(blob.data(), q2k, (size_t)n * 8);
   std::memcpy(blob.data() + bk, a, (size_t)n * 8);
   std::memcpy(blob.data() + bk + bv, hc.data(), hc.size() * sizeof(CellCoef));
+  if (!hh.empty()) std::memcpy(blob.data() + bk + bv + bc, hh.data(), hh.size() * sizeof(short));
   void* mem = nullptr;
   hipError_t e = hipMalloc(&mem, blob.size());
   if (e != hipSuccess) return fail_hip(e, "hipMalloc(alpha_s)");
@@ -514,6 +529,7 @@ extern "C" int pdf_load_alphas(int32_t n, const double* q2k, const double* a) {
   A.knots = reinterpret_cast<const double*>(b);
   A.vals = reinterpret_cast<const double*>(b + bk);
   A.cells = reinterpret_cast<const CellCoef*>(b + bk + bv);
+  A.hints = reinterpret_cast<const short*>(b + bk + bv + bc);
   if (g_alphas_mem) (void)hipFree(g_alphas_mem);
   g_alphas_mem = mem;
   g_alphas = A;
@@ -611,7 +627,7 @@ extern "C" int pdf_set_tuning(int32_t knob, int32_t value) {
       g_vector_cols = value;
       return PDF_OK;
     case PDF_TUNE_BLOCKS_PER_CU:
-      if (value < 1 || value > 64) return fail(PDF_ERR_ARG, "blocks per CU must be in [1, 64]");
+      if (value < 1 || value > 4096) return fail(PDF_ERR_ARG, "blocks per CU must be in [1, 4096]");
       g_blocks_per_cu = value;
       return PDF_OK;
     default:
@@ -1433,7 +1449,21 @@ extern "C" int pdf_fk_contract(const double* pdf, const double* fk, int32_t nrep
   int rc = ensure_init();
   if (rc != PDF_OK) return rc;
   if (nrep == 0 || ndat == 0) return PDF_OK;
-  hipError_t e = launch_fk_contract(pdf, fk, nrep, ndat, K, out, (hipStream_t)stream);
+  const int S = fk_slices(nrep, ndat, K, g_ncu);
+  const size_t need = S > 1 ? (size_t)S * nrep * ndat * sizeof(double) : 0;
+  if (need > g_fk_ws_bytes) {
+    // the stream's earlier work may still read the old buffer
+    hipError_t e = g_fk_ws ? hipStreamSynchronize((hipStream_t)stream) : hipSuccess;
+    if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+    if (g_fk_ws) (void)hipFree(g_fk_ws);
+    g_fk_ws = nullptr;
+    g_fk_ws_bytes = 0;
+    e = hipMalloc(&g_fk_ws, need);
+    if (e != hipSuccess) return fail_hip(e, "hipMalloc(fk workspace)");
+    g_fk_ws_bytes = need;
+  }
+  hipError_t e = launch_fk_contract(pdf, fk, nrep, ndat, K, out, S, static_cast<double*>(g_fk_ws),
+                                    (hipStream_t)stream);
   if (e != hipSuccess) return fail_hip(e, "launch fk contraction");
   return PDF_OK;
 }
@@ -1463,6 +1493,9 @@ extern "C" int pdf_shutdown(void) {
   g_surs.clear();
   if (g_nerr) (void)hipFree(g_nerr);
   g_nerr = nullptr;
+  if (g_fk_ws) (void)hipFree(g_fk_ws);
+  g_fk_ws = nullptr;
+  g_fk_ws_bytes = 0;
   g_init = false;
   return PDF_OK;
 }

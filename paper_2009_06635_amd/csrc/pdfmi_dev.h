@@ -94,12 +94,15 @@ struct LaunchCfg {
 struct AlphasDev {
   int n;                   // knots
   int nseg;
+  int nhints;              // search hints (all segments)
   int seg_lo[kMaxSeg];     // first knot index of each segment
   int seg_hi[kMaxSeg];     // last knot index of each segment
   double seg_first[kMaxSeg];
+  HintAxis seg_hint[kMaxSeg];  // knot-search hints of each segment (off < 0: binary search)
   const double* knots;     // device, n
   const double* vals;      // device, n
   const CellCoef* cells;   // device, cell j = [knot j, knot j+1] (within a segment)
+  const short* hints;      // device, nhints
 };
 
 }  // namespace pdfmi

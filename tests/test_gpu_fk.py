@@ -31,7 +31,8 @@ def check(pdf, table, out):
 
 
 @pytest.mark.parametrize("nrep,ndat,K", [(1, 1, 1), (1, 1, 0), (3, 5, 7), (63, 64, 31), (64, 65, 32), (65, 63, 33),
-                                         (130, 100, 1000), (400, 257, 3 * 13 * 11)])
+                                         (130, 100, 1000), (400, 257, 3 * 13 * 11), (70, 70, 20000),
+                                         (5, 300, 31395)])
 def test_contract_matches_oracle(nrep, ndat, K):
     rng = np.random.default_rng(nrep * 1000 + ndat + K)
     pdf = rng.normal(size=(nrep, K))

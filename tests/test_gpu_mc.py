@@ -157,3 +157,25 @@ def test_fused_large_grid_reads_global():
             assert s.view(np.uint64)[0] == s_ref.view(np.uint64)[0], (f32, s, s_ref)
     finally:
         pdfmi.unload(m)
+
+
+@pytest.mark.parametrize("P", [1, 13, 40, 64])
+@pytest.mark.parametrize("f32", [False, True])
+def test_chunk_sum_any_width(P, f32):
+    """Widths that stage rows in LDS and widths that read them directly."""
+    rng = np.random.default_rng(P + 100 * f32)
+    n = 5000
+    a = rng.normal(size=(n, P))
+    b = rng.normal(size=(n, P))
+    w = rng.uniform(0.1, 0.3, n)
+    if f32:
+        a, b = a.astype(np.float32), b.astype(np.float32)
+    ta = torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    tb = torch.from_numpy(np.ascontiguousarray(b)).to(DEV)
+    s1 = pdfmi.mc_chunk_sum(ta, tb, dev(w)).item()
+    s2 = pdfmi.mc_chunk_sum(ta, tb, dev(w)).item()
+    assert s1 == s2
+    terms = w * np.sum(a.astype(np.float64) * b.astype(np.float64), axis=1)
+    ref = math.fsum(terms)
+    scale = math.fsum(np.abs(w) * np.sum(np.abs(a.astype(np.float64) * b.astype(np.float64)), axis=1))
+    assert abs(s1 - ref) <= 1e-12 * scale
