@@ -100,9 +100,19 @@ struct PointInfo {
   int pad;
 };
 
+// A point's record: weights and location side by side (80 bytes in FP64,
+// 48 in FP32), so that the 9-16 different records one phase-2 load
+// instruction reads fall in different LDS banks.
+template <typename T>
+struct PointRec {
+  T w[4];
+  T v[4];
+  PointInfo info;
+};
+
 template <typename T>
 __host__ __device__ constexpr size_t wave_record_bytes() {
-  return (size_t)kWave * (8 * sizeof(T) + 16 + sizeof(PointInfo));
+  return (size_t)kWave * (sizeof(PointRec<T>) + 16);
 }
 
 // One wave's 64-point tile [pbeg, pbeg + tp): phase 1 (one lane per point,
@@ -124,10 +134,8 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, 
                                           double xv, double qv, int tp, T* __restrict__ obase,
                                           unsigned long long* __restrict__ nerr, double invL01,
                                           unsigned char* rec, int lane) {
-  T* sw = reinterpret_cast<T*>(rec);                       // [64][4]
-  T* sv = sw + kWave * 4;                                  // [64][4]
-  double* sp = reinterpret_cast<double*>(sv + kWave * 4);  // [64][2]
-  PointInfo* sinfo = reinterpret_cast<PointInfo*>(sp + 2 * kWave);
+  PointRec<T>* srec = reinterpret_cast<PointRec<T>*>(rec);        // [64]
+  double* sp = reinterpret_cast<double*>(srec + kWave);           // [64][2] extrapolation parameters
   const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
   const int rowb = Pp * (int)sizeof(T);  // bytes between consecutive Q^2 knots
   constexpr int kSlow = kLowX | kLowQ | kHighQ;
@@ -141,14 +149,16 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, 
     const PointLoc L = locate_point<T>(m, tb, xv, qv, w, v);
     bad = L.mode & kInvalid;
     slow = L.mode & kSlow;
+    PointRec<T> r;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      sw[lane * 4 + a] = w[a];
-      sv[lane * 4 + a] = v[a];
+      r.w[a] = w[a];
+      r.v[a] = v[a];
     }
+    r.info = PointInfo{L.base * (int)sizeof(T), L.sa * (int)sizeof(T), L.mode, 0};
+    srec[lane] = r;
     sp[2 * lane] = L.p0;
     sp[2 * lane + 1] = L.p1;
-    sinfo[lane] = PointInfo{L.base * (int)sizeof(T), L.sa * (int)sizeof(T), L.mode, 0};
   }
   const unsigned long long bal = __ballot(bad);
   if (bal && lane == 0) atomicAdd(nerr, (unsigned long long)__popcll(bal));
@@ -163,13 +173,13 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, 
   const int nev = tp * NE;
   int p = e_p0, j = e_j0;
   for (int e = lane; e < nev; e += kWave) {
-    const PointInfo pi = sinfo[p];
+    const PointInfo pi = srec[p].info;
     if (!(pi.mode & kSlow)) {
       T w[4], v[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        w[a] = sw[p * 4 + a];
-        v[a] = sv[p * 4 + a];
+        w[a] = srec[p].w[a];
+        v[a] = srec[p].v[a];
       }
       const bool inv = pi.mode & kInvalid;
       int c0;       // first output column of this entry
@@ -235,9 +245,10 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, 
   while (slow_mask) {
     const int q = __builtin_ctzll(slow_mask);
     slow_mask &= slow_mask - 1;
-    const PointInfo pi = sinfo[q];
-    const Wts wt{(double)sw[q * 4], (double)sw[q * 4 + 1], (double)sw[q * 4 + 2], (double)sw[q * 4 + 3],
-                 (double)sv[q * 4], (double)sv[q * 4 + 1], (double)sv[q * 4 + 2], (double)sv[q * 4 + 3]};
+    const PointInfo pi = srec[q].info;
+    const PointRec<T>& rq = srec[q];
+    const Wts wt{(double)rq.w[0], (double)rq.w[1], (double)rq.w[2], (double)rq.w[3],
+                 (double)rq.v[0], (double)rq.v[1], (double)rq.v[2], (double)rq.v[3]};
     for (int jj = lane; jj < R; jj += kWave) {
       const int col = G == 1 ? scol[jj] : jj;
       T val = (T)0;
