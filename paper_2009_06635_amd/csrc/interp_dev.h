@@ -59,11 +59,14 @@ __device__ __forceinline__ void stencil_weights(double u64, const CellCoef& c, i
   const T h10 = ((u - (T)2) * u + (T)1) * u;
   const T h01 = ((T)3 - (T)2 * u) * u2;
   const T h11 = (u - (T)1) * u2;
+  const bool L = c.hl >= 0.0, R = c.hr >= 0.0;
+  const double am1 = L ? -c.hl : 0.0, a0 = L ? c.hl - 0.5 : -1.0, a1 = L ? 0.5 : 1.0;
+  const double b0 = R ? -0.5 : -1.0, b1 = R ? 0.5 - c.hr : 1.0, b2 = R ? c.hr : 0.0;
   T r[4];
-  r[0] = h10 * (T)c.am1;
-  r[1] = h00 + h10 * (T)c.a0 + h11 * (T)c.b0;
-  r[2] = h01 + h10 * (T)c.a1 + h11 * (T)c.b1;
-  r[3] = h11 * (T)c.b2;
+  r[0] = h10 * (T)am1;
+  r[1] = h00 + h10 * (T)a0 + h11 * (T)b0;
+  r[2] = h01 + h10 * (T)a1 + h11 * (T)b1;
+  r[3] = h11 * (T)b2;
   out[0] = d == 0 ? r[1] : (d == 1 ? r[0] : (T)0);
   out[1] = d == 0 ? r[2] : (d == 1 ? r[1] : r[0]);
   out[2] = d == 0 ? r[3] : (d == 1 ? r[2] : r[1]);

@@ -140,26 +140,8 @@ void cell_coefs(const double* t, int n, CellCoef* out) {
     c.inv_t0 = 1.0 / t[i];
     c.invD = 1.0 / D[i];
     const bool L = i > 0, R = i + 1 < n - 1;
-    if (L) {
-      const double rl = D[i] / D[i - 1];
-      c.am1 = -0.5 * rl;
-      c.a0 = 0.5 * rl - 0.5;
-      c.a1 = 0.5;
-    } else {
-      c.am1 = 0.0;
-      c.a0 = -1.0;
-      c.a1 = 1.0;
-    }
-    if (R) {
-      const double rr = D[i] / D[i + 1];
-      c.b0 = -0.5;
-      c.b1 = 0.5 - 0.5 * rr;
-      c.b2 = 0.5 * rr;
-    } else {
-      c.b0 = -1.0;
-      c.b1 = 1.0;
-      c.b2 = 0.0;
-    }
+    c.hl = L ? 0.5 * (D[i] / D[i - 1]) : -1.0;
+    c.hr = R ? 0.5 * (D[i] / D[i + 1]) : -1.0;
     out[i] = c;
   }
 }

@@ -22,13 +22,18 @@ enum : int { kLowX = 1, kLowQ = 2, kHighQ = 4, kInvalid = 8, kXHigh = 16 };
 // where (am1,a0,a1) expand Delta_i * slope_i and (b0,b1,b2) expand
 // Delta_i * slope_{i+1} over the knot values (finite-difference slopes:
 // mean of adjacent secants inside the table, the one secant at its ends).
+// Inside the table they depend only on hl = Delta_i / (2 Delta_{i-1}) and
+// hr = Delta_i / (2 Delta_{i+1}):
+//   am1 = -hl, a0 = hl - 1/2, a1 = 1/2;   b0 = -1/2, b1 = 1/2 - hr, b2 = hr;
+// at the table's first cell (no left neighbour, hl < 0 marks it)
+//   am1 = 0, a0 = -1, a1 = 1, and at its last cell (hr < 0)
+//   b0 = -1, b1 = 1, b2 = 0.  48 bytes: three 16-byte LDS reads per cell.
 struct CellCoef {
   double t0;      // knot i
   double t1;      // knot i+1
   double inv_t0;  // 1 / knot i
   double invD;    // 1 / ln(t1 / t0)
-  double am1, a0, a1;
-  double b0, b1, b2;
+  double hl, hr;  // half ratios of the neighbouring cells' log-widths, or -1 at a table edge
 };
 
 // Knot search by bucket hints: positive doubles order like their IEEE-754
