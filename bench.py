@@ -76,7 +76,7 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="skip the variants")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM byte counters)")
-    ap.add_argument("--sur-steps", type=int, default=2000)
+    ap.add_argument("--sur-steps", type=int, default=20000)
     ap.add_argument("--mc-chunks", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -1047,10 +1047,12 @@ int sur_ensure_batch(Surrogate& S, int B) {
   S.bmem = nullptr;
   const int H = sur_hidden(), O = sur_out_width();
   // floats: h1,h2,h3,dh,dz (B*H each) + y,dy,sq (B*O each); shorts: h1b,h2b,h3b,dzb (B*H), dyb (B*O)
-  const size_t nf = (size_t)B * (5 * H + 3 * O), ns = (size_t)B * (4 * H + O);
+  const size_t nw = (size_t)64 * H * H;  // split-reduction partials
+  const size_t nf = (size_t)B * (5 * H + 3 * O) + nw, ns = (size_t)B * (4 * H + O);
   hipError_t e = hipMalloc(&S.bmem, nf * 4 + ns * 2 + 256);
   if (e != hipSuccess) return fail_hip(e, "hipMalloc(surrogate batch)");
   float* f = static_cast<float*>(S.bmem);
+  S.b.wpart = f; f += nw;
   S.b.h1 = f; f += (size_t)B * H;
   S.b.h2 = f; f += (size_t)B * H;
   S.b.h3 = f; f += (size_t)B * H;

@@ -165,6 +165,7 @@ struct SurBufs {
   unsigned short *h1b, *h2b, *h3b, *dyb, *dzb;
   float* loss;              // [1]
   float* partial;           // [256]
+  float* wpart;             // split-reduction partial sums, 64 slices x 64 x 64
 };
 
 }  // namespace pdfmi

@@ -56,21 +56,27 @@ __device__ __forceinline__ float tanh_f(float z) {
 // M, N multiples of 16; K any (zero padded to 32).  One wave per 16x16 tile,
 // K walked in order (fixed summation order).  Writes FP32 C (ldc) and, if
 // Cb != null, its BF16 copy.
+// With gridDim.y > 1 workgroup y covers k in [y kchunk, (y + 1) kchunk) and
+// writes its partial tile to C + y M ldc (the slices are added in order by
+// k_sum_slices); bias and activation then belong to the unsplit form only.
 __global__ __launch_bounds__(64) void k_gemm_bf16(const unsigned short* __restrict__ A, int sam, int sak,
                                                   const unsigned short* __restrict__ B, int sbk, int sbn,
                                                   float* __restrict__ C, int ldc, unsigned short* __restrict__ Cb,
-                                                  int M, int N, int K, const float* __restrict__ bias, int act) {
+                                                  int M, int N, int K, const float* __restrict__ bias, int act,
+                                                  int kchunk) {
   const int tn = N / 16;
   const int m0 = (blockIdx.x / tn) * 16, n0 = (blockIdx.x % tn) * 16;
   const int l = threadIdx.x, r = l & 15, g = l >> 4;
+  const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+  C += (int64_t)blockIdx.y * M * ldc;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int k0 = kb; k0 < ke; k0 += 32) {
     bf16x8 a, b;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = k0 + 8 * g + i;
-      const unsigned short av = k < K ? A[(int64_t)(m0 + r) * sam + (int64_t)k * sak] : (unsigned short)0;
-      const unsigned short bv = k < K ? B[(int64_t)k * sbk + (int64_t)(n0 + r) * sbn] : (unsigned short)0;
+      const unsigned short av = k < ke ? A[(int64_t)(m0 + r) * sam + (int64_t)k * sak] : (unsigned short)0;
+      const unsigned short bv = k < ke ? B[(int64_t)k * sbk + (int64_t)(n0 + r) * sbn] : (unsigned short)0;
       a[i] = __builtin_bit_cast(__bf16, av);
       b[i] = __builtin_bit_cast(__bf16, bv);
     }
@@ -125,24 +131,28 @@ __global__ void k_tanh_back(const float* __restrict__ dH, const float* __restric
   dZb[i] = bf16_bits(v);
 }
 
-// out[c] = sum_b X[b][c] (sequential in b: fixed order), for c < ncols.
-__global__ void k_col_sum(const float* __restrict__ X, int B, int ncols, float* __restrict__ out) {
+// out[y][c] = sum over b in slice y of X[b][c] (sequential in b), for c < ncols;
+// slices of kchunk rows, one per blockIdx.y (added in order afterwards).
+__global__ void k_col_sum(const float* __restrict__ X, int B, int ncols, int kchunk, float* __restrict__ out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncols) return;
+  const int b0 = blockIdx.y * kchunk, b1 = min(B, b0 + kchunk);
   float s = 0.0f;
-  for (int b = 0; b < B; ++b) s += X[(int64_t)b * ncols + c];
-  out[c] = s;
+  for (int b = b0; b < b1; ++b) s += X[(int64_t)b * ncols + c];
+  out[(int64_t)blockIdx.y * ncols + c] = s;
 }
 
-// dW1[j][t] = sum_b dZ1[b][j] in[b][t] (BF16-rounded operands, FP32 sum in b order).
-__global__ void k_dw1(const unsigned short* __restrict__ dZb, const float* __restrict__ in, int B,
+// dW1[j][t] = sum_b dZ1[b][j] in[b][t] (BF16-rounded operands, FP32 sum in b
+// order within a slice of kchunk rows per blockIdx.y; slices added in order).
+__global__ void k_dw1(const unsigned short* __restrict__ dZb, const float* __restrict__ in, int B, int kchunk,
                       float* __restrict__ dW1) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= kH * 2) return;
   const int j = o / 2, t = o % 2;
+  const int b0 = blockIdx.y * kchunk, b1 = min(B, b0 + kchunk);
   float s = 0.0f;
-  for (int b = 0; b < B; ++b) s = fmaf(bf16_float(dZb[(int64_t)b * kH + j]), bf16_float(bf16_bits(in[2 * b + t])), s);
-  dW1[o] = s;
+  for (int b = b0; b < b1; ++b) s = fmaf(bf16_float(dZb[(int64_t)b * kH + j]), bf16_float(bf16_bits(in[2 * b + t])), s);
+  dW1[(int64_t)blockIdx.y * kH * 2 + o] = s;
 }
 
 // Adam step on the FP32 masters, then their BF16 copies.
@@ -390,10 +400,35 @@ size_t sur_batch_floats(int B) { return (size_t)B * (3 * kH + 3 * kO + 2 * kH) ;
 
 static unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// out[i] = sum over slices s = 0..S-1 (in order) of P[s n + i].
+__global__ void k_sum_slices(const float* __restrict__ P, int S, int n, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = P[i];
+  for (int q = 1; q < S; ++q) acc += P[(int64_t)q * n + i];
+  out[i] = acc;
+}
+
+// Long reductions (the weight gradients, K = batch) are split into slices of
+// kSplitK rows so that the few 16x16 output tiles keep many waves busy.
+constexpr int kSplitK = 256;
+constexpr int kMaxSlices = 64;
+
 static void gemm(const unsigned short* A, int sam, int sak, const unsigned short* B, int sbk, int sbn, float* C, int ldc,
-                 unsigned short* Cb, int M, int N, int K, const float* bias, int act, hipStream_t s) {
-  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((M / 16) * (N / 16))), dim3(64), 0, s, A, sam, sak, B, sbk, sbn, C,
-                     ldc, Cb, M, N, K, bias, act);
+                 unsigned short* Cb, int M, int N, int K, const float* bias, int act, float* ws, hipStream_t s) {
+  const unsigned tiles = (unsigned)((M / 16) * (N / 16));
+  int S = (K + kSplitK - 1) / kSplitK;
+  if (S > kMaxSlices) S = kMaxSlices;
+  if (S > 1 && !bias && !act && !Cb && ws && ldc == N) {
+    const int kchunk = ((K + S - 1) / S + 31) / 32 * 32;
+    S = (K + kchunk - 1) / kchunk;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles, (unsigned)S), dim3(64), 0, s, A, sam, sak, B, sbk, sbn, ws, ldc,
+                       nullptr, M, N, K, nullptr, 0, kchunk);
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, s, ws, S, M * N, C);
+    return;
+  }
+  hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles), dim3(64), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, Cb, M, N, K, bias,
+                     act, K);
 }
 
 __global__ void k_sum_partial(const float* __restrict__ x, int64_t n, float* __restrict__ partial) {
@@ -412,6 +447,23 @@ __global__ void k_sum_final(const float* __restrict__ partial, float scale, floa
   }
 }
 
+// Column sums and the first-layer weight gradient over the batch, in row
+// slices added in order (the same slicing as the weight-gradient GEMMs).
+static void col_sum(const float* X, int B, int ncols, float* out, float* ws, hipStream_t s) {
+  const int S = min(kMaxSlices, (B + kSplitK - 1) / kSplitK);
+  const int kchunk = (B + S - 1) / S;
+  hipLaunchKernelGGL(k_col_sum, dim3((unsigned)((ncols + 63) / 64), (unsigned)S), dim3(64), 0, s, X, B, ncols, kchunk,
+                     ws);
+  hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, ws, S, ncols, out);
+}
+
+static void dw1(const unsigned short* dZb, const float* in, int B, float* out, float* ws, hipStream_t s) {
+  const int S = min(kMaxSlices, (B + kSplitK - 1) / kSplitK);
+  const int kchunk = (B + S - 1) / S;
+  hipLaunchKernelGGL(k_dw1, dim3(1, (unsigned)S), dim3(128), 0, s, dZb, in, B, kchunk, ws);
+  hipLaunchKernelGGL(k_sum_slices, dim3(1), dim3(256), 0, s, ws, S, kH * 2, out);
+}
+
 // One forward + backward pass on a batch (inputs in[B][2], targets T[B][kO]):
 // gradients into buf.G, loss (mean squared error) into buf.loss.
 hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s) {
@@ -420,16 +472,16 @@ hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* 
   const unsigned short* W4 = b.Pb + kOffW4;
   hipLaunchKernelGGL(k_layer1, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, in, b.P, B, b.h1, b.h1b);
   // z = h W^T + b: A(m=b,k) = h[b][k]; B(k,n) = W[n][k]
-  gemm(b.h1b, kH, 1, W2, 1, kH, b.h2, kH, b.h2b, B, kH, kH, b.P + kOffB2, 1, s);
-  gemm(b.h2b, kH, 1, W3, 1, kH, b.h3, kH, b.h3b, B, kH, kH, b.P + kOffB3, 1, s);
-  gemm(b.h3b, kH, 1, W4, 1, kH, b.y, kO, nullptr, B, kO, kH, b.P + kOffB4, 0, s);
+  gemm(b.h1b, kH, 1, W2, 1, kH, b.h2, kH, b.h2b, B, kH, kH, b.P + kOffB2, 1, b.wpart, s);
+  gemm(b.h2b, kH, 1, W3, 1, kH, b.h3, kH, b.h3b, B, kH, kH, b.P + kOffB3, 1, b.wpart, s);
+  gemm(b.h3b, kH, 1, W4, 1, kH, b.y, kO, nullptr, B, kO, kH, b.P + kOffB4, 0, b.wpart, s);
   hipLaunchKernelGGL(k_loss_grad, dim3(nb((int64_t)B * kO, 256)), dim3(256), 0, s, b.y, T, B, b.dy, b.dyb, b.sq);
   hipLaunchKernelGGL(k_sum_partial, dim3(1), dim3(256), 0, s, b.sq, (int64_t)B * kO, b.partial);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, s, b.partial, 1.0f / (float)((int64_t)B * kO), b.loss);
   // layer 4: dW4[o][i] = sum_b dy[b][o] h3[b][i]; db4; dh3 = dy W4
-  gemm(b.dyb, 1, kO, b.h3b, kH, 1, b.G + kOffW4, kH, nullptr, kO, kH, B, nullptr, 0, s);
-  hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(64), 0, s, b.dy, B, kO, b.G + kOffB4);
-  gemm(b.dyb, kO, 1, W4, kH, 1, b.dh, kH, nullptr, B, kH, kO, nullptr, 0, s);
+  gemm(b.dyb, 1, kO, b.h3b, kH, 1, b.G + kOffW4, kH, nullptr, kO, kH, B, nullptr, 0, b.wpart, s);
+  col_sum(b.dy, B, kO, b.G + kOffB4, b.wpart, s);
+  gemm(b.dyb, kO, 1, W4, kH, 1, b.dh, kH, nullptr, B, kH, kO, nullptr, 0, b.wpart, s);
   // layers 3 and 2
   const float* Hs[3] = {b.h1, b.h2, b.h3};
   const unsigned short* Hbs[3] = {b.h1b, b.h2b, b.h3b};
@@ -438,16 +490,16 @@ hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* 
   for (int L = 1; L >= 0; --L) {  // L = 1: layer 3 (input h2, output h3); L = 0: layer 2 (h1 -> h2)
     hipLaunchKernelGGL(k_tanh_back, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, b.dh, Hs[L + 1],
                        (int64_t)B * kH, b.dz, b.dzb);
-    gemm(b.dzb, 1, kH, Hbs[L], kH, 1, b.G + offW[L], kH, nullptr, kH, kH, B, nullptr, 0, s);
-    hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(64), 0, s, b.dz, B, kH, b.G + offB[L]);
+    gemm(b.dzb, 1, kH, Hbs[L], kH, 1, b.G + offW[L], kH, nullptr, kH, kH, B, nullptr, 0, b.wpart, s);
+    col_sum(b.dz, B, kH, b.G + offB[L], b.wpart, s);
     // dh_in = dz W: A(m=b, k=j) = dz[b][j]; B(k=j, n=i) = W[j][i]
-    gemm(b.dzb, kH, 1, Ws[L], kH, 1, b.dh, kH, nullptr, B, kH, kH, nullptr, 0, s);
+    gemm(b.dzb, kH, 1, Ws[L], kH, 1, b.dh, kH, nullptr, B, kH, kH, nullptr, 0, b.wpart, s);
   }
   // layer 1
   hipLaunchKernelGGL(k_tanh_back, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, b.dh, b.h1, (int64_t)B * kH, b.dz,
                      b.dzb);
-  hipLaunchKernelGGL(k_dw1, dim3(1), dim3(128), 0, s, b.dzb, in, B, b.G + kOffW1);
-  hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(64), 0, s, b.dz, B, kH, b.G + kOffB1);
+  dw1(b.dzb, in, B, b.G + kOffW1, b.wpart, s);
+  col_sum(b.dz, B, kH, b.G + kOffB1, b.wpart, s);
   return hipGetLastError();
 }
 
