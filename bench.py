@@ -3,12 +3,14 @@
 Workload of the headline line (one "step" = one pass of the hot path over one
 batch): 1e7 query points of the three-sub-grid, 13-flavour synthetic set (196
 x knots, 3 x 17 Q^2 knots split at the 1.51 / 4.92 GeV thresholds, 1% of the
-points outside the grid), all flavours at every point in FP64 (pdf_xfxq2) plus
-alpha_s at every point (pdf_alphas_q2).  Inputs are resident in device memory
-before the timed region.  `value` counts PDF evaluations (points x flavours).
+points outside the grid), all flavours and alpha_s at every point in FP64, in
+one launch (pdf_xfxq2_alphas).  Inputs are resident in device memory before
+the timed region.  `value` counts PDF evaluations (points x flavours).
 
 "variants" reports, on the same clock:
-  f32        FP32 bulk arithmetic on the headline workload (pdf_xfxq2_f32)
+  f32        FP32 bulk arithmetic on the headline workload
+             (pdf_xfxq2_alphas_f32)
+  separate   the headline step as two launches (pdf_xfxq2, pdf_alphas_q2)
   small      the 1e5-point one-sub-grid workload (latency-bound), FP64
   batched    101 members, 200 requests (log-normal sizes, random flavour
              subsets), one persistent hipGraph-replayed launch with autotuned
@@ -23,8 +25,8 @@ before the timed region.  `value` counts PDF evaluations (points x flavours).
              shape, its GPU seconds quoted as context), then the FP64
              matrix-core contraction with a 1024-row synthetic FK table
 The dominant kernel's roofline uses its algorithmic bytes (16 B of (x, Q^2) in
-+ 8 B per output value) over its average duration measured with HIP events on
-the launch stream.  cpu_baseline times the FP64 oracle on the host cores.
++ 8 B per output value, PDF or alpha_s) over its average duration measured
+with HIP events on the launch stream.  cpu_baseline times the FP64 oracle on the host cores.
 """
 import argparse
 import hashlib
@@ -146,15 +148,21 @@ def main():
     def step64(e):
         if e:
             e[0].record()
-        pdfmi.xfxq2(member, g.pids, xd, qd, out=out64)
+        pdfmi.xfxq2_alphas(member, g.pids, xd, qd, out=out64, alphas_out=aout)
         if e:
             e[1].record()
-        pdfmi.alphas_q2(qd, out=aout)
 
     def step32(e):
         if e:
             e[0].record()
-        pdfmi.xfxq2_f32(member, g.pids, xd, qd, out=out32)
+        pdfmi.xfxq2_alphas(member, g.pids, xd, qd, out=out32, alphas_out=aout, f32=True)
+        if e:
+            e[1].record()
+
+    def step_separate(e):
+        if e:
+            e[0].record()
+        pdfmi.xfxq2(member, g.pids, xd, qd, out=out64)
         if e:
             e[1].record()
         pdfmi.alphas_q2(qd, out=aout)
@@ -163,8 +171,8 @@ def main():
     wall64, k64 = timed(step64, args.steps, args.warmup)
     wall32, k32 = timed(step32, args.steps, args.warmup)
     evals = args.n * P
-    bytes64 = args.n * (16 + 8 * P)
-    bytes32 = args.n * (16 + 4 * P)
+    bytes64 = args.n * (16 + 8 * P + 8)
+    bytes32 = args.n * (16 + 4 * P + 8)
     ach64 = bytes64 / (k64 * 1e-3) / 1e9
     ach32 = bytes32 / (k32 * 1e-3) / 1e9
     res = {
@@ -185,7 +193,7 @@ def main():
                    "subgrids": 3, "x_knots": 196, "q2_knots_per_subgrid": 17},
         "roofline": {"bound": "hbm", "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach64 / HBM_PEAK_GBS, "traffic": measured_traffic("xfxq2_f64"),
-                     "kernel": "k_xfxq2<double> (pdf_xfxq2)", "kernel_ms": k64,
+                     "kernel": "k_xfxq2<double> with alpha_s output (pdf_xfxq2_alphas)", "kernel_ms": k64,
                      "algorithmic_bytes_per_launch": bytes64},
         "variants": {
             "f64_kernel_evals_per_s": evals / (k64 * 1e-3),
@@ -200,6 +208,11 @@ def main():
 
     if not args.only_headline:
         import oracle
+
+        log("timing the headline step as two launches")
+        wall_sep, k_sep = timed(step_separate, args.steps, args.warmup)
+        V["separate"] = {"ms_per_step": wall_sep * 1e3, "xfxq2_kernel_ms": k_sep,
+                         "fused_speedup": wall_sep / wall64}
 
         def rel_stats(o, ora, floor=1e-8):
             ok = np.abs(ora) > floor

@@ -291,6 +291,23 @@ int pdf_mc_chunk_sum_f32(const float* xf1, const float* xf2, int32_t n_pids,
                          double* sum_out, pdf_stream_t stream);
 
 /*
+ * PDFs and alpha_s at the same points in one pass (the shape of an
+ * integrand, which needs both at every phase-space point; sections 2.2 and
+ * 2.3): out as pdf_xfxq2 (or pdf_xfxq2_f32), alphas_out[i] = alpha_s(q2[i])
+ * as pdf_alphas_q2 -- both bit-identical to the separate calls; q2 is read
+ * once.  alphas_out: device [n].  Invalid points add to pdf_error_count as
+ * the two separate calls would (once for x*f, once for alpha_s).  Errors as
+ * pdf_xfxq2, plus PDF_ERR_ARG for a null alphas_out (n > 0) and
+ * PDF_ERR_STATE when no alpha_s table is loaded.  Asynchronous on stream.
+ */
+int pdf_xfxq2_alphas(int32_t member, const int32_t* pids, int32_t n_pids,
+                     const double* x, const double* q2, int64_t n, double* out,
+                     double* alphas_out, pdf_stream_t stream);
+int pdf_xfxq2_alphas_f32(int32_t member, const int32_t* pids, int32_t n_pids,
+                         const double* x, const double* q2, int64_t n, float* out,
+                         double* alphas_out, pdf_stream_t stream);
+
+/*
  * LHAPDF6 data files (section 2: the set folders are loaded directly, with
  * the same layout as LHAPDF).  Host-only parsing; no device work except the
  * final pdf_load_grid / pdf_load_alphas of the load calls.

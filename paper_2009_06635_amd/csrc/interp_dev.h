@@ -78,6 +78,41 @@ __device__ __forceinline__ double cell_u(double v, const CellCoef& c) {
   return v == c.t0 ? 0.0 : (v == c.t1 ? 1.0 : log(v * c.inv_t0) * c.invD);
 }
 
+// alpha_s at one Q^2 from the table (knots sk, values sv, cells sc); NaN for
+// Q^2 <= 0 or non-finite.
+__device__ __forceinline__ double alphas_point(const AlphasDev& A, const double* sk, const double* sv,
+                                               const CellCoef* sc, const short* sh, double q2) {
+  const bool valid = q2 > 0.0 && q2 < INFINITY;
+  if (!valid) return NAN;
+  if (q2 < sk[0]) return sv[0];
+  if (q2 > sk[A.n - 1]) return sv[A.n - 1];
+  int s = 0;
+  for (int j = 1; j < A.nseg; ++j)
+    if (A.seg_first[j] <= q2) s = j;
+  const int lo = A.seg_lo[s], hi = A.seg_hi[s];
+  const int m = hi - lo + 1;
+  const int c = lo + find_cell_hint(sk + lo, m, q2, A.seg_hint[s], sh);
+  const CellCoef cc = sc[c];
+  const int m4 = m < 4 ? m : 4;
+  const int st = min(max(c - 1, lo), hi - m4 + 1);
+  double w[4];
+  stencil_weights<double>(cell_u(q2, cc), cc, c - st, w);
+  double acc = w[0] * sv[st];
+  for (int a = 1; a < m4; ++a) acc = fma(w[a], sv[st + a], acc);
+  return acc;
+}
+
+
+// The alpha_s table as a kernel reads it (staged in LDS) and where a fused
+// evaluation writes alpha_s: out == nullptr means no alpha_s output.
+struct AsView {
+  const double* k;
+  const double* v;
+  const CellCoef* c;
+  const short* h;
+  double* out;
+};
+
 struct PointLoc {
   int mode;      // region bits | kXHigh | (anchor row << 8) for high Q^2
   int k, ix, iq;

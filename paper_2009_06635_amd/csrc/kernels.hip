@@ -100,6 +100,8 @@ struct PointInfo {
   int pad;
 };
 
+__device__ constexpr AlphasDev kNoAlphas{};
+
 // A point's record: weights and location side by side (80 bytes in FP64,
 // 48 in FP32), so that the 9-16 different records one phase-2 load
 // instruction reads fall in different LDS banks.
@@ -128,12 +130,12 @@ __host__ __device__ constexpr size_t wave_record_bytes() {
 // column gets the same value twice).  Reading it from LDS, groups start at
 // G*j (16-byte aligned LDS reads; rows are zero-padded to a multiple of G)
 // and the last group stores only the columns below R.
-template <typename T, bool kLdsGrid, int G, bool kOverlap = !kLdsGrid>
+template <typename T, bool kLdsGrid, int G, bool kAlphas = false, bool kOverlap = !kLdsGrid>
 __device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, const int* scol, int R,
                                           const T* sgrid, const T* __restrict__ gvals, uint32_t gbytes,
                                           double xv, double qv, int tp, T* __restrict__ obase,
                                           unsigned long long* __restrict__ nerr, double invL01,
-                                          unsigned char* rec, int lane) {
+                                          unsigned char* rec, int lane, const AlphasDev& A, const AsView& av) {
   PointRec<T>* srec = reinterpret_cast<PointRec<T>*>(rec);        // [64]
   double* sp = reinterpret_cast<double*>(srec + kWave);           // [64][2] extrapolation parameters
   const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
@@ -143,6 +145,12 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, 
   const int NE = G == 1 ? R : (R + G - 1) / G;
   const int e_p0 = lane / NE, e_j0 = lane - (lane / NE) * NE;
   const int e_dp = kWave / NE, e_dj = kWave - (kWave / NE) * NE;
+  if constexpr (kAlphas) {  // alpha_s at the same points (fused evaluation), counted like pdf_alphas_q2
+    const bool qbad = lane < tp && !(qv > 0.0 && qv < INFINITY);
+    if (lane < tp) av.out[lane] = alphas_point(A, av.k, av.v, av.c, av.h, qv);
+    const unsigned long long qb = __ballot(qbad);
+    if (qb && lane == 0) atomicAdd(nerr, (unsigned long long)__popcll(qb));
+  }
   bool bad = false, slow = false;
   if (lane < tp) {
     T w[4], v[4];
@@ -272,10 +280,11 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, 
 // LDS layout of k_xfxq2 and k_batched: [location tables][column map][per-wave
 // records][grid values], the tables only when they are staged (kLdsTables)
 // and the grid only when it is staged (kLdsGrid, which implies kLdsTables).
-template <typename T, bool kLdsGrid, int G, int BS, bool kLdsTables>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PDFMI_WAVES_PER_EU)))
+template <typename T, bool kLdsGrid, int G, int BS, bool kLdsTables, bool kAlphas>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kAlphas ? 4 : PDFMI_WAVES_PER_EU)))
 void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X, const double* __restrict__ Q2, int64_t n,
-             T* __restrict__ out, unsigned long long* __restrict__ nerr, int lds_grid_elems, double invL01) {
+             T* __restrict__ out, unsigned long long* __restrict__ nerr, int lds_grid_elems, double invL01,
+             AlphasDev A, double* __restrict__ aout) {
   static_assert(kLdsTables || !kLdsGrid, "a staged grid needs staged tables");
   constexpr int kWaves = BS / kWave;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -283,6 +292,26 @@ void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X, const double
   int* scol = reinterpret_cast<int*>(smem + (kLdsTables ? m.tbl_bytes : 0));
   unsigned char* srec = reinterpret_cast<unsigned char*>(scol + kMaxReq);
   T* sgrid = reinterpret_cast<T*>(srec + kWaves * wave_record_bytes<T>());
+  // alpha_s table (fused alpha_s output only), after the staged grid
+  unsigned char* sas = reinterpret_cast<unsigned char*>(sgrid) + (kLdsGrid ? (size_t)lds_grid_elems * sizeof(T) : 0);
+  const int an2 = (A.n + 1) & ~1;
+  AsView av{reinterpret_cast<const double*>(sas), reinterpret_cast<const double*>(sas) + an2,
+            reinterpret_cast<const CellCoef*>(reinterpret_cast<const double*>(sas) + 2 * an2),
+            reinterpret_cast<const short*>(reinterpret_cast<const CellCoef*>(reinterpret_cast<const double*>(sas) +
+                                                                               2 * an2) + an2),
+            nullptr};
+  if constexpr (kAlphas) {
+    double* k = const_cast<double*>(av.k);
+    double* v = const_cast<double*>(av.v);
+    CellCoef* c = const_cast<CellCoef*>(av.c);
+    short* h = const_cast<short*>(av.h);
+    for (int i = threadIdx.x; i < A.n; i += BS) {
+      k[i] = A.knots[i];
+      v[i] = A.vals[i];
+      c[i] = A.cells[i];
+    }
+    for (int i = threadIdx.x; i < A.nhints; i += BS) h[i] = A.hints[i];
+  }
 
   if constexpr (kLdsTables) {
     const uint4* src = reinterpret_cast<const uint4*>(m.tables);
@@ -319,8 +348,9 @@ void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X, const double
       xn = X[nxt];
       qn = Q2[nxt];
     }
-    wave_tile<T, kLdsGrid, G>(m, tb, scol, R, sgrid, gvals, gbytes, xc, qc, tp, out + pbeg * R, nerr, invL01, rec,
-                              lane);
+    if constexpr (kAlphas) av.out = aout + pbeg;
+    wave_tile<T, kLdsGrid, G, kAlphas>(m, tb, scol, R, sgrid, gvals, gbytes, xc, qc, tp, out + pbeg * R, nerr, invL01, rec,
+                              lane, A, av);
     xc = xn;
     qc = qn;
   }
@@ -347,32 +377,8 @@ __global__ __launch_bounds__(256) void k_locate(MemberDev m, const double* __res
 // (knots, values, cell coefficients) is staged in LDS once per workgroup.
 constexpr int kAlphasMaxKnots = 256;
 
-// alpha_s at one Q^2 from the table (knots sk, values sv, cells sc); NaN for
-// Q^2 <= 0 or non-finite.
-__device__ __forceinline__ double alphas_point(const AlphasDev& A, const double* sk, const double* sv,
-                                               const CellCoef* sc, const short* sh, double q2) {
-  const bool valid = q2 > 0.0 && q2 < INFINITY;
-  if (!valid) return NAN;
-  if (q2 < sk[0]) return sv[0];
-  if (q2 > sk[A.n - 1]) return sv[A.n - 1];
-  int s = 0;
-  for (int j = 1; j < A.nseg; ++j)
-    if (A.seg_first[j] <= q2) s = j;
-  const int lo = A.seg_lo[s], hi = A.seg_hi[s];
-  const int m = hi - lo + 1;
-  const int c = lo + find_cell_hint(sk + lo, m, q2, A.seg_hint[s], sh);
-  const CellCoef cc = sc[c];
-  const int m4 = m < 4 ? m : 4;
-  const int st = min(max(c - 1, lo), hi - m4 + 1);
-  double w[4];
-  stencil_weights<double>(cell_u(q2, cc), cc, c - st, w);
-  double acc = w[0] * sv[st];
-  for (int a = 1; a < m4; ++a) acc = fma(w[a], sv[st + a], acc);
-  return acc;
-}
-
-// One thread per group of 4 consecutive points (32-byte loads and stores,
-// four independent evaluations in flight per thread).
+// alpha_s(Q^2) at n points, the table and its search hints staged in LDS;
+// four independent evaluations in flight per lane.
 constexpr int kAlphasMaxHints = 2048;
 
 __global__ __launch_bounds__(256) void k_alphas(AlphasDev A, const double* __restrict__ Q2, int64_t n,
@@ -388,37 +394,55 @@ __global__ __launch_bounds__(256) void k_alphas(AlphasDev A, const double* __res
   }
   for (int i = threadIdx.x; i < A.nhints; i += 256) sh[i] = A.hints[i];
   __syncthreads();
-  const int64_t ngroups = (n + 3) / 4;
-  for (int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gi < ngroups;
-       gi += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i0 = gi * 4;
-    double q[4], r[4];
-    int bad = 0;
+  // each wave takes 256 consecutive points per step, lane l the points l + 64 j
+  // (j = 0..3): every load and store instruction covers 512 contiguous bytes.
+  // The next step's Q^2 are loaded before the current step is evaluated.
+  const int lane = threadIdx.x & 63;
+  const int64_t nchunks = (n + 255) / 256;
+  const int64_t wstride = (int64_t)gridDim.x * (256 / 64);
+  int64_t c = (int64_t)blockIdx.x * (256 / 64) + (threadIdx.x >> 6);
+  double q[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) q[j] = i0 + j < n ? Q2[i0 + j] : 1.0;
+  for (int j = 0; j < 4; ++j) {
+    const int64_t i = c * 256 + j * 64 + lane;
+    q[j] = i < n ? Q2[i] : 1.0;
+  }
+  unsigned long long cnt = 0;
+  for (; c < nchunks; c += wstride) {
+    double qn[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      r[j] = alphas_point(A, sk, sv, sc, sh, q[j]);
-      bad += (i0 + j < n && !(q[j] > 0.0 && q[j] < INFINITY)) ? 1 : 0;
+      const int64_t i = (c + wstride) * 256 + j * 64 + lane;
+      qn[j] = i < n ? Q2[i] : 1.0;
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (i0 + j < n) out[i0 + j] = r[j];
-    // lane-summed invalid count, one atomic per wave
-    unsigned long long cnt = 0;
-    for (int b = 1; b <= 4; ++b) cnt += (unsigned long long)b * __popcll(__ballot(bad == b));
-    if (cnt && (threadIdx.x & 63) == 0) atomicAdd(nerr, cnt);
+    for (int j = 0; j < 4; ++j) {
+      const int64_t i = c * 256 + j * 64 + lane;
+      const double r = alphas_point(A, sk, sv, sc, sh, q[j]);
+      if (i < n) out[i] = r;
+      cnt += __popcll(__ballot(i < n && !(q[j] > 0.0 && q[j] < INFINITY)));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = qn[j];
   }
+  if (cnt && lane == 0) atomicAdd(nerr, cnt);
 }
 
 // ---------------------------------------------------------------------------------------
 // Launchers (host side, called by pdfmi.cpp)
 
 // Location tables up to this size are staged in LDS (typical sets need
-// 10-40 KB: a few hundred knots of 8 bytes plus 80 bytes of coefficients per
+// 10-40 KB: a few hundred knots of 8 bytes plus 48 bytes of coefficients per
 // cell); larger ones are read from global memory.
 constexpr size_t kMaxLdsTables = 56 * 1024;
 static bool tables_fit(const MemberDev& m) { return (size_t)m.tbl_bytes <= kMaxLdsTables; }
+
+// LDS bytes of the alpha_s table staged for a fused alpha_s output.
+size_t alphas_lds_bytes(const AlphasDev* A) {
+  if (!A) return 0;
+  const size_t an2 = (size_t)((A->n + 1) & ~1);
+  return an2 * (8 + 8 + sizeof(CellCoef)) + (size_t)A->nhints * 2;
+}
 
 // LDS bytes of k_xfxq2 other than the staged grid, for a block of bs threads.
 static size_t shared_bytes(const MemberDev& m, bool f32, int bs, bool tables) {
@@ -428,43 +452,55 @@ static size_t shared_bytes(const MemberDev& m, bool f32, int bs, bool tables) {
 constexpr int kBlockGlobal = 256;   // tables and grid read from global memory
 constexpr int kBlockTables = 512;   // tables staged in LDS, grid read from global memory
 constexpr int kBlockLds = 1024;     // tables and grid staged once per workgroup in LDS
-size_t xfxq2_shared_bytes(const MemberDev& m, bool f32) { return shared_bytes(m, f32, kBlockLds, true); }
+size_t xfxq2_shared_bytes(const MemberDev& m, bool f32) {
+  return shared_bytes(m, f32, kBlockLds, true) + alphas_lds_bytes(nullptr);
+}
 
-template <typename T, int G, int BS, bool kLdsGrid, bool kLdsTables>
+// Launch context: the alpha_s table and output of a fused evaluation (A and
+// aout null when alpha_s is not requested).
+struct AsOut {
+  const AlphasDev* A;
+  double* aout;
+};
+
+template <typename T, int G, int BS, bool kLdsGrid, bool kLdsTables, bool kAlphas>
 static hipError_t launch_one(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2, int64_t n,
                              T* out, unsigned long long* nerr, int lds_grid_elems, double invL01, int64_t nb,
-                             size_t shm, hipStream_t s) {
-  const void* fn = reinterpret_cast<const void*>(&k_xfxq2<T, kLdsGrid, G, BS, kLdsTables>);
+                             size_t shm, const AsOut& ao, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&k_xfxq2<T, kLdsGrid, G, BS, kLdsTables, kAlphas>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_xfxq2<T, kLdsGrid, G, BS, kLdsTables>), dim3((unsigned)nb), dim3(BS), shm, s, m, rc, x, q2,
-                     n, out, nerr, lds_grid_elems, invL01);
+  const AlphasDev A = ao.A ? *ao.A : AlphasDev{};
+  hipLaunchKernelGGL((k_xfxq2<T, kLdsGrid, G, BS, kLdsTables, kAlphas>), dim3((unsigned)nb), dim3(BS), shm, s, m, rc, x, q2,
+                     n, out, nerr, lds_grid_elems, invL01, A, ao.aout);
   return hipGetLastError();
 }
 
-template <typename T, int G>
+template <typename T, int G, bool kAlphas>
 static hipError_t launch_xfxq2_g(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2,
                                  int64_t n, T* out, unsigned long long* nerr, int lds_grid_elems,
-                                 double invL01, const LaunchCfg& cfg, hipStream_t s) {
+                                 double invL01, const LaunchCfg& cfg, const AsOut& ao, hipStream_t s) {
   const int n_cu = cfg.n_cu;
   const bool f32 = sizeof(T) == 4;
+  const size_t as_bytes = alphas_lds_bytes(ao.A);
   if (lds_grid_elems > 0) {
-    const size_t shm = shared_bytes(m, f32, kBlockLds, true) + (size_t)lds_grid_elems * sizeof(T);
+    const size_t shm = shared_bytes(m, f32, kBlockLds, true) + (size_t)lds_grid_elems * sizeof(T) + as_bytes;
     const int per_cu = (int)(160 * 1024 / shm) > 0 ? (int)(160 * 1024 / shm) : 1;
     const int64_t ntiles = (n + kBlockLds - 1) / kBlockLds;
     const int64_t nb = min(ntiles, (int64_t)n_cu * per_cu);
-    return launch_one<T, G, kBlockLds, true, true>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, nb, shm, s);
+    return launch_one<T, G, kBlockLds, true, true, kAlphas>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, nb, shm, ao,
+                                                   s);
   }
   if (tables_fit(m)) {
-    const size_t shm = shared_bytes(m, f32, kBlockTables, true);
+    const size_t shm = shared_bytes(m, f32, kBlockTables, true) + as_bytes;
     const int64_t ntiles = (n + kBlockTables - 1) / kBlockTables;
     const int64_t nb = min(ntiles, (int64_t)n_cu * cfg.blocks_per_cu);
-    return launch_one<T, G, kBlockTables, false, true>(m, rc, x, q2, n, out, nerr, 0, invL01, nb, shm, s);
+    return launch_one<T, G, kBlockTables, false, true, kAlphas>(m, rc, x, q2, n, out, nerr, 0, invL01, nb, shm, ao, s);
   }
-  const size_t shm = shared_bytes(m, f32, kBlockGlobal, false);
+  const size_t shm = shared_bytes(m, f32, kBlockGlobal, false) + as_bytes;
   const int64_t ntiles = (n + kBlockGlobal - 1) / kBlockGlobal;
   const int64_t nb = min(ntiles, (int64_t)n_cu * cfg.blocks_per_cu);
-  return launch_one<T, G, kBlockGlobal, false, false>(m, rc, x, q2, n, out, nerr, 0, invL01, nb, shm, s);
+  return launch_one<T, G, kBlockGlobal, false, false, kAlphas>(m, rc, x, q2, n, out, nerr, 0, invL01, nb, shm, ao, s);
 }
 
 // The vectorised kernel serves requests for every stored column in load order.
@@ -476,20 +512,29 @@ static bool all_columns(const MemberDev& m, const ReqCols& rc, int G) {
   return true;
 }
 
+// A, aout: the alpha_s table and output of a fused evaluation, or null.
 hipError_t launch_xfxq2_f64(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2, int64_t n,
                             double* out, unsigned long long* nerr, int lds_grid_elems, double invL01,
-                            const LaunchCfg& cfg, hipStream_t s) {
-  if (cfg.vector_cols && all_columns(m, rc, 2))
-    return launch_xfxq2_g<double, 2>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
-  return launch_xfxq2_g<double, 1>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
+                            const LaunchCfg& cfg, const AlphasDev* A, double* aout, hipStream_t s) {
+  const AsOut ao{aout ? A : nullptr, aout};
+  const bool vec = cfg.vector_cols && all_columns(m, rc, 2);
+  if (aout)
+    return vec ? launch_xfxq2_g<double, 2, true>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, ao, s)
+               : launch_xfxq2_g<double, 1, true>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, ao, s);
+  return vec ? launch_xfxq2_g<double, 2, false>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, ao, s)
+             : launch_xfxq2_g<double, 1, false>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, ao, s);
 }
 
 hipError_t launch_xfxq2_f32(const MemberDev& m, const ReqCols& rc, const double* x, const double* q2, int64_t n,
                             float* out, unsigned long long* nerr, int lds_grid_elems, double invL01,
-                            const LaunchCfg& cfg, hipStream_t s) {
-  if (cfg.vector_cols && all_columns(m, rc, 4))
-    return launch_xfxq2_g<float, 4>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
-  return launch_xfxq2_g<float, 1>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, s);
+                            const LaunchCfg& cfg, const AlphasDev* A, double* aout, hipStream_t s) {
+  const AsOut ao{aout ? A : nullptr, aout};
+  const bool vec = cfg.vector_cols && all_columns(m, rc, 4);
+  if (aout)
+    return vec ? launch_xfxq2_g<float, 4, true>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, ao, s)
+               : launch_xfxq2_g<float, 1, true>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, ao, s);
+  return vec ? launch_xfxq2_g<float, 4, false>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, ao, s)
+             : launch_xfxq2_g<float, 1, false>(m, rc, x, q2, n, out, nerr, lds_grid_elems, invL01, cfg, ao, s);
 }
 
 hipError_t launch_locate(const MemberDev& m, const double* x, const double* q2, int64_t n, int32_t* k, int32_t* ix,
@@ -501,7 +546,7 @@ hipError_t launch_locate(const MemberDev& m, const double* x, const double* q2, 
 
 hipError_t launch_alphas(const AlphasDev& A, const double* q2, int64_t n, double* out, unsigned long long* nerr,
                          int n_cu, hipStream_t s) {
-  const int64_t nb = min(((n + 3) / 4 + 255) / 256, (int64_t)n_cu * 8);
+  const int64_t nb = min((n + 1023) / 1024, (int64_t)n_cu * 8);
   hipLaunchKernelGGL(k_alphas, dim3((unsigned)nb), dim3(256), 0, s, A, q2, n, out, nerr);
   return hipGetLastError();
 }
@@ -899,10 +944,10 @@ __global__ __launch_bounds__(kBatchBS) void k_batched(const BatchReq* __restrict
       const double qv = lane < tp ? rq.q2[pbeg + lane] : 0.0;
       if (vector_cols && rq.all_cols && rq.R >= G)
         wave_tile<T, kLdsGrid, G>(m, tb, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp, out + pbeg * rq.R, nerr,
-                                  invL01, rec, lane);
+                                  invL01, rec, lane, kNoAlphas, AsView{});
       else
         wave_tile<T, kLdsGrid, 1>(m, tb, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp, out + pbeg * rq.R, nerr,
-                                  invL01, rec, lane);
+                                  invL01, rec, lane, kNoAlphas, AsView{});
     }
   }
 }

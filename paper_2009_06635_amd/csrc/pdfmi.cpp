@@ -20,10 +20,11 @@
 
 namespace pdfmi {
 size_t xfxq2_shared_bytes(const MemberDev& m, bool f32);
+size_t alphas_lds_bytes(const AlphasDev* A);
 hipError_t launch_xfxq2_f64(const MemberDev&, const ReqCols&, const double*, const double*, int64_t, double*,
-                            unsigned long long*, int, double, const LaunchCfg&, hipStream_t);
+                            unsigned long long*, int, double, const LaunchCfg&, const AlphasDev*, double*, hipStream_t);
 hipError_t launch_xfxq2_f32(const MemberDev&, const ReqCols&, const double*, const double*, int64_t, float*,
-                            unsigned long long*, int, double, const LaunchCfg&, hipStream_t);
+                            unsigned long long*, int, double, const LaunchCfg&, const AlphasDev*, double*, hipStream_t);
 hipError_t launch_locate(const MemberDev&, const double*, const double*, int64_t, int32_t*, int32_t*, int32_t*,
                          int8_t*, int, hipStream_t);
 hipError_t launch_alphas(const AlphasDev&, const double*, int64_t, double*, unsigned long long*, int, hipStream_t);
@@ -230,10 +231,11 @@ Member* get_member(int32_t id) {
 }
 
 // Stage the whole grid in LDS for this call?
-int lds_grid_elems(const Member& M, bool f32, int64_t n) {
+// extra: further LDS bytes the launch needs (the alpha_s table of a fused call).
+int lds_grid_elems(const Member& M, bool f32, int64_t n, size_t extra = 0) {
   if (g_lds_policy == 1) return 0;
   const int64_t elems = f32 ? M.dev.elems32 : M.dev.elems64;
-  const size_t bytes = (size_t)elems * (f32 ? 4 : 8) + xfxq2_shared_bytes(M.dev, f32);
+  const size_t bytes = (size_t)elems * (f32 ? 4 : 8) + xfxq2_shared_bytes(M.dev, f32) + extra;
   if (bytes > kLdsBytes - 1024) return 0;
   if (g_lds_policy == 0) {
     // each workgroup pays one grid copy; require enough tiles to amortise it
@@ -519,39 +521,54 @@ extern "C" int pdf_load_alphas(int32_t n, const double* q2k, const double* a) {
   return PDF_OK;
 }
 
+// aout: alpha_s output of a fused call (nullptr: PDFs only).
 template <typename T>
 static int xfxq2_impl(int32_t member, const int32_t* pids, int32_t n_pids, const double* x, const double* q2,
-                      int64_t n, T* out, pdf_stream_t stream) {
+                      int64_t n, T* out, double* aout, bool fused, pdf_stream_t stream) {
   int rc = check_stream_args(x, q2, n);
   if (rc != PDF_OK) return rc;
   if (n > 0 && !out) return fail(PDF_ERR_ARG, "null out");
+  if (fused && n > 0 && !aout) return fail(PDF_ERR_ARG, "null alphas_out");
   std::lock_guard<std::mutex> lock(g_mu);
   Member* M = get_member(member);
   if (!M) return fail(PDF_ERR_MEMBER, "unknown member %d", member);
+  if (fused && !g_has_alphas) return fail(PDF_ERR_STATE, "no alpha_s table loaded");
   ReqCols req{};
   if ((rc = build_req(*M, pids, n_pids, req)) != PDF_OK) return rc;
   if (n == 0) return PDF_OK;
   if (n * (int64_t)req.n > ((int64_t)1 << 40)) return fail(PDF_ERR_ARG, "n too large");
   const bool f32 = sizeof(T) == 4;
-  const int lds = lds_grid_elems(*M, f32, n);
+  const int lds = lds_grid_elems(*M, f32, n, alphas_lds_bytes(fused ? &g_alphas : nullptr));
   hipError_t e;
   const LaunchCfg cfg{g_ncu, g_blocks_per_cu, g_vector_cols};
+  const AlphasDev* A = fused ? &g_alphas : nullptr;
   if constexpr (sizeof(T) == 8)
-    e = launch_xfxq2_f64(M->dev, req, x, q2, n, out, g_nerr, lds, M->invL01, cfg, (hipStream_t)stream);
+    e = launch_xfxq2_f64(M->dev, req, x, q2, n, out, g_nerr, lds, M->invL01, cfg, A, aout, (hipStream_t)stream);
   else
-    e = launch_xfxq2_f32(M->dev, req, x, q2, n, out, g_nerr, lds, M->invL01, cfg, (hipStream_t)stream);
+    e = launch_xfxq2_f32(M->dev, req, x, q2, n, out, g_nerr, lds, M->invL01, cfg, A, aout, (hipStream_t)stream);
   if (e != hipSuccess) return fail_hip(e, "launch xfxq2");
   return PDF_OK;
 }
 
 extern "C" int pdf_xfxq2(int32_t member, const int32_t* pids, int32_t n_pids, const double* x, const double* q2,
                          int64_t n, double* out, pdf_stream_t stream) {
-  return xfxq2_impl<double>(member, pids, n_pids, x, q2, n, out, stream);
+  return xfxq2_impl<double>(member, pids, n_pids, x, q2, n, out, nullptr, false, stream);
 }
 
 extern "C" int pdf_xfxq2_f32(int32_t member, const int32_t* pids, int32_t n_pids, const double* x,
                              const double* q2, int64_t n, float* out, pdf_stream_t stream) {
-  return xfxq2_impl<float>(member, pids, n_pids, x, q2, n, out, stream);
+  return xfxq2_impl<float>(member, pids, n_pids, x, q2, n, out, nullptr, false, stream);
+}
+
+extern "C" int pdf_xfxq2_alphas(int32_t member, const int32_t* pids, int32_t n_pids, const double* x,
+                                const double* q2, int64_t n, double* out, double* alphas_out, pdf_stream_t stream) {
+  return xfxq2_impl<double>(member, pids, n_pids, x, q2, n, out, alphas_out, true, stream);
+}
+
+extern "C" int pdf_xfxq2_alphas_f32(int32_t member, const int32_t* pids, int32_t n_pids, const double* x,
+                                    const double* q2, int64_t n, float* out, double* alphas_out,
+                                    pdf_stream_t stream) {
+  return xfxq2_impl<float>(member, pids, n_pids, x, q2, n, out, alphas_out, true, stream);
 }
 
 extern "C" int pdf_alphas_q2(const double* q2, int64_t n, double* out, pdf_stream_t stream) {
@@ -1215,7 +1232,8 @@ extern "C" int pdf_surrogate_set_data(int32_t sid, const double* x, const double
   build_req(*M, nullptr, 0, rc);
   // targets from this library's FP64 interpolator
   const LaunchCfg cfg{g_ncu, g_blocks_per_cu, g_vector_cols};
-  e = launch_xfxq2_f64(M->dev, rc, x, q2, n, xf, g_nerr, lds_grid_elems(*M, false, n), M->invL01, cfg, s);
+  e = launch_xfxq2_f64(M->dev, rc, x, q2, n, xf, g_nerr, lds_grid_elems(*M, false, n), M->invL01, cfg, nullptr,
+                       nullptr, s);
   if (e == hipSuccess) e = sur_prep(S->sd, x, q2, xf, n, S->d_in, S->d_t, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(xf);

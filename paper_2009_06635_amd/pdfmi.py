@@ -55,6 +55,8 @@ _SIGS = {
     "pdf_surrogate_save": [_i32, ctypes.c_char_p],
     "pdf_surrogate_load": [_i32, ctypes.c_char_p],
     "pdf_shutdown": [],
+    "pdf_xfxq2_alphas": [_i32, _P, _i32, _P, _P, _i64, _P, _P, _P],
+    "pdf_xfxq2_alphas_f32": [_i32, _P, _i32, _P, _P, _i64, _P, _P, _P],
     "pdf_mc_fused": [_i32, _P, _i32, _P, _P, _P, _i64, _P, _P, _P],
     "pdf_mc_fused_f32": [_i32, _P, _i32, _P, _P, _P, _i64, _P, _P, _P],
     "pdf_fk_contract": [_P, _P, _i32, _i32, _i64, _P, _P],
@@ -224,6 +226,23 @@ def xfxq2(member, pids, x, q2, out=None, n_cols=None, stream=None):
     _check(_lib.pdf_xfxq2(int(member), _ptr(arr) if arr is not None else None, npid, _P(x.data_ptr()),
                           _P(q2.data_ptr()), x.shape[0], _P(out.data_ptr()), _stream(stream)))
     return out
+
+
+def xfxq2_alphas(member, pids, x, q2, out=None, alphas_out=None, f32=False, n_cols=None, stream=None):
+    """x*f (FP64, or FP32 arithmetic with f32) and alpha_s at the same points
+    in one pass; returns (out, alphas_out)."""
+    _dev_f64(x, "x")
+    _dev_f64(q2, "q2")
+    arr, npid = _pid_arg(pids)
+    cols = npid if pids is not None else n_cols
+    if out is None:
+        out = torch.empty((x.shape[0], cols), dtype=torch.float32 if f32 else torch.float64, device=x.device)
+    if alphas_out is None:
+        alphas_out = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    fn = _lib.pdf_xfxq2_alphas_f32 if f32 else _lib.pdf_xfxq2_alphas
+    _check(fn(int(member), _ptr(arr) if arr is not None else None, npid, _P(x.data_ptr()), _P(q2.data_ptr()),
+              x.shape[0], _P(out.data_ptr()), _P(alphas_out.data_ptr()), _stream(stream)))
+    return out, alphas_out
 
 
 def xfxq2_f32(member, pids, x, q2, out=None, n_cols=None, stream=None):
