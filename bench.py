@@ -83,7 +83,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: query points shard across GPUs with no exchange, "
-              "and this build runs and reports the single-GPU path only.", file=sys.stderr)
+              "and only the single-GPU path is implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -153,22 +153,25 @@ __device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const Table
   const CellCoef cq = tb.cells[S.qc_off + iq];
   const int sx = min(max(ix - 1, 0), S.nxp - 4);
   const int sq = min(max(iq - 1, 0), S.nqp - 4);
+  // one logarithm per axis whatever the region: below x_0 the cell is the
+  // first one and ux = ln(x/x_0) / ln(x_1/x_0) is the continuation parameter
+  // itself; above the last Q^2 knot uq - 1 = ln(Q^2/q_n-1) / ln(q_n-1/q_n-2)
+  const double ux = cell_u(x, cx);
+  const double uq = cell_u(q2, cq);
   if (!(mode & kLowX)) {
-    stencil_weights<T>(cell_u(x, cx), cx, ix - sx, w);
+    stencil_weights<T>(ux, cx, ix - sx, w);
   } else {
     for (int a = 0; a < 4; ++a) w[a] = (T)0;
-    // continuation in ln x from knots 0 and 1: s = ln(x/x_0) / ln(x_1/x_0)
-    const double sx_par = log(x * cx.inv_t0) * cx.invD;
-    if (mode & (kLowQ | kHighQ)) L.p1 = sx_par; else L.p0 = sx_par;
+    if (mode & (kLowQ | kHighQ)) L.p1 = ux; else L.p0 = ux;
   }
   if (!(mode & (kLowQ | kHighQ))) {
-    stencil_weights<T>(cell_u(q2, cq), cq, iq - sq, v);
+    stencil_weights<T>(uq, cq, iq - sq, v);
   } else {
     for (int b = 0; b < 4; ++b) v[b] = (T)0;
     if (mode & kLowQ) {
-      L.p0 = q2 / cq.t0;                          // r = Q^2 / Q^2_0
+      L.p0 = q2 * cq.inv_t0;                       // r = Q^2 / Q^2_0
     } else {
-      L.p0 = log(q2 / cq.t1) * cq.invD;            // s = ln(Q^2/q_n-1) / ln(q_n-1/q_n-2)
+      L.p0 = uq - 1.0;                             // s = ln(Q^2/q_n-1) / ln(q_n-1/q_n-2)
       mode |= (S.nq - 2 - sq) << 8;                // stencil row of q_n-2
     }
   }
