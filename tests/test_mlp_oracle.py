@@ -28,7 +28,11 @@ def test_backward_matches_finite_differences():
 
 def test_bf16_rounding_matches_torch():
     rng = np.random.default_rng(1)
-    a = np.concatenate([rng.normal(0, 1, 5000), rng.normal(0, 1e-3, 5000), rng.uniform(-1e4, 1e4, 5000)])
+    # exact ties (low 16 bits 0x8000) with even and odd upper halves: round half to even
+    hi = rng.integers(0x0080, 0x7F00, 2000).astype(np.uint32)
+    ties = ((hi << 16) | 0x8000).view(np.float32).astype(np.float64)
+    a = np.concatenate([rng.normal(0, 1, 5000), rng.normal(0, 1e-3, 5000), rng.uniform(-1e4, 1e4, 5000),
+                        ties, -ties])
     want = torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(mlp.bf16(a), want)
 

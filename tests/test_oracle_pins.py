@@ -299,6 +299,14 @@ def test_locate_matches_searchsorted():
     g = synth.config2_grid()
     og = ogrid(g)
     x, q2 = synth.config2_queries(n=20000, seed=77, out_fraction=0.05)
+    # every knot and its float neighbours (ties: a query on an interior knot opens that knot's cell)
+    xk = g.xknots[0]
+    qk_all = np.concatenate(g.q2knots)
+    xs = np.concatenate([xk, np.nextafter(xk, 0.0), np.nextafter(xk[:-1], 2.0)])
+    qs = np.concatenate([qk_all, np.nextafter(qk_all, 0.0), np.nextafter(qk_all, np.inf)])
+    r = rng(78)
+    x = np.concatenate([x, xs, xs[r.integers(0, len(xs), len(qs))]])
+    q2 = np.concatenate([q2, qs[r.integers(0, len(qs), len(xs))], qs])
     k, ix, iq, reg = oracle.locate(og, x, q2)
     firsts = np.array([q[0] for q in g.q2knots])
     kk = np.clip(np.searchsorted(firsts, q2, side="right") - 1, 0, 2)
