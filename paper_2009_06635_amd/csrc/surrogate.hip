@@ -41,13 +41,13 @@ __device__ __forceinline__ float bf16_float(unsigned short b) {
   return __uint_as_float(((unsigned)b) << 16);
 }
 
-// tanh(|z|) = 1 - 2 / (exp(2|z|) + 1) from the hardware exp2 and reciprocal
-// (relative error ~1e-6 near 0 and far smaller elsewhere: well below the
-// BF16 rounding of the activations).
+// tanh(z) = 1 - 2 / (exp(2z) + 1) from the hardware exp2 and reciprocal:
+// exp2 overflows to +inf (result 1) and underflows to 0 (result -1); near 0
+// the absolute error is a few 1e-8, far below the BF16 rounding of the
+// activations.
 __device__ __forceinline__ float tanh_f(float z) {
-  const float e = __builtin_amdgcn_exp2f(fminf(2.8853900817779268f * fabsf(z), 64.0f));  // 2|z| log2(e)
-  const float r = fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
-  return copysignf(r, z);
+  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * z);  // 2 z log2(e)
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -212,12 +212,17 @@ __global__ void k_prep_samples(SurDev S, const double* __restrict__ X, const dou
 }
 
 // ---------------------------------------------------------------------------------------
-// Fused inference.  One wave = 16 points; layer 1 on the VALUs directly into
+// Fused inference.  Each wave takes 64 consecutive points: their inputs,
+// fallback flags and envelope cells are prepared one lane per point, then the
+// network runs on four 16-point sub-tiles (layer 1 on the VALUs directly into
 // the A-operand layout of layer 2; layers 2-4 on the matrix cores with the
 // weight fragments held in registers; hidden activations re-laid out from the
-// accumulator layout to the A-operand layout through 2 KB of LDS per wave.
-// Points in the fallback domain are evaluated by the FP32 interpolator inside
-// the same wave (one lane per flavour).
+// accumulator layout to the A-operand layout through 2 KB of LDS per wave).
+// (Keeping the activations in registers by computing the transposed products,
+// weights as the A operand, needs ~250 registers and ran 40 % slower.)
+// Points in the fallback domain are then evaluated by the FP32 interpolator:
+// each is located once (one lane per point: sub-grid, cells, weights), after
+// which one lane per (point, flavour) gathers its 4x4 stencil.
 constexpr int kSurWaves = 4;
 
 __device__ __forceinline__ bool trusted(const SurDev& S, const MemberDev& m, double x, double q2) {
@@ -228,11 +233,21 @@ __device__ __forceinline__ bool trusted(const SurDev& S, const MemberDev& m, dou
   return S.trust[k] && x >= S.txlo[k] && x < S.txhi[k] && q2 >= S.tqlo[k] && q2 < S.tqhi[k];
 }
 
+// Location of one fallback point (what interp_point derives before its gathers).
+struct FbRec {
+  float w[4], v[4];
+  int base, sa, mode, pt;  // grid offset and x stride (elements), region bits, point within the 64
+  double p0, p1;           // extrapolation parameters
+};
+
 // LDS of k_sur_infer: [nx] ln x knots, [nx][16] envelope, W1 (BF16-rounded),
-// b1, b2, b3, b4, then per wave the point records and the activation tile.
+// b1, b2, b3, b4, then per wave the fallback records, the activation tile and
+// the point records.
 size_t sur_infer_shared_bytes(int nx) {
-  return (size_t)4 * (nx + nx * kO + 2 * kH + 3 * kH + kO) + (size_t)kSurWaves * (16 * kH * 2 + 16 * 16 + 64 * 4);
+  const size_t head = (size_t)4 * (nx + nx * kO + 2 * kH + 3 * kH + kO);
+  return ((head + 15) & ~(size_t)15) + (size_t)kSurWaves * (64 * sizeof(FbRec) + 16 * kH * 2 + 64 * 16);
 }
+
 
 __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDev m, const unsigned short* __restrict__ Pb,
                                                              const float* __restrict__ Pf,
@@ -248,9 +263,10 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
   float* sb2 = sb1 + kH;
   float* sb3 = sb2 + kH;
   float* sb4 = sb3 + kH;                      // [kO]
-  unsigned short* shs = reinterpret_cast<unsigned short*>(sb4 + kO);             // [waves][16 * kH]
-  float* spt = reinterpret_cast<float*>(shs + kSurWaves * 16 * kH);              // [waves][16][4]
-  int* sfb = reinterpret_cast<int*>(spt + kSurWaves * 64);                        // [waves][64]
+  const size_t head = (size_t)4 * (S.nx + S.nx * kO + 2 * kH + 3 * kH + kO);
+  FbRec* sfb = reinterpret_cast<FbRec*>(reinterpret_cast<unsigned char*>(sdyn) + ((head + 15) & ~(size_t)15));
+  unsigned short* shs = reinterpret_cast<unsigned short*>(sfb + kSurWaves * 64);  // [waves][16 * kH]
+  float* spt = reinterpret_cast<float*>(shs + kSurWaves * 16 * kH);                // [waves][64][4]
   for (int i = threadIdx.x; i < S.nx; i += 64 * kSurWaves) slxk[i] = S.lxk[i];
   for (int i = threadIdx.x; i < S.nx * kO; i += 64 * kSurWaves) senv[i] = S.env[i];
   for (int i = threadIdx.x; i < 2 * kH; i += 64 * kSurWaves) sw1[i] = bf16_float(bf16_bits(Pf[kOffW1 + i]));
@@ -264,8 +280,8 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
 
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
   unsigned short* hs = shs + wv * 16 * kH;
-  float* pt4 = spt + wv * 64;   // per point: u, v, envelope t, envelope cell (as int bits)
-  int* fbl = sfb + wv * 64;
+  float* pt4 = spt + wv * 64 * 4;   // per point: u, v, envelope t, envelope cell (as int bits)
+  FbRec* fbr = sfb + wv * 64;
   // weight fragments: B operand of layer L, N-tile t, K-step s: lane holds W[n = 16t + r][k = 32s + 8g + i]
   bf16x8 w2[4][2], w3[4][2], w4[2];
 #pragma unroll
@@ -283,12 +299,13 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
 #pragma unroll
     for (int i = 0; i < 8; ++i) w4[s][i] = __builtin_bit_cast(__bf16, Pb[kOffW4 + r * kH + 32 * s + 8 * g + i]);
   const Tables gtb{m.knots, m.cells, m.hints, m.subs};
+  const float* __restrict__ gvals = member_values<float>(m);
 
-  const int64_t ntiles = (n + 15) / 16;
+  const int64_t ntiles = (n + 63) / 64;
   for (int64_t tile = (int64_t)blockIdx.x * kSurWaves + wv; tile < ntiles; tile += (int64_t)gridDim.x * kSurWaves) {
-    const int64_t p0 = tile * 16;
-    const int np = (int)min((int64_t)16, n - p0);
-    // lanes 0..15: the wave's 16 points (inputs, fallback flag, envelope interval)
+    const int64_t p0 = tile * 64;
+    const int np = (int)min((int64_t)64, n - p0);
+    // one lane per point: inputs, fallback flag, envelope interval
     double xr = 0.5, qr = 1.0;
     bool fb = false;
     if (l < np) {
@@ -306,77 +323,108 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
       }
       pt4[4 * l + 2] = fminf(fmaxf((lxf - slxk[lo]) / (slxk[lo + 1] - slxk[lo]), 0.0f), 1.0f);
       pt4[4 * l + 3] = __int_as_float(lo);
-    } else if (l < 16) {
+    } else {
       pt4[4 * l] = pt4[4 * l + 1] = pt4[4 * l + 2] = 0.0f;
       pt4[4 * l + 3] = __int_as_float(0);
     }
-    const unsigned long long fbmask = __ballot(fb) & 0xFFFFull;
+    const unsigned long long fbmask = __ballot(fb);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // layer 1 straight into the A layout: lane (r, g) holds h1[r][32 s + 8 g + i]
-    const float u = bf16_float(bf16_bits(pt4[4 * r])), v = bf16_float(bf16_bits(pt4[4 * r + 1]));
-    bf16x8 a[2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int j = 32 * s + 8 * g + i;
-        const float z = fmaf(sw1[2 * j], u, fmaf(sw1[2 * j + 1], v, sb1[j]));
-        a[s][i] = __builtin_bit_cast(__bf16, bf16_bits(tanh_f(z)));
-      }
-    // layers 2 and 3
-#pragma unroll
-    for (int layer = 0; layer < 2; ++layer) {
-      const float* bl = layer == 0 ? sb2 : sb3;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], layer == 0 ? w2[t][0] : w3[t][0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], layer == 0 ? w2[t][1] : w3[t][1], acc, 0, 0, 0);
-        const float bn = bl[16 * t + r];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) hs[(4 * g + i) * kH + 16 * t + r] = bf16_bits(tanh_f(acc[i] + bn));
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q0 = 0; q0 < np; q0 += 16) {
+      // layer 1 straight into the A layout: lane (r, g) holds h1[point q0 + r][32 s + 8 g + i]
+      const float u = bf16_float(bf16_bits(pt4[4 * (q0 + r)])), v = bf16_float(bf16_bits(pt4[4 * (q0 + r) + 1]));
+      bf16x8 a[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) a[s][i] = __builtin_bit_cast(__bf16, hs[r * kH + 32 * s + 8 * g + i]);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    // layer 4: lane (r, g) gets y[point 4 g + i][output r]; times the envelope
-    f32x4 y = {0.f, 0.f, 0.f, 0.f};
-    y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], w4[0], y, 0, 0, 0);
-    y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], w4[1], y, 0, 0, 0);
-    const float b4 = sb4[r];
+        for (int i = 0; i < 8; ++i) {
+          const int j = 32 * s + 8 * g + i;
+          const float z = fmaf(sw1[2 * j], u, fmaf(sw1[2 * j + 1], v, sb1[j]));
+          a[s][i] = __builtin_bit_cast(__bf16, bf16_bits(tanh_f(z)));
+        }
+      // layers 2 and 3
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int pt = 4 * g + i;
-      if (pt < np && r < S.P && !((fbmask >> pt) & 1ull)) {
-        const int lo = __float_as_int(pt4[4 * pt + 3]);
-        const float t = pt4[4 * pt + 2];
-        const float e0 = senv[lo * kO + r], e1 = senv[(lo + 1) * kO + r];
-        out[(p0 + pt) * S.P + r] = (y[i] + b4) * (e0 + t * (e1 - e0));
+      for (int layer = 0; layer < 2; ++layer) {
+        const float* bl = layer == 0 ? sb2 : sb3;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], layer == 0 ? w2[t][0] : w3[t][0], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], layer == 0 ? w2[t][1] : w3[t][1], acc, 0, 0, 0);
+          const float bn = bl[16 * t + r];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) hs[(4 * g + i) * kH + 16 * t + r] = bf16_bits(tanh_f(acc[i] + bn));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) a[s][i] = __builtin_bit_cast(__bf16, hs[r * kH + 32 * s + 8 * g + i]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      // layer 4: lane (r, g) gets y[point q0 + 4 g + i][output r]; times the envelope
+      f32x4 y = {0.f, 0.f, 0.f, 0.f};
+      y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], w4[0], y, 0, 0, 0);
+      y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], w4[1], y, 0, 0, 0);
+      const float b4 = sb4[r];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pt = q0 + 4 * g + i;
+        if (pt < np && r < S.P && !((fbmask >> pt) & 1ull)) {
+          const int lo = __float_as_int(pt4[4 * pt + 3]);
+          const float t = pt4[4 * pt + 2];
+          const float e0 = senv[lo * kO + r], e1 = senv[(lo + 1) * kO + r];
+          out[(p0 + pt) * S.P + r] = (y[i] + b4) * (e0 + t * (e1 - e0));
+        }
       }
     }
-    // fallback points: FP32 interpolator, one lane per (point, stored column)
+    // fallback points: located once each, then one lane per (point, stored column)
     if (fbmask) {
       const int nfb = __popcll(fbmask);
-      if (l < 16 && ((fbmask >> l) & 1ull)) fbl[__popcll(fbmask & ((1ull << l) - 1))] = l;
-      if (l < 16 && ((fbmask >> l) & 1ull) && !((xr > 0.0) && (xr <= m.xmax) && (qr > 0.0) && (qr < INFINITY)))
-        atomicAdd(nerr, 1ull);
+      bool bad = false;
+      if (fb) {
+        FbRec& rc = fbr[__popcll(fbmask & ((1ull << l) - 1))];
+        const PointLoc L = locate_point<float>(m, gtb, xr, qr, rc.w, rc.v);
+        rc.base = L.base;
+        rc.sa = L.sa;
+        rc.mode = L.mode;
+        rc.pt = l;
+        rc.p0 = L.p0;
+        rc.p1 = L.p1;
+        bad = L.mode & kInvalid;
+      }
+      const unsigned long long badm = __ballot(bad);
+      if (badm && l == 0) atomicAdd(nerr, (unsigned long long)__popcll(badm));
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int w = l; w < nfb * S.P; w += 64) {
-        const int pt = fbl[w / S.P], c = w - (w / S.P) * S.P;
-        const double xp = X[p0 + pt], qp = Q2[p0 + pt];
-        out[(p0 + pt) * S.P + c] = interp_point<float>(m, gtb, xp, qp, c, invL01);
+      for (int e = l; e < nfb * S.P; e += 64) {
+        const int k = e / S.P, c = e - k * S.P;
+        const FbRec& rc = fbr[k];
+        float val;
+        if (rc.mode & kInvalid) {
+          val = NAN;
+        } else {
+          const float* f = gvals + rc.base + c;
+          if (!(rc.mode & (kLowX | kLowQ | kHighQ))) {
+            float F[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int b = 0; b < 4; ++b) F[a][b] = f[a * rc.sa + b * m.P32];
+            val = interp_stencil<float>(F, rc.w, rc.v);
+          } else {
+            const Wts wt{(double)rc.w[0], (double)rc.w[1], (double)rc.w[2], (double)rc.w[3],
+                         (double)rc.v[0], (double)rc.v[1], (double)rc.v[2], (double)rc.v[3]};
+            val = (float)extrap_entry<float>(f, rc.sa, m.P32, rc.mode, wt, rc.p0, rc.p1, invL01);
+          }
+        }
+        out[(p0 + rc.pt) * S.P + c] = val;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -525,7 +573,7 @@ hipError_t sur_prep(const SurDev& S, const double* x, const double* q2, const do
 
 hipError_t sur_infer(const SurDev& S, const MemberDev& m, const SurBufs& b, const double* x, const double* q2,
                      int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu, hipStream_t s) {
-  const int64_t tiles = (n + 15) / 16;
+  const int64_t tiles = (n + 63) / 64;
   const int64_t blocks = min((tiles + kSurWaves - 1) / kSurWaves, (int64_t)n_cu * 8);
   if (blocks > 0) {
     const size_t shm = sur_infer_shared_bytes(S.nx);
