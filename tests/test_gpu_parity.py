@@ -268,3 +268,35 @@ def test_full_size_sampled_config2(cfg2):
     j6 = g.pids.index(6)
     assert bool((out64[:, j6] == 0).all())
     print("full-size sampled: literal FP64 pass %.6f (max %.3g), FP32 %.6f (max %.3g)" % (lit, mx, lit32, mx32))
+
+
+def test_outputs_beyond_4_gib(cfg2):
+    """42e6 points x 13 flavours: the FP64 output spans 4.4 GB, so rows past
+    the first 4 GiB are addressed through 64-bit offsets; sampled rows there
+    (and at the start) are checked against the oracle, for x*f, the fused
+    alpha_s output and FP32."""
+    g, m = cfg2
+    n = 42_000_000
+    x, q2 = synth.config2_queries(n=n, seed=14)
+    xd, qd = dev(x), dev(q2)
+    pdfmi.load_alphas(*synth.config2_alphas())
+    out64, a = pdfmi.xfxq2_alphas(m, g.pids, xd, qd)
+    assert out64.numel() * 8 > 2 ** 32
+    first_far = 2 ** 32 // (8 * len(g.pids)) + 1
+    rng = np.random.default_rng(15)
+    idx = np.concatenate([rng.integers(first_far, n, 3000), rng.integers(0, first_far, 1000), [n - 1, first_far]])
+    idx_t = torch.from_numpy(idx).to(DEV)
+    s64 = out64[idx_t].cpu().numpy()
+    sa = a[idx_t].cpu().numpy()
+    del out64, a
+    out32 = pdfmi.xfxq2_f32(m, g.pids, xd, qd)
+    s32 = out32[idx_t].cpu().numpy()
+    del out32
+    ora, scale = oracle.xfxq2(ogrid(g), g.pids, x[idx], q2[idx], with_scale=True)
+    ok = check_f64(s64, ora, scale, grid_L(g))[0]
+    assert ok.all(), describe_failures(ok, s64, ora, x[idx], q2[idx], g.pids)
+    ok32 = check_f32(s32, ora, scale)[0]
+    assert ok32.all(), describe_failures(ok32, s32, ora, x[idx], q2[idx], g.pids)
+    qk, av = synth.config2_alphas()
+    oa = oracle.alphas_q2(qk, av, q2[idx])
+    assert np.max(np.abs(sa - oa) / np.abs(oa)) < 1e-13
