@@ -213,7 +213,9 @@ int pdf_batch_create(const pdf_request* reqs, int32_t n_req, int32_t out_f64, in
  * Plan settings: tile_points (multiple of 64, default 4096), vector_cols
  * (1: 16-byte column groups for requests of every stored flavour in order),
  * use_graph (1: pdf_batch_run replays a hipGraph holding the counter reset
- * and the persistent kernel, built on first use).
+ * and the persistent kernel, built on first use).  A change of tile_points
+ * rebuilds the tile table and first waits for the device to be idle (a run
+ * of the plan may still be reading the old table).
  */
 int pdf_batch_configure(int32_t plan, int32_t tile_points, int32_t vector_cols, int32_t use_graph);
 /* Queue one evaluation of every request of the plan on stream. */

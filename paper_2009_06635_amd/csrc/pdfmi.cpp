@@ -696,8 +696,14 @@ void plan_release(Plan& P) {
   P = Plan();
 }
 
-// (Re)build the tile list for the plan's tile size and upload it.
+// (Re)build the tile list for the plan's tile size and upload it.  The device
+// is drained first: a run of this plan still in flight on some stream reads
+// the tile list being replaced.
 int plan_tiles(Plan& P) {
+  if (P.d_tiles) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail_hip(e, "hipDeviceSynchronize");
+  }
   std::vector<BatchTile> t;
   // tiles grouped by member so that consecutive tiles tend to share a staged grid
   std::vector<int> order(P.reqs.size());
@@ -931,39 +937,45 @@ extern "C" int pdf_batch_autotune(int32_t plan, int32_t reps, pdf_stream_t strea
     best_tile = it->second.first;
     best_vec = it->second.second;
   } else {
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-      return fail(PDF_ERR_DEVICE, "hipEventCreate");
-    float best = 1e30f;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     const int saved_graph = P->use_graph;
-    P->use_graph = 0;
-    for (int tp : {1024, 2048, 4096, 8192, 16384}) {
-      for (int vec : {0, 1}) {
-        P->tile_points = tp;
-        P->vector_cols = vec;
-        int rc = plan_tiles(*P);
-        if (rc != PDF_OK) return rc;
-        if ((rc = plan_run(*P, s)) != PDF_OK) return rc;  // warm-up
-        float tot = 0.0f;
-        for (int r = 0; r < reps; ++r) {
-          (void)hipEventRecord(e0, s);
-          if ((rc = plan_run(*P, s)) != PDF_OK) return rc;
-          (void)hipEventRecord(e1, s);
-          if (hipEventSynchronize(e1) != hipSuccess) return fail(PDF_ERR_DEVICE, "hipEventSynchronize");
-          float ms = 0.0f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          tot += ms;
-        }
-        if (tot < best) {
-          best = tot;
-          best_tile = tp;
-          best_vec = vec;
+    // the sweep; every exit path below restores the plan's graph flag and frees the events
+    auto sweep = [&]() -> int {
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(PDF_ERR_DEVICE, "hipEventCreate");
+      float best = 1e30f;
+      P->use_graph = 0;
+      for (int tp : {1024, 2048, 4096, 8192, 16384}) {
+        for (int vec : {0, 1}) {
+          P->tile_points = tp;
+          P->vector_cols = vec;
+          int rc = plan_tiles(*P);
+          if (rc != PDF_OK) return rc;
+          if ((rc = plan_run(*P, s)) != PDF_OK) return rc;  // warm-up
+          float tot = 0.0f;
+          for (int r = 0; r < reps; ++r) {
+            (void)hipEventRecord(e0, s);
+            if ((rc = plan_run(*P, s)) != PDF_OK) return rc;
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) return fail(PDF_ERR_DEVICE, "hipEventSynchronize");
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tot += ms;
+          }
+          if (tot < best) {
+            best = tot;
+            best_tile = tp;
+            best_vec = vec;
+          }
         }
       }
-    }
+      return PDF_OK;
+    };
+    const int rc = sweep();
     P->use_graph = saved_graph;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != PDF_OK) return rc;
     g_tune_cache[key] = {best_tile, best_vec};
   }
   plan_free_graph(*P);
