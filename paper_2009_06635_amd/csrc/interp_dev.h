@@ -122,15 +122,64 @@ struct PointLoc {
   double p0, p1; // extrapolation parameters
 };
 
-// Phase 1: everything that depends on the point only.
+// Phase 1: everything that depends on the point only, in two halves: the Q^2
+// half (validity of Q^2, region bits, sub-grid, Q^2 cell and weights) is
+// shared by every point at the same Q^2 (the two lookups of a Monte-Carlo
+// point); the x half completes the location.
 template <typename T>
-__device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const Tables& tb, double x, double q2, T w[4],
-                                                 T v[4]) {
+struct QLoc {
+  int mode;      // kInvalid (Q^2 <= 0 or not finite), else kLowQ | kHighQ | (anchor row << 8)
+  int k, iq, sq;
+  double p0;     // Q^2 continuation parameter (below Q^2_min: r; above Q^2_max: s)
+  T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ QLoc<T> locate_q(const MemberDev& m, const Tables& tb, double q2) {
+  QLoc<T> Q;
+  Q.p0 = 0.0;
+  for (int b = 0; b < 4; ++b) Q.v[b] = (T)0;
+  if (!((q2 > 0.0) && (q2 < INFINITY))) {
+    Q.mode = kInvalid;
+    Q.k = Q.iq = -1;
+    Q.sq = 0;
+    return Q;
+  }
+  int mode = 0;
+  if (q2 < m.qmin) mode |= kLowQ;
+  if (q2 > m.qmax) mode |= kHighQ;
+  int k = 0;
+  for (int j = 1; j < m.K; ++j)
+    if (m.sub[j].qfirst <= q2) k = j;
+  const SubDesc S = tb.subs[k];
+  const int iq = find_cell_hint(tb.knots + S.qk_off, S.nq, q2, S.qh, tb.hints);
+  const CellCoef cq = tb.cells[S.qc_off + iq];
+  const int sq = min(max(iq - 1, 0), S.nqp - 4);
+  // one logarithm whatever the region: above the last knot
+  // uq - 1 = ln(Q^2/q_n-1) / ln(q_n-1/q_n-2)
+  const double uq = cell_u(q2, cq);
+  if (!(mode & (kLowQ | kHighQ))) {
+    stencil_weights<T>(uq, cq, iq - sq, Q.v);
+  } else if (mode & kLowQ) {
+    Q.p0 = q2 * cq.inv_t0;                         // r = Q^2 / Q^2_0
+  } else {
+    Q.p0 = uq - 1.0;                               // s = ln(Q^2/q_n-1) / ln(q_n-1/q_n-2)
+    mode |= (S.nq - 2 - sq) << 8;                  // stencil row of q_n-2
+  }
+  Q.mode = mode;
+  Q.k = k;
+  Q.iq = iq;
+  Q.sq = sq;
+  return Q;
+}
+
+template <typename T>
+__device__ __forceinline__ PointLoc locate_x(const MemberDev& m, const Tables& tb, const QLoc<T>& Q, double x, T w[4],
+                                             T v[4]) {
   PointLoc L;
   L.p0 = 0.0;
   L.p1 = 0.0;
-  const bool valid = (x > 0.0) && (x <= m.xmax) && (q2 > 0.0) && (q2 < INFINITY);
-  if (!valid) {
+  if ((Q.mode & kInvalid) || !((x > 0.0) && (x <= m.xmax))) {
     L.mode = kInvalid;
     L.k = L.ix = L.iq = -1;
     L.sx = L.sq = 0;
@@ -139,53 +188,41 @@ __device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const Table
     for (int a = 0; a < 4; ++a) w[a] = v[a] = (T)0;
     return L;
   }
-  int mode = 0;
-  if (x < m.xmin) mode |= kLowX;
-  if (q2 < m.qmin) mode |= kLowQ;
-  if (q2 > m.qmax) mode |= kHighQ;
-  int k = 0;
-  for (int j = 1; j < m.K; ++j)
-    if (m.sub[j].qfirst <= q2) k = j;
-  const SubDesc S = tb.subs[k];
+  int mode = Q.mode;
+  const bool qout = mode & (kLowQ | kHighQ);
+  const SubDesc S = tb.subs[Q.k];
   const int ix = find_cell_hint(tb.knots + S.xk_off, S.nx, x, S.xh, tb.hints);
-  const int iq = find_cell_hint(tb.knots + S.qk_off, S.nq, q2, S.qh, tb.hints);
   const CellCoef cx = tb.cells[S.xc_off + ix];
-  const CellCoef cq = tb.cells[S.qc_off + iq];
   const int sx = min(max(ix - 1, 0), S.nxp - 4);
-  const int sq = min(max(iq - 1, 0), S.nqp - 4);
-  // one logarithm per axis whatever the region: below x_0 the cell is the
-  // first one and ux = ln(x/x_0) / ln(x_1/x_0) is the continuation parameter
-  // itself; above the last Q^2 knot uq - 1 = ln(Q^2/q_n-1) / ln(q_n-1/q_n-2)
+  // below x_0 the cell is the first one and ux = ln(x/x_0) / ln(x_1/x_0) is
+  // the continuation parameter itself
   const double ux = cell_u(x, cx);
-  const double uq = cell_u(q2, cq);
-  if (!(mode & kLowX)) {
+  if (!(x < m.xmin)) {
     stencil_weights<T>(ux, cx, ix - sx, w);
   } else {
+    mode |= kLowX;
     for (int a = 0; a < 4; ++a) w[a] = (T)0;
-    if (mode & (kLowQ | kHighQ)) L.p1 = ux; else L.p0 = ux;
+    if (qout) L.p1 = ux; else L.p0 = ux;
   }
-  if (!(mode & (kLowQ | kHighQ))) {
-    stencil_weights<T>(uq, cq, iq - sq, v);
-  } else {
-    for (int b = 0; b < 4; ++b) v[b] = (T)0;
-    if (mode & kLowQ) {
-      L.p0 = q2 * cq.inv_t0;                       // r = Q^2 / Q^2_0
-    } else {
-      L.p0 = uq - 1.0;                             // s = ln(Q^2/q_n-1) / ln(q_n-1/q_n-2)
-      mode |= (S.nq - 2 - sq) << 8;                // stencil row of q_n-2
-    }
-  }
+  if (qout) L.p0 = Q.p0;
+  for (int b = 0; b < 4; ++b) v[b] = Q.v[b];
   if (x > 0.9) mode |= kXHigh;
   L.mode = mode;
-  L.k = k;
+  L.k = Q.k;
   L.ix = ix;
-  L.iq = iq;
+  L.iq = Q.iq;
   L.sx = sx;
-  L.sq = sq;
+  L.sq = Q.sq;
   const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
   L.sa = S.nqp * Pp;
-  L.base = (int)((sizeof(T) == 8 ? S.val_off64 : S.val_off32) + (int64_t)(sx * S.nqp + sq) * Pp);
+  L.base = (int)((sizeof(T) == 8 ? S.val_off64 : S.val_off32) + (int64_t)(sx * S.nqp + Q.sq) * Pp);
   return L;
+}
+
+template <typename T>
+__device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const Tables& tb, double x, double q2, T w[4],
+                                                 T v[4]) {
+  return locate_x<T>(m, tb, locate_q<T>(m, tb, q2), x, w, v);
 }
 
 // Two-anchor continuation (log-linear when both anchors exceed 1e-3).

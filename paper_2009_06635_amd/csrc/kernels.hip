@@ -782,8 +782,9 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
         q2 = Q2[i];
       }
       T w1[4], v1[4], w2[4], v2[4];
-      const PointLoc L1 = locate_point<T>(m, tb, x1, q2, w1, v1);
-      const PointLoc L2 = locate_point<T>(m, tb, x2, q2, w2, v2);
+      const QLoc<T> Qs = locate_q<T>(m, tb, q2);  // shared Q^2: located once for both lookups
+      const PointLoc L1 = locate_x<T>(m, tb, Qs, x1, w1, v1);
+      const PointLoc L2 = locate_x<T>(m, tb, Qs, x2, w2, v2);
       const double as = alphas_point(A, ask, asv, asc, ash, q2);
       const bool bad1 = live && (L1.mode & kInvalid), bad2 = live && (L2.mode & kInvalid);
       const bool bada = live && !(q2 > 0.0 && q2 < INFINITY);
