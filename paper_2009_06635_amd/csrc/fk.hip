@@ -6,8 +6,9 @@
 // a dense FP64 contraction of the replica matrix F [nrep][K] with the table
 // [ndat][K], on the FP64 matrix cores (v_mfma_f64_16x16x4_f64).
 //
-// Tiling: a workgroup of 4 waves computes a 64 x 128 tile of T (64 members x
-// 128 table rows); each wave a 32 x 64 part as 2 x 4 MFMA tiles of 16 x 16.
+// Tiling: a workgroup of 8 waves computes a 64 x 128 tile of T (64 members x
+// 128 table rows); each wave a 32 x 32 part as 2 x 2 MFMA tiles of 16 x 16
+// (two workgroups per compute unit: 4 waves per SIMD).
 // K is walked in steps of 32 staged in LDS as rows of 36 doubles (the 16 rows
 // x 4 k read by one MFMA operand then fall on distinct bank pairs), with the
 // next step's global loads (32 consecutive k per half-wave: 256-byte
@@ -24,7 +25,7 @@ namespace pdfmi {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kFkBM = 64, kFkBN = 128, kFkBK = 32, kFkLd = kFkBK + 4, kFkThreads = 256;
+constexpr int kFkBM = 64, kFkBN = 128, kFkBK = 32, kFkLd = kFkBK + 4, kFkThreads = 512;
 constexpr int kFkRowsA = kFkBM * kFkBK / kFkThreads, kFkRowsB = kFkBN * kFkBK / kFkThreads;  // loads per thread
 
 // One (64 x 128 tile, K slice) per workgroup: the slice [blockIdx.z * kslice,
@@ -37,9 +38,9 @@ __global__ __launch_bounds__(kFkThreads) void k_fk_contract(const double* __rest
   __shared__ double sa[kFkBM * kFkLd];
   __shared__ double sb[kFkBN * kFkLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;  // wave part of the tile: rows 32 wm.., columns 64 wn..
+  const int wm = wave >> 2, wn = wave & 3;  // wave part of the tile: rows 32 wm.., columns 32 wn..
   const int m0 = blockIdx.y * kFkBM, n0 = blockIdx.x * kFkBN;
-  // cooperative loads: thread -> k = tid % 32 of rows tid / 32 + 8 i
+  // cooperative loads: thread -> k = tid % 32 of rows tid / 32 + 16 i
   const int lk = tid & 31, lr = tid >> 5;
   const int64_t kbeg = (int64_t)blockIdx.z * kslice, kend = min(K, kbeg + kslice);
   T += (int64_t)blockIdx.z * nrep * ndat;
@@ -49,41 +50,41 @@ __global__ __launch_bounds__(kFkThreads) void k_fk_contract(const double* __rest
     const bool kok = k < kend;
 #pragma unroll
     for (int i = 0; i < kFkRowsA; ++i) {
-      const int row = m0 + lr + 8 * i;
+      const int row = m0 + lr + 16 * i;
       ra[i] = (kok && row < nrep) ? F[(int64_t)row * K + k] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < kFkRowsB; ++i) {
-      const int row = n0 + lr + 8 * i;
+      const int row = n0 + lr + 16 * i;
       rb[i] = (kok && row < ndat) ? FK[(int64_t)row * K + k] : 0.0;
     }
   };
-  f64x4 acc[2][4];
+  f64x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int r16 = lane & 15, kq = lane >> 4;
   fetch(kbeg);
   for (int64_t k0 = kbeg; k0 < kend; k0 += kFkBK) {
     __syncthreads();  // previous step's operands consumed
 #pragma unroll
-    for (int i = 0; i < kFkRowsA; ++i) sa[(lr + 8 * i) * kFkLd + lk] = ra[i];
+    for (int i = 0; i < kFkRowsA; ++i) sa[(lr + 16 * i) * kFkLd + lk] = ra[i];
 #pragma unroll
-    for (int i = 0; i < kFkRowsB; ++i) sb[(lr + 8 * i) * kFkLd + lk] = rb[i];
+    for (int i = 0; i < kFkRowsB; ++i) sb[(lr + 16 * i) * kFkLd + lk] = rb[i];
     __syncthreads();
     if (k0 + kFkBK < kend) fetch(k0 + kFkBK);
 #pragma unroll
     for (int kk = 0; kk < kFkBK; kk += 4) {
-      double a[2], b[4];
+      double a[2], b[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) a[t] = sa[(wm * 32 + t * 16 + r16) * kFkLd + kk + kq];  // A: row r16, k = kq
 #pragma unroll
-      for (int t = 0; t < 4; ++t) b[t] = sb[(wn * 64 + t * 16 + r16) * kFkLd + kk + kq];  // B: column r16, k = kq
+      for (int t = 0; t < 2; ++t) b[t] = sb[(wn * 32 + t * 16 + r16) * kFkLd + kk + kq];  // B: column r16, k = kq
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
   // accumulator layout of the FP64 16x16x4 form: value v of a lane is row
@@ -91,11 +92,11 @@ __global__ __launch_bounds__(kFkThreads) void k_fk_contract(const double* __rest
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm * 32 + i * 16 + kq + 4 * v;
-        const int n = n0 + wn * 64 + j * 16 + r16;
+        const int n = n0 + wn * 32 + j * 16 + r16;
         if (m < nrep && n < ndat) T[(int64_t)m * ndat + n] = acc[i][j][v];
       }
 }
