@@ -214,189 +214,197 @@ def main():
         V["separate"] = {"ms_per_step": wall_sep * 1e3, "xfxq2_kernel_ms": k_sep,
                          "fused_speedup": wall_sep / wall64}
 
-        def rel_stats(o, ora, floor=1e-8):
-            ok = np.abs(ora) > floor
-            r = (np.abs(o - ora) / np.abs(ora))[ok]
-            return {"median_rel": float(np.median(r)), "p99_rel": float(np.percentile(r, 99)),
-                    "max_rel": float(r.max()), "frac_le_1e-3": float((r <= 1e-3).mean())}
+        def variants():
+            def rel_stats(o, ora, floor=1e-8):
+                ok = np.abs(ora) > floor
+                r = (np.abs(o - ora) / np.abs(ora))[ok]
+                return {"median_rel": float(np.median(r)), "p99_rel": float(np.percentile(r, 99)),
+                        "max_rel": float(r.max()), "frac_le_1e-3": float((r <= 1e-3).mean())}
 
-        # ---------------------------------------------------------- small (1e5)
-        log("small workload")
-        g1 = synth.config1_grid()
-        m1 = pdfmi.load_synth(g1)
-        x1, q1 = synth.config1_queries()
-        x1d, q1d = torch.from_numpy(x1).to(dev), torch.from_numpy(q1).to(dev)
-        o1 = torch.empty((len(x1), len(g1.pids)), dtype=torch.float64, device=dev)
-        ks = dtime(lambda: pdfmi.xfxq2(m1, g1.pids, x1d, q1d, out=o1), reps=20)
-        V["small"] = {"n_points": len(x1), "n_flavours": len(g1.pids), "kernel_ms": ks,
-                      "evals_per_s": len(x1) * len(g1.pids) / (ks * 1e-3)}
+            # ---------------------------------------------------------- small (1e5)
+            log("small workload")
+            g1 = synth.config1_grid()
+            m1 = pdfmi.load_synth(g1)
+            x1, q1 = synth.config1_queries()
+            x1d, q1d = torch.from_numpy(x1).to(dev), torch.from_numpy(q1).to(dev)
+            o1 = torch.empty((len(x1), len(g1.pids)), dtype=torch.float64, device=dev)
+            ks = dtime(lambda: pdfmi.xfxq2(m1, g1.pids, x1d, q1d, out=o1), reps=20)
+            V["small"] = {"n_points": len(x1), "n_flavours": len(g1.pids), "kernel_ms": ks,
+                          "evals_per_s": len(x1) * len(g1.pids) / (ks * 1e-3)}
 
-        # ---------------------------------------------------------- batched
-        log("batched workload: 101 members, 200 requests")
-        members = synth.config3_members()
-        mids = [pdfmi.load_synth(mg) for mg in members]
-        reqs_h = synth.config3_requests()
-        reqs = []
-        for r in reqs_h:
-            xr = torch.from_numpy(r["x"]).to(dev)
-            qr = torch.from_numpy(r["q2"]).to(dev)
-            orr = torch.empty((len(r["x"]), len(r["pids"])), dtype=torch.float32, device=dev)
-            reqs.append((mids[r["member"]], r["pids"], xr, qr, orr))
-        plan = pdfmi.BatchPlan(reqs)
-        tile, vec = plan.autotune(reps=2)
-        plan.configure(tile_points=tile, vector_cols=vec, use_graph=1)
-        tb = dtime(plan.run, reps=10)
-        npts = sum(len(r["x"]) for r in reqs_h)
-        nev = sum(len(r["x"]) * len(r["pids"]) for r in reqs_h)
-        o64 = [torch.empty((t[2].shape[0], len(t[1])), dtype=torch.float64, device=dev) for t in reqs]
+            # ---------------------------------------------------------- batched
+            log("batched workload: 101 members, 200 requests")
+            members = synth.config3_members()
+            mids = [pdfmi.load_synth(mg) for mg in members]
+            reqs_h = synth.config3_requests()
+            reqs = []
+            for r in reqs_h:
+                xr = torch.from_numpy(r["x"]).to(dev)
+                qr = torch.from_numpy(r["q2"]).to(dev)
+                orr = torch.empty((len(r["x"]), len(r["pids"])), dtype=torch.float32, device=dev)
+                reqs.append((mids[r["member"]], r["pids"], xr, qr, orr))
+            plan = pdfmi.BatchPlan(reqs)
+            tile, vec = plan.autotune(reps=2)
+            plan.configure(tile_points=tile, vector_cols=vec, use_graph=1)
+            tb = dtime(plan.run, reps=10)
+            npts = sum(len(r["x"]) for r in reqs_h)
+            nev = sum(len(r["x"]) * len(r["pids"]) for r in reqs_h)
+            o64 = [torch.empty((t[2].shape[0], len(t[1])), dtype=torch.float64, device=dev) for t in reqs]
 
-        def per_request_f64():
-            for t, o in zip(reqs, o64):
-                pdfmi.xfxq2(t[0], t[1], t[2], t[3], out=o)
-        tp = dtime(per_request_f64, reps=3)
-        # error of the batched FP32 output vs the FP64 oracle on a sample of requests
-        errs = []
-        for i in range(0, len(reqs_h), 25):
-            r = reqs_h[i]
-            mg = members[r["member"]]
-            k = min(2000, len(r["x"]))
-            ora = oracle.xfxq2(oracle.Grid(mg.xknots, mg.q2knots, mg.values, mg.pids), r["pids"], r["x"][:k],
-                               r["q2"][:k])
-            errs.append((reqs[i][4][:k].cpu().numpy().astype(np.float64), ora))
-        V["batched"] = {"members": len(mids), "requests": len(reqs), "points": npts, "evals": nev,
-                        "tile_points": tile, "vector_cols": vec, "graph": True, "ms": tb,
-                        "evals_per_s": nev / (tb * 1e-3), "per_request_f64_ms": tp,
-                        "speedup_vs_per_request_f64": tp / tb,
-                        "error_vs_oracle": rel_stats(np.concatenate([e[0].ravel() for e in errs]),
-                                                     np.concatenate([e[1].ravel() for e in errs]))}
-        plan.destroy()
-        del reqs, o64
-        for m_ in mids:
-            pdfmi.unload(m_)
-
-        # ---------------------------------------------------------- surrogate
-        log("surrogate: training on 2e6 samples")
-        xt, qt = synth.config1_queries(n=2_000_000, seed=40)
-        sur = pdfmi.Surrogate(m1, seed=3)
-        sur.set_data(torch.from_numpy(xt).to(dev), torch.from_numpy(qt).to(dev))
-        t0 = time.perf_counter()
-        sur.train(args.sur_steps, 4096, 3e-3, 3e-5, args.sur_steps)
-        torch.cuda.synchronize()
-        ttrain = time.perf_counter() - t0
-        xs, qs = synth.config1_queries(n=10_000_000, seed=41)
-        xsd, qsd = torch.from_numpy(xs).to(dev), torch.from_numpy(qs).to(dev)
-        P1 = len(g1.pids)
-        so = torch.empty((len(xs), P1), dtype=torch.float32, device=dev)
-        ref64 = torch.empty((len(xs), P1), dtype=torch.float64, device=dev)
-        ref32 = torch.empty((len(xs), P1), dtype=torch.float32, device=dev)
-        t_sur = dtime(lambda: sur.xfxq2(xsd, qsd, P1, out=so))
-        t_i64 = dtime(lambda: pdfmi.xfxq2(m1, g1.pids, xsd, qsd, out=ref64))
-        t_i32 = dtime(lambda: pdfmi.xfxq2_f32(m1, g1.pids, xsd, qsd, out=ref32))
-        idx = np.random.default_rng(0).choice(len(xs), 20000, replace=False)
-        ora = oracle.xfxq2(oracle.Grid(g1.xknots, g1.q2knots, g1.values, g1.pids), g1.pids, xs[idx], qs[idx])
-        idx_t = torch.from_numpy(idx).to(dev)
-        V["surrogate"] = {"n_points": len(xs), "n_flavours": P1, "train_s": ttrain, "train_steps": args.sur_steps,
-                          "ms": t_sur, "evals_per_s": len(xs) * P1 / (t_sur * 1e-3),
-                          "interp_f64_ms": t_i64, "interp_f32_ms": t_i32,
-                          "speedup_vs_f64_interp": t_i64 / t_sur, "speedup_vs_f32_interp": t_i32 / t_sur,
-                          "error_vs_oracle": rel_stats(so[idx_t].cpu().numpy().astype(np.float64), ora)}
-        del ref32
-
-        # ---------------------------------------------------------- Monte-Carlo load
-        nchunk = args.mc_chunks
-        log("mc workload: %d chunks of 1e6 points" % nchunk)
-        qk1, a1 = synth.config1_alphas()
-        pdfmi.load_alphas(qk1, a1)
-        ch = [synth.config5_chunk(c) for c in range(nchunk)]
-        X1 = [torch.from_numpy(c[0]).to(dev) for c in ch]
-        X2 = [torch.from_numpy(c[1]).to(dev) for c in ch]
-        Q = [torch.from_numpy(c[2]).to(dev) for c in ch]
-        PIDS = synth.PIDS_13
-        n_c = len(ch[0][0])
-        f1_64 = torch.empty((n_c, 13), dtype=torch.float64, device=dev)
-        f2_64 = torch.empty_like(f1_64)
-        f1_32 = torch.empty((n_c, 13), dtype=torch.float32, device=dev)
-        f2_32 = torch.empty_like(f1_32)
-        s1 = torch.empty((n_c, P1), dtype=torch.float32, device=dev)
-        s2 = torch.empty_like(s1)
-        al = torch.empty(n_c, dtype=torch.float64, device=dev)
-        ws = pdfmi.mc_workspace(n_c, dev)
-        sums = {k: torch.empty(nchunk, dtype=torch.float64, device=dev) for k in ("f64", "f32", "sur")}
-
-        def run_mc(kind):
-            for c in range(nchunk):
-                pdfmi.alphas_q2(Q[c], out=al)
-                if kind == "f64":
-                    pdfmi.xfxq2(m1, PIDS, X1[c], Q[c], out=f1_64)
-                    pdfmi.xfxq2(m1, PIDS, X2[c], Q[c], out=f2_64)
-                    pdfmi.mc_chunk_sum(f1_64, f2_64, al, workspace=ws, out=sums[kind][c:c + 1])
-                elif kind == "f32":
-                    pdfmi.xfxq2_f32(m1, PIDS, X1[c], Q[c], out=f1_32)
-                    pdfmi.xfxq2_f32(m1, PIDS, X2[c], Q[c], out=f2_32)
-                    pdfmi.mc_chunk_sum(f1_32, f2_32, al, workspace=ws, out=sums[kind][c:c + 1])
-                else:   # surrogate gives the stored flavours; absent ones are zero and add nothing
-                    sur.xfxq2(X1[c], Q[c], P1, out=s1)
-                    sur.xfxq2(X2[c], Q[c], P1, out=s2)
-                    pdfmi.mc_chunk_sum(s1, s2, al, workspace=ws, out=sums[kind][c:c + 1])
-        sums["f64_fused"] = torch.empty(nchunk, dtype=torch.float64, device=dev)
-        sums["f32_fused"] = torch.empty(nchunk, dtype=torch.float64, device=dev)
-
-        def run_fused(kind):
-            for c in range(nchunk):
-                pdfmi.mc_fused(m1, PIDS, X1[c], X2[c], Q[c], f32=(kind == "f32_fused"), workspace=ws,
-                               out=sums[kind][c:c + 1])
-        mc = {"points": nchunk * n_c, "chunks": nchunk, "evals_per_point": 26}
-        for kind in ("f64", "f32", "sur", "f64_fused", "f32_fused"):
-            fn = (lambda: run_fused(kind)) if kind.endswith("_fused") else (lambda: run_mc(kind))
-            ms = dtime(fn, reps=1)
-            mc[kind] = {"ms": ms, "evals_per_s": nchunk * n_c * 26 / (ms * 1e-3)}
-        tot = {k: float(sums[k].sum().item()) for k in sums}
-        # chunk 0 against the oracle
-        og1 = oracle.Grid(g1.xknots, g1.q2knots, g1.values, g1.pids)
-        th = max(1, min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1))
-        oc1 = oracle.xfxq2(og1, PIDS, ch[0][0], ch[0][2], n_threads=th)
-        oc2 = oracle.xfxq2(og1, PIDS, ch[0][1], ch[0][2], n_threads=th)
-        oa = oracle.alphas_q2(qk1, a1, ch[0][2])
-        s0 = math.fsum(oa * np.sum(oc1 * oc2, axis=1))
-        for kind in ("f64", "f32", "sur", "f64_fused", "f32_fused"):
-            mc[kind]["chunk0_rel_err_vs_oracle"] = abs(float(sums[kind][0].item()) - s0) / abs(s0)
-            mc[kind]["total"] = tot[kind]
-            mc[kind]["speedup_vs_f64"] = mc["f64"]["ms"] / mc[kind]["ms"]
-        mc["fused_bit_identical"] = {
-            "f64": bool(torch.equal(sums["f64"].view(torch.int64), sums["f64_fused"].view(torch.int64))),
-            "f32": bool(torch.equal(sums["f32"].view(torch.int64), sums["f32_fused"].view(torch.int64)))}
-        V["mc"] = mc
-        sur.destroy()
-        del X1, X2, Q
-
-        # ---------------------------------------------------------- multi-member x grid + FK contraction
-        log("multi-member evaluation on a 2415-point x grid and FK contraction")
-        nx_fk, ndat = 2415, 1024
-        fk_members = synth.config3_members(n_members=400)
-        fk_ids = [pdfmi.load_synth(mg) for mg in fk_members]
-        xg = torch.from_numpy(np.exp(np.linspace(np.log(2e-6), np.log(0.95), nx_fk))).to(dev)
-        qg = torch.full((nx_fk,), 1.65 ** 2, dtype=torch.float64, device=dev)
-        table = torch.from_numpy(np.random.default_rng(11).normal(size=(ndat, nx_fk * 13))).to(dev)
-        paper_gpu_s = {10: 0.07, 50: 0.35, 100: 0.69, 200: 1.46, 300: 1.29, 400: 1.69}
-        fkv = {"x_points": nx_fk, "flavours": 13, "q": 1.65, "ndat": ndat, "rows": []}
-        for nrep in (10, 50, 100, 200, 300, 400):
-            F = torch.empty((nrep, nx_fk, 13), dtype=torch.float64, device=dev)
-            plan = pdfmi.BatchPlan([(fk_ids[r], synth.PIDS_13, xg, qg, F[r]) for r in range(nrep)], out_f64=True)
-            plan.configure(tile_points=2048, vector_cols=1, use_graph=1)
-            t_eval = dtime(plan.run, reps=5)
-            Fm = F.reshape(nrep, -1)
-            T = torch.empty((nrep, ndat), dtype=torch.float64, device=dev)
-            t_fk = dtime(lambda: pdfmi.fk_contract(Fm, table, out=T), reps=5)
-            flops = 2.0 * nrep * ndat * nx_fk * 13
-            fkv["rows"].append({"nrep": nrep, "eval_ms": t_eval, "evals_per_s": nrep * nx_fk * 13 / (t_eval * 1e-3),
-                                "contract_ms": t_fk, "contract_tflops": flops / (t_fk * 1e-3) / 1e12,
-                                "contract_frac_fp64_peak": flops / (t_fk * 1e-3) / 78.6e12,
-                                "paper_table2_gpu_s_context": paper_gpu_s[nrep]})
+            def per_request_f64():
+                for t, o in zip(reqs, o64):
+                    pdfmi.xfxq2(t[0], t[1], t[2], t[3], out=o)
+            tp = dtime(per_request_f64, reps=3)
+            # error of the batched FP32 output vs the FP64 oracle on a sample of requests
+            errs = []
+            for i in range(0, len(reqs_h), 25):
+                r = reqs_h[i]
+                mg = members[r["member"]]
+                k = min(2000, len(r["x"]))
+                ora = oracle.xfxq2(oracle.Grid(mg.xknots, mg.q2knots, mg.values, mg.pids), r["pids"], r["x"][:k],
+                                   r["q2"][:k])
+                errs.append((reqs[i][4][:k].cpu().numpy().astype(np.float64), ora))
+            V["batched"] = {"members": len(mids), "requests": len(reqs), "points": npts, "evals": nev,
+                            "tile_points": tile, "vector_cols": vec, "graph": True, "ms": tb,
+                            "evals_per_s": nev / (tb * 1e-3), "per_request_f64_ms": tp,
+                            "speedup_vs_per_request_f64": tp / tb,
+                            "error_vs_oracle": rel_stats(np.concatenate([e[0].ravel() for e in errs]),
+                                                         np.concatenate([e[1].ravel() for e in errs]))}
             plan.destroy()
-            del F, T
-        V["members_fk"] = fkv
-        for m_ in fk_ids:
-            pdfmi.unload(m_)
+            del reqs, o64
+            for m_ in mids:
+                pdfmi.unload(m_)
+
+            # ---------------------------------------------------------- surrogate
+            log("surrogate: training on 2e6 samples")
+            xt, qt = synth.config1_queries(n=2_000_000, seed=40)
+            sur = pdfmi.Surrogate(m1, seed=3)
+            sur.set_data(torch.from_numpy(xt).to(dev), torch.from_numpy(qt).to(dev))
+            t0 = time.perf_counter()
+            sur.train(args.sur_steps, 4096, 3e-3, 3e-5, args.sur_steps)
+            torch.cuda.synchronize()
+            ttrain = time.perf_counter() - t0
+            xs, qs = synth.config1_queries(n=10_000_000, seed=41)
+            xsd, qsd = torch.from_numpy(xs).to(dev), torch.from_numpy(qs).to(dev)
+            P1 = len(g1.pids)
+            so = torch.empty((len(xs), P1), dtype=torch.float32, device=dev)
+            ref64 = torch.empty((len(xs), P1), dtype=torch.float64, device=dev)
+            ref32 = torch.empty((len(xs), P1), dtype=torch.float32, device=dev)
+            t_sur = dtime(lambda: sur.xfxq2(xsd, qsd, P1, out=so))
+            t_i64 = dtime(lambda: pdfmi.xfxq2(m1, g1.pids, xsd, qsd, out=ref64))
+            t_i32 = dtime(lambda: pdfmi.xfxq2_f32(m1, g1.pids, xsd, qsd, out=ref32))
+            idx = np.random.default_rng(0).choice(len(xs), 20000, replace=False)
+            ora = oracle.xfxq2(oracle.Grid(g1.xknots, g1.q2knots, g1.values, g1.pids), g1.pids, xs[idx], qs[idx])
+            idx_t = torch.from_numpy(idx).to(dev)
+            V["surrogate"] = {"n_points": len(xs), "n_flavours": P1, "train_s": ttrain, "train_steps": args.sur_steps,
+                              "ms": t_sur, "evals_per_s": len(xs) * P1 / (t_sur * 1e-3),
+                              "interp_f64_ms": t_i64, "interp_f32_ms": t_i32,
+                              "speedup_vs_f64_interp": t_i64 / t_sur, "speedup_vs_f32_interp": t_i32 / t_sur,
+                              "error_vs_oracle": rel_stats(so[idx_t].cpu().numpy().astype(np.float64), ora)}
+            del ref32
+
+            # ---------------------------------------------------------- Monte-Carlo load
+            nchunk = args.mc_chunks
+            log("mc workload: %d chunks of 1e6 points" % nchunk)
+            qk1, a1 = synth.config1_alphas()
+            pdfmi.load_alphas(qk1, a1)
+            ch = [synth.config5_chunk(c) for c in range(nchunk)]
+            X1 = [torch.from_numpy(c[0]).to(dev) for c in ch]
+            X2 = [torch.from_numpy(c[1]).to(dev) for c in ch]
+            Q = [torch.from_numpy(c[2]).to(dev) for c in ch]
+            PIDS = synth.PIDS_13
+            n_c = len(ch[0][0])
+            f1_64 = torch.empty((n_c, 13), dtype=torch.float64, device=dev)
+            f2_64 = torch.empty_like(f1_64)
+            f1_32 = torch.empty((n_c, 13), dtype=torch.float32, device=dev)
+            f2_32 = torch.empty_like(f1_32)
+            s1 = torch.empty((n_c, P1), dtype=torch.float32, device=dev)
+            s2 = torch.empty_like(s1)
+            al = torch.empty(n_c, dtype=torch.float64, device=dev)
+            ws = pdfmi.mc_workspace(n_c, dev)
+            sums = {k: torch.empty(nchunk, dtype=torch.float64, device=dev) for k in ("f64", "f32", "sur")}
+
+            def run_mc(kind):
+                for c in range(nchunk):
+                    pdfmi.alphas_q2(Q[c], out=al)
+                    if kind == "f64":
+                        pdfmi.xfxq2(m1, PIDS, X1[c], Q[c], out=f1_64)
+                        pdfmi.xfxq2(m1, PIDS, X2[c], Q[c], out=f2_64)
+                        pdfmi.mc_chunk_sum(f1_64, f2_64, al, workspace=ws, out=sums[kind][c:c + 1])
+                    elif kind == "f32":
+                        pdfmi.xfxq2_f32(m1, PIDS, X1[c], Q[c], out=f1_32)
+                        pdfmi.xfxq2_f32(m1, PIDS, X2[c], Q[c], out=f2_32)
+                        pdfmi.mc_chunk_sum(f1_32, f2_32, al, workspace=ws, out=sums[kind][c:c + 1])
+                    else:   # surrogate gives the stored flavours; absent ones are zero and add nothing
+                        sur.xfxq2(X1[c], Q[c], P1, out=s1)
+                        sur.xfxq2(X2[c], Q[c], P1, out=s2)
+                        pdfmi.mc_chunk_sum(s1, s2, al, workspace=ws, out=sums[kind][c:c + 1])
+            sums["f64_fused"] = torch.empty(nchunk, dtype=torch.float64, device=dev)
+            sums["f32_fused"] = torch.empty(nchunk, dtype=torch.float64, device=dev)
+
+            def run_fused(kind):
+                for c in range(nchunk):
+                    pdfmi.mc_fused(m1, PIDS, X1[c], X2[c], Q[c], f32=(kind == "f32_fused"), workspace=ws,
+                                   out=sums[kind][c:c + 1])
+            mc = {"points": nchunk * n_c, "chunks": nchunk, "evals_per_point": 26}
+            for kind in ("f64", "f32", "sur", "f64_fused", "f32_fused"):
+                fn = (lambda: run_fused(kind)) if kind.endswith("_fused") else (lambda: run_mc(kind))
+                ms = dtime(fn, reps=1)
+                mc[kind] = {"ms": ms, "evals_per_s": nchunk * n_c * 26 / (ms * 1e-3)}
+            tot = {k: float(sums[k].sum().item()) for k in sums}
+            # chunk 0 against the oracle
+            og1 = oracle.Grid(g1.xknots, g1.q2knots, g1.values, g1.pids)
+            th = max(1, min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1))
+            oc1 = oracle.xfxq2(og1, PIDS, ch[0][0], ch[0][2], n_threads=th)
+            oc2 = oracle.xfxq2(og1, PIDS, ch[0][1], ch[0][2], n_threads=th)
+            oa = oracle.alphas_q2(qk1, a1, ch[0][2])
+            s0 = math.fsum(oa * np.sum(oc1 * oc2, axis=1))
+            for kind in ("f64", "f32", "sur", "f64_fused", "f32_fused"):
+                mc[kind]["chunk0_rel_err_vs_oracle"] = abs(float(sums[kind][0].item()) - s0) / abs(s0)
+                mc[kind]["total"] = tot[kind]
+                mc[kind]["speedup_vs_f64"] = mc["f64"]["ms"] / mc[kind]["ms"]
+            mc["fused_bit_identical"] = {
+                "f64": bool(torch.equal(sums["f64"].view(torch.int64), sums["f64_fused"].view(torch.int64))),
+                "f32": bool(torch.equal(sums["f32"].view(torch.int64), sums["f32_fused"].view(torch.int64)))}
+            V["mc"] = mc
+            sur.destroy()
+            del X1, X2, Q
+
+            # ---------------------------------------------------------- multi-member x grid + FK contraction
+            log("multi-member evaluation on a 2415-point x grid and FK contraction")
+            nx_fk, ndat = 2415, 1024
+            fk_members = synth.config3_members(n_members=400)
+            fk_ids = [pdfmi.load_synth(mg) for mg in fk_members]
+            xg = torch.from_numpy(np.exp(np.linspace(np.log(2e-6), np.log(0.95), nx_fk))).to(dev)
+            qg = torch.full((nx_fk,), 1.65 ** 2, dtype=torch.float64, device=dev)
+            table = torch.from_numpy(np.random.default_rng(11).normal(size=(ndat, nx_fk * 13))).to(dev)
+            paper_gpu_s = {10: 0.07, 50: 0.35, 100: 0.69, 200: 1.46, 300: 1.29, 400: 1.69}
+            fkv = {"x_points": nx_fk, "flavours": 13, "q": 1.65, "ndat": ndat, "rows": []}
+            for nrep in (10, 50, 100, 200, 300, 400):
+                F = torch.empty((nrep, nx_fk, 13), dtype=torch.float64, device=dev)
+                plan = pdfmi.BatchPlan([(fk_ids[r], synth.PIDS_13, xg, qg, F[r]) for r in range(nrep)], out_f64=True)
+                plan.configure(tile_points=2048, vector_cols=1, use_graph=1)
+                t_eval = dtime(plan.run, reps=5)
+                Fm = F.reshape(nrep, -1)
+                T = torch.empty((nrep, ndat), dtype=torch.float64, device=dev)
+                t_fk = dtime(lambda: pdfmi.fk_contract(Fm, table, out=T), reps=5)
+                flops = 2.0 * nrep * ndat * nx_fk * 13
+                fkv["rows"].append({"nrep": nrep, "eval_ms": t_eval, "evals_per_s": nrep * nx_fk * 13 / (t_eval * 1e-3),
+                                    "contract_ms": t_fk, "contract_tflops": flops / (t_fk * 1e-3) / 1e12,
+                                    "contract_frac_fp64_peak": flops / (t_fk * 1e-3) / 78.6e12,
+                                    "paper_table2_gpu_s_context": paper_gpu_s[nrep]})
+                plan.destroy()
+                del F, T
+            V["members_fk"] = fkv
+            for m_ in fk_ids:
+                pdfmi.unload(m_)
+
+        try:
+            variants()
+        except Exception as exc:  # a failing variant must not cost the headline line
+            import traceback
+            traceback.print_exc()
+            V["error"] = "%s: %s" % (type(exc).__name__, exc)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")
