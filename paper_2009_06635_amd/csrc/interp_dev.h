@@ -122,10 +122,80 @@ struct PointLoc {
   double p0, p1; // extrapolation parameters
 };
 
-// Phase 1: everything that depends on the point only, in two halves: the Q^2
-// half (validity of Q^2, region bits, sub-grid, Q^2 cell and weights) is
-// shared by every point at the same Q^2 (the two lookups of a Monte-Carlo
-// point); the x half completes the location.
+// Phase 1: everything that depends on the point only.
+template <typename T>
+__device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const Tables& tb, double x, double q2, T w[4],
+                                                 T v[4]) {
+  PointLoc L;
+  L.p0 = 0.0;
+  L.p1 = 0.0;
+  const bool valid = (x > 0.0) && (x <= m.xmax) && (q2 > 0.0) && (q2 < INFINITY);
+  if (!valid) {
+    L.mode = kInvalid;
+    L.k = L.ix = L.iq = -1;
+    L.sx = L.sq = 0;
+    L.base = 0;
+    L.sa = 0;
+    for (int a = 0; a < 4; ++a) w[a] = v[a] = (T)0;
+    return L;
+  }
+  int mode = 0;
+  if (x < m.xmin) mode |= kLowX;
+  if (q2 < m.qmin) mode |= kLowQ;
+  if (q2 > m.qmax) mode |= kHighQ;
+  int k = 0;
+  for (int j = 1; j < m.K; ++j)
+    if (m.sub[j].qfirst <= q2) k = j;
+  const SubDesc S = tb.subs[k];
+  const int ix = find_cell_hint(tb.knots + S.xk_off, S.nx, x, S.xh, tb.hints);
+  const int iq = find_cell_hint(tb.knots + S.qk_off, S.nq, q2, S.qh, tb.hints);
+  const CellCoef cx = tb.cells[S.xc_off + ix];
+  const CellCoef cq = tb.cells[S.qc_off + iq];
+  const int sx = min(max(ix - 1, 0), S.nxp - 4);
+  const int sq = min(max(iq - 1, 0), S.nqp - 4);
+  // one logarithm per axis whatever the region: below x_0 the cell is the
+  // first one and ux = ln(x/x_0) / ln(x_1/x_0) is the continuation parameter
+  // itself; above the last Q^2 knot uq - 1 = ln(Q^2/q_n-1) / ln(q_n-1/q_n-2)
+  const double ux = cell_u(x, cx);
+  const double uq = cell_u(q2, cq);
+  if (!(mode & kLowX)) {
+    stencil_weights<T>(ux, cx, ix - sx, w);
+  } else {
+    for (int a = 0; a < 4; ++a) w[a] = (T)0;
+    if (mode & (kLowQ | kHighQ)) L.p1 = ux; else L.p0 = ux;
+  }
+  if (!(mode & (kLowQ | kHighQ))) {
+    stencil_weights<T>(uq, cq, iq - sq, v);
+  } else {
+    for (int b = 0; b < 4; ++b) v[b] = (T)0;
+    if (mode & kLowQ) {
+      L.p0 = q2 * cq.inv_t0;                       // r = Q^2 / Q^2_0
+    } else {
+      L.p0 = uq - 1.0;                             // s = ln(Q^2/q_n-1) / ln(q_n-1/q_n-2)
+      mode |= (S.nq - 2 - sq) << 8;                // stencil row of q_n-2
+    }
+  }
+  if (x > 0.9) mode |= kXHigh;
+  L.mode = mode;
+  L.k = k;
+  L.ix = ix;
+  L.iq = iq;
+  L.sx = sx;
+  L.sq = sq;
+  const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
+  L.sa = S.nqp * Pp;
+  L.base = (int)((sizeof(T) == 8 ? S.val_off64 : S.val_off32) + (int64_t)(sx * S.nqp + sq) * Pp);
+  return L;
+}
+
+// The same location in two halves, for points that share Q^2 (the two
+// lookups of a Monte-Carlo point): the Q^2 half (validity of Q^2, region bits,
+// sub-grid, Q^2 cell and weights) is computed once, the x half completes each
+// location.  locate_x(locate_q(q2), x) equals locate_point(x, q2) field by
+// field (the fused Monte-Carlo sum, which uses the halves, is compared bit
+// for bit with the unfused one, which uses locate_point); locate_point stays
+// one function because the split form compiles to a slower schedule in the
+// fused x*f + alpha_s kernel.
 template <typename T>
 struct QLoc {
   int mode;      // kInvalid (Q^2 <= 0 or not finite), else kLowQ | kHighQ | (anchor row << 8)
@@ -217,12 +287,6 @@ __device__ __forceinline__ PointLoc locate_x(const MemberDev& m, const Tables& t
   L.sa = S.nqp * Pp;
   L.base = (int)((sizeof(T) == 8 ? S.val_off64 : S.val_off32) + (int64_t)(sx * S.nqp + Q.sq) * Pp);
   return L;
-}
-
-template <typename T>
-__device__ __forceinline__ PointLoc locate_point(const MemberDev& m, const Tables& tb, double x, double q2, T w[4],
-                                                 T v[4]) {
-  return locate_x<T>(m, tb, locate_q<T>(m, tb, q2), x, w, v);
 }
 
 // Two-anchor continuation (log-linear when both anchors exceed 1e-3).
