@@ -229,8 +229,10 @@ def main():
             x1d, q1d = torch.from_numpy(x1).to(dev), torch.from_numpy(q1).to(dev)
             o1 = torch.empty((len(x1), len(g1.pids)), dtype=torch.float64, device=dev)
             ks = dtime(lambda: pdfmi.xfxq2(m1, g1.pids, x1d, q1d, out=o1), reps=20)
+            sb = len(x1) * (16 + 8 * len(g1.pids))
             V["small"] = {"n_points": len(x1), "n_flavours": len(g1.pids), "kernel_ms": ks,
-                          "evals_per_s": len(x1) * len(g1.pids) / (ks * 1e-3)}
+                          "evals_per_s": len(x1) * len(g1.pids) / (ks * 1e-3),
+                          "achieved_GBs": sb / (ks * 1e-3) / 1e9, "frac_hbm": sb / (ks * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
             # ---------------------------------------------------------- batched
             log("batched workload: 101 members, 200 requests")
@@ -264,9 +266,11 @@ def main():
                 ora = oracle.xfxq2(oracle.Grid(mg.xknots, mg.q2knots, mg.values, mg.pids), r["pids"], r["x"][:k],
                                    r["q2"][:k])
                 errs.append((reqs[i][4][:k].cpu().numpy().astype(np.float64), ora))
+            bb = npts * 16 + nev * 4  # (x, Q^2) in, FP32 values out
             V["batched"] = {"members": len(mids), "requests": len(reqs), "points": npts, "evals": nev,
                             "tile_points": tile, "vector_cols": vec, "graph": True, "ms": tb,
-                            "evals_per_s": nev / (tb * 1e-3), "per_request_f64_ms": tp,
+                            "evals_per_s": nev / (tb * 1e-3), "achieved_GBs": bb / (tb * 1e-3) / 1e9,
+                            "frac_hbm": bb / (tb * 1e-3) / 1e9 / HBM_PEAK_GBS, "per_request_f64_ms": tp,
                             "speedup_vs_per_request_f64": tp / tb,
                             "error_vs_oracle": rel_stats(np.concatenate([e[0].ravel() for e in errs]),
                                                          np.concatenate([e[1].ravel() for e in errs]))}
@@ -296,8 +300,14 @@ def main():
             idx = np.random.default_rng(0).choice(len(xs), 20000, replace=False)
             ora = oracle.xfxq2(oracle.Grid(g1.xknots, g1.q2knots, g1.values, g1.pids), g1.pids, xs[idx], qs[idx])
             idx_t = torch.from_numpy(idx).to(dev)
+            # network arithmetic per point: 2*64 + 64*64 + 64*64 + 64*16 multiply-adds (16 outputs incl.
+            # padding), 3*64 tanh; layers 2-4 on the BF16 matrix cores (2.5 PFLOP/s dense peak)
+            mfma_flop = 2.0 * (64 * 64 * 2 + 64 * 16) * len(xs)
             V["surrogate"] = {"n_points": len(xs), "n_flavours": P1, "train_s": ttrain, "train_steps": args.sur_steps,
                               "ms": t_sur, "evals_per_s": len(xs) * P1 / (t_sur * 1e-3),
+                              "mfma_TFLOPs": mfma_flop / (t_sur * 1e-3) / 1e12,
+                              "frac_bf16_mfma_peak": mfma_flop / (t_sur * 1e-3) / 2.5e15,
+                              "tanh_per_s": 3 * 64 * len(xs) / (t_sur * 1e-3),
                               "interp_f64_ms": t_i64, "interp_f32_ms": t_i32,
                               "speedup_vs_f64_interp": t_i64 / t_sur, "speedup_vs_f32_interp": t_i32 / t_sur,
                               "error_vs_oracle": rel_stats(so[idx_t].cpu().numpy().astype(np.float64), ora)}
@@ -363,6 +373,9 @@ def main():
                 mc[kind]["chunk0_rel_err_vs_oracle"] = abs(float(sums[kind][0].item()) - s0) / abs(s0)
                 mc[kind]["total"] = tot[kind]
                 mc[kind]["speedup_vs_f64"] = mc["f64"]["ms"] / mc[kind]["ms"]
+            for kind in ("f64_fused", "f32_fused"):   # 24 B of (x1, x2, Q^2) per point in, one sum per chunk out
+                mc[kind]["achieved_GBs"] = 24.0 * mc["points"] / (mc[kind]["ms"] * 1e-3) / 1e9
+                mc[kind]["frac_hbm"] = mc[kind]["achieved_GBs"] / HBM_PEAK_GBS
             mc["fused_bit_identical"] = {
                 "f64": bool(torch.equal(sums["f64"].view(torch.int64), sums["f64_fused"].view(torch.int64))),
                 "f32": bool(torch.equal(sums["f32"].view(torch.int64), sums["f32_fused"].view(torch.int64)))}
