@@ -371,7 +371,9 @@ int pdf_mc_fused_f32(int32_t member, const int32_t* pids, int32_t n_pids,
  * device [nrep][ndat].  K = 0 gives zeros.  For long K the sum is split into
  * slices whose partial sums the library keeps in a workspace it allocates on
  * first need and reuses (grown, after synchronising the stream, when a
- * larger one is needed; freed by pdf_shutdown).  Errors: PDF_ERR_ARG
+ * larger one is needed; freed by pdf_shutdown).  Every call uses that one
+ * workspace: calls on different streams must not run concurrently (calls on
+ * one stream are ordered by the stream).  Errors: PDF_ERR_ARG
  * (negative sizes, nrep > 2^22, null pointers), PDF_ERR_NOMEM,
  * PDF_ERR_DEVICE.  Asynchronous on stream.
  */
