@@ -45,10 +45,12 @@ __device__ __forceinline__ float bf16_float(unsigned short b) {
 // exp2 overflows to +inf (result 1) and underflows to 0 (result -1); near 0
 // the absolute error is a few 1e-8, far below the BF16 rounding of the
 // activations.
-__device__ __forceinline__ float tanh_f(float z) {
-  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * z);  // 2 z log2(e)
-  return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+constexpr float kTwoLog2e = 2.8853900817779268f;  // 2 log2(e)
+// tanh(z) from zs = 2 log2(e) z (inference folds the factor into its weights and biases)
+__device__ __forceinline__ float tanh_scaled(float zs) {
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(zs) + 1.0f), 1.0f);
 }
+__device__ __forceinline__ float tanh_f(float z) { return tanh_scaled(kTwoLog2e * z); }
 
 // ---------------------------------------------------------------------------------------
 // Generic BF16 GEMM tile: C[m][n] = sum_k A(m,k) B(k,n) (+ bias[n]) (then tanh)
@@ -240,7 +242,8 @@ struct FbRec {
   double p0, p1;           // extrapolation parameters
 };
 
-// LDS of k_sur_infer: [nx] ln x knots, [nx][16] envelope, W1 (BF16-rounded),
+// LDS of k_sur_infer: [nx] ln x knots, [nx][16] envelope, W1 (BF16-rounded; W1 and
+// b1-b3 times 2 log2(e)),
 // b1, b2, b3, b4, then per wave the fallback records, the activation tile and
 // the point records.
 size_t sur_infer_shared_bytes(int nx) {
@@ -269,11 +272,13 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
   float* spt = reinterpret_cast<float*>(shs + kSurWaves * 16 * kH);                // [waves][64][4]
   for (int i = threadIdx.x; i < S.nx; i += 64 * kSurWaves) slxk[i] = S.lxk[i];
   for (int i = threadIdx.x; i < S.nx * kO; i += 64 * kSurWaves) senv[i] = S.env[i];
-  for (int i = threadIdx.x; i < 2 * kH; i += 64 * kSurWaves) sw1[i] = bf16_float(bf16_bits(Pf[kOffW1 + i]));
+  // hidden-layer weights and biases staged times 2 log2(e), the argument scale of tanh_scaled
+  for (int i = threadIdx.x; i < 2 * kH; i += 64 * kSurWaves)
+    sw1[i] = kTwoLog2e * bf16_float(bf16_bits(Pf[kOffW1 + i]));
   for (int i = threadIdx.x; i < kH; i += 64 * kSurWaves) {
-    sb1[i] = Pf[kOffB1 + i];
-    sb2[i] = Pf[kOffB2 + i];
-    sb3[i] = Pf[kOffB3 + i];
+    sb1[i] = kTwoLog2e * Pf[kOffB1 + i];
+    sb2[i] = kTwoLog2e * Pf[kOffB2 + i];
+    sb3[i] = kTwoLog2e * Pf[kOffB3 + i];
   }
   for (int i = threadIdx.x; i < kO; i += 64 * kSurWaves) sb4[i] = Pf[kOffB4 + i];
   __syncthreads();
@@ -340,8 +345,8 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const int j = 32 * s + 8 * g + i;
-          const float z = fmaf(sw1[2 * j], u, fmaf(sw1[2 * j + 1], v, sb1[j]));
-          a[s][i] = __builtin_bit_cast(__bf16, bf16_bits(tanh_f(z)));
+          const float zs = fmaf(sw1[2 * j], u, fmaf(sw1[2 * j + 1], v, sb1[j]));
+          a[s][i] = __builtin_bit_cast(__bf16, bf16_bits(tanh_scaled(zs)));
         }
       // layers 2 and 3
 #pragma unroll
@@ -354,7 +359,7 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], layer == 0 ? w2[t][1] : w3[t][1], acc, 0, 0, 0);
           const float bn = bl[16 * t + r];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) hs[(4 * g + i) * kH + 16 * t + r] = bf16_bits(tanh_f(acc[i] + bn));
+          for (int i = 0; i < 4; ++i) hs[(4 * g + i) * kH + 16 * t + r] = bf16_bits(tanh_scaled(fmaf(acc[i], kTwoLog2e, bn)));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
