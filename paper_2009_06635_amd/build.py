@@ -29,7 +29,25 @@ def build(verbose=False):
     if verbose and out.strip():
         print(out)
     os.replace(tmp, LIB)
+    build_capi_demo(verbose)
     return LIB
+
+
+def build_capi_demo(verbose=False):
+    """tests/capi_demo: a plain C consumer of the ABI (gcc, HIP runtime headers)."""
+    src = os.path.join(ROOT, "tests", "capi_demo.c")
+    exe = os.path.join(ROOT, "tests", "capi_demo")
+    tmp = exe + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", "/opt/rocm/include", src, "-L", HERE, "-lpdfmi", "-L", "/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/../paper_2009_06635_amd", "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("gcc (capi_demo) failed:\n" + res.stdout + res.stderr)
+    os.replace(tmp, exe)
+    return exe
 
 
 if __name__ == "__main__":

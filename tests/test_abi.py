@@ -2,6 +2,7 @@
 and its host-only validation rejects malformed input (no GPU calls)."""
 import ctypes
 import os
+import subprocess
 import re
 
 import numpy as np
@@ -110,3 +111,13 @@ def test_validate_alphas(lib):
     assert v([1, 3, 2], [0.1] * 3) == -2
     assert v([1, 2, 3], [0.1, np.nan, 0.1]) == -2
     assert v([0, 2, 3], [0.1] * 3) == -2
+
+
+def test_capi_demo_is_built_against_the_library():
+    """tests/capi_demo (a plain C consumer of include/pdfmi.h) is built with the library."""
+    exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "capi_demo")
+    if not os.path.exists(exe):
+        pytest.skip("library not built")
+    assert os.access(exe, os.X_OK)
+    out = subprocess.run(["ldd", exe], capture_output=True, text=True).stdout
+    assert "libpdfmi.so" in out
