@@ -300,3 +300,26 @@ def test_outputs_beyond_4_gib(cfg2):
     qk, av = synth.config2_alphas()
     oa = oracle.alphas_q2(qk, av, q2[idx])
     assert np.max(np.abs(sa - oa) / np.abs(oa)) < 1e-13
+
+
+def test_extreme_but_valid_inputs(cfg2):
+    """Subnormal and huge (but valid) x and Q^2: far extrapolation on both
+    sides; values compared where the oracle is finite and moderate, and the
+    two sides agree on which results are finite."""
+    g, m = cfg2
+    xs = np.array([5e-324, 1e-310, 1e-300, 1e-200, 1e-100, 1e-20, 1e-12, 0.999999, 1.0])
+    qs = np.array([5e-324, 1e-300, 1e-100, 1e-10, 0.25, 10.0, 1e20, 1e100, 1e300])
+    x, q2 = np.meshgrid(xs, qs, indexing="ij")
+    x, q2 = x.ravel(), q2.ravel()
+    out = pdfmi.xfxq2(m, g.pids, dev(x), dev(q2)).cpu().numpy()
+    ora, scale = oracle.xfxq2(ogrid(g), g.pids, x, q2, with_scale=True)
+    assert np.array_equal(np.isfinite(out), np.isfinite(ora))
+    sel = np.isfinite(ora) & (np.abs(ora) < 1e250) & np.isfinite(scale) & (scale < 1e250)
+    ok = check_f64(out, ora, scale, grid_L(g))[0] | ~sel
+    assert ok.all(), describe_failures(ok, out, ora, x, q2, g.pids)
+    # FP32 arithmetic: compared where the value and its scale stay well inside the FP32 range
+    out32 = pdfmi.xfxq2_f32(m, g.pids, dev(x), dev(q2)).cpu().numpy()
+    sel32 = sel & (np.abs(ora) < 1e30) & (scale < 1e30)
+    ok32 = check_f32(out32, ora, scale)[0] | ~sel32
+    assert ok32.all(), describe_failures(ok32, out32, ora, x, q2, g.pids)
+    print("extreme inputs: %d of %d values compared (FP32: %d)" % (sel.sum(), sel.size, sel32.sum()))
