@@ -234,7 +234,7 @@ int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, int32_t out_f64, p
 
 /*
  * MLP surrogate of one member's PDFs (an alternative evaluator grown on top
- * of the interpolator; the interpolator stays the judge of its error).
+ * of the interpolator; the interpolator remains the reference for its error).
  * Network (ln x, ln Q^2) normalised to [-1,1]^2 -> 64 -> 64 -> 64 -> 16,
  * tanh hidden activations; BF16 weights and activations on the matrix cores
  * with FP32 accumulation; FP32 master weights trained with Adam.  Output c is
