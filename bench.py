@@ -376,6 +376,11 @@ def main():
             for kind in ("f64_fused", "f32_fused"):   # 24 B of (x1, x2, Q^2) per point in, one sum per chunk out
                 mc[kind]["achieved_GBs"] = 24.0 * mc["points"] / (mc[kind]["ms"] * 1e-3) / 1e9
                 mc[kind]["frac_hbm"] = mc[kind]["achieved_GBs"] / HBM_PEAK_GBS
+                # the bound that matters: stencil gathers from the LDS-staged grid, 2 x 16 values per
+                # stored flavour per point, against 128 B/clk/CU x 256 CUs x 2.4 GHz
+                lds_b = 2 * 16 * len(g1.pids) * (8 if kind == "f64_fused" else 4) * mc["points"]
+                mc[kind]["lds_TBs"] = lds_b / (mc[kind]["ms"] * 1e-3) / 1e12
+                mc[kind]["frac_lds_peak"] = mc[kind]["lds_TBs"] / (128 * 256 * 2.4e9 / 1e12)
             mc["fused_bit_identical"] = {
                 "f64": bool(torch.equal(sums["f64"].view(torch.int64), sums["f64_fused"].view(torch.int64))),
                 "f32": bool(torch.equal(sums["f32"].view(torch.int64), sums["f32_fused"].view(torch.int64)))}
