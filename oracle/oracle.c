@@ -31,9 +31,10 @@
  *     by x first; constants TAU_X, TAU_Q and X_HIGH below;
  *   - invalid queries (x <= 0, x > x_max, Q^2 <= 0, non-finite) give NaN.
  *
- * Parity of the extrapolation constants and of LHAPDF agreement is unpinned
- * against the paper (it prints neither); the test-suite pins every part
- * against closed forms, invariants and brute force instead.
+ * The extrapolation constants (TAU_X, TAU_Q, X_HIGH) and the agreement with
+ * LHAPDF are "parity unpinned" against the paper (it prints neither); the
+ * test-suite pins every part against closed forms, invariants and brute force
+ * instead.
  *
  * Arithmetic: FP64 throughout, libm log/exp/pow, built with
  * -O2 -ffp-contract=off and no fast-math.
