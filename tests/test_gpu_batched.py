@@ -132,3 +132,82 @@ def test_one_shot_and_errors(members):
         pdfmi.BatchPlan(bad)
     assert e.value.code == pdfmi.PDF_ERR_MEMBER
     pdfmi.xfxq2_batched([])
+
+
+@pytest.mark.parametrize("out_f64", [False, True])
+def test_mixed_grid_shapes_read_global(members, out_f64):
+    """A plan holding a three-sub-grid 13-flavour member next to the small
+    ones: the largest grid does not fit LDS, so every tile reads its grid from
+    global memory; outputs bit-identical to the per-request calls and within
+    tolerance of the oracle."""
+    grids, ids = members
+    g2 = synth.config2_grid()
+    m2 = pdfmi.load_synth(g2)
+    try:
+        rng = np.random.default_rng(9)
+        reqs, host = [], []
+        for i, n in enumerate((5000, 64, 1, 3000)):
+            if i % 2 == 0:
+                x, q2 = synth.config2_queries(n=n, seed=400 + i, out_fraction=0.05)
+                m, g, pids = m2, g2, [int(p) for p in rng.permutation(g2.pids)[:7]]
+            else:
+                x, q2 = synth.config1_queries(n=n, seed=400 + i)
+                m, g, pids = ids[i % len(ids)], grids[i % len(ids)], None
+            P = len(g.pids) if pids is None else len(pids)
+            out = torch.full((n, P), -7.0, dtype=torch.float64 if out_f64 else torch.float32, device=DEV)
+            reqs.append((m, pids, dev(x), dev(q2), out))
+            host.append((g, pids, x, q2))
+        plan = pdfmi.BatchPlan(reqs, out_f64=out_f64)
+        try:
+            plan.configure(tile_points=1024, vector_cols=1)
+            plan.run()
+            torch.cuda.synchronize()
+            for (m, pids, x, q2, out), (g, p2, xh, qh) in zip(reqs, host):
+                fn = pdfmi.xfxq2 if out_f64 else pdfmi.xfxq2_f32
+                ref = fn(m, pids, x, q2, n_cols=len(g.pids))
+                assert torch.equal(torch.nan_to_num(out, nan=123.0), torch.nan_to_num(ref, nan=123.0))
+                req = g.pids if p2 is None else p2
+                ora, sc = oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, g.values, g.pids), req, xh, qh,
+                                       with_scale=True)
+                o = out.cpu().numpy()
+                ok = check_f64(o, ora, sc, grid_L(g))[0] if out_f64 else check_f32(o, ora, sc)[0]
+                assert ok.all()
+        finally:
+            plan.destroy()
+    finally:
+        pdfmi.unload(m2)
+
+
+def test_full_size_workload_as_benchmarked():
+    """The 101-member, 200-request workload in the benchmark's launch
+    configuration (autotuned tiles, graph replay): every request bit-identical
+    to its per-request FP32 call; a sample of each eighth request against the
+    oracle."""
+    grids = synth.config3_members()
+    ids = [pdfmi.load_synth(g) for g in grids]
+    try:
+        reqs_h = synth.config3_requests()
+        reqs = []
+        for r in reqs_h:
+            out = torch.empty((len(r["x"]), len(r["pids"])), dtype=torch.float32, device=DEV)
+            reqs.append((ids[r["member"]], r["pids"], dev(r["x"]), dev(r["q2"]), out))
+        plan = pdfmi.BatchPlan(reqs)
+        try:
+            tile, vec = plan.autotune(reps=1)
+            plan.configure(tile_points=tile, vector_cols=vec, use_graph=1)
+            plan.run()
+            torch.cuda.synchronize()
+            for i, ((m, pids, x, q2, out), r) in enumerate(zip(reqs, reqs_h)):
+                ref = pdfmi.xfxq2_f32(m, pids, x, q2)
+                assert torch.equal(torch.nan_to_num(out, nan=1.0), torch.nan_to_num(ref, nan=1.0)), i
+                if i % 8 == 0:
+                    g = grids[r["member"]]
+                    k = min(500, len(r["x"]))
+                    ora, sc = oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, g.values, g.pids), r["pids"],
+                                           r["x"][:k], r["q2"][:k], with_scale=True)
+                    assert check_f32(out[:k].cpu().numpy(), ora, sc)[0].all(), i
+        finally:
+            plan.destroy()
+    finally:
+        for m in ids:
+            pdfmi.unload(m)
