@@ -211,3 +211,32 @@ def test_trained_surrogate_gain(cfg1):
         assert np.median(e_tr) < 5e-2
     finally:
         s.destroy()
+
+
+def test_full_size_inference_sampled(cfg1):
+    """1e7 points (the benchmarked inference size): sampled network outputs
+    against the oracle forward pass, and every fallback point of the sample
+    equal to the FP32 interpolator."""
+    g, m = cfg1
+    s = pdfmi.Surrogate(m, seed=12)
+    try:
+        rng = np.random.default_rng(4)
+        p = rng.normal(0, 0.3, mlp.NPARAMS).astype(np.float32)
+        s.set_params(p)
+        x, q2 = synth.config1_queries(n=10_000_000, seed=41)
+        xd, qd = dev(x), dev(q2)
+        out = s.xfxq2(xd, qd, len(g.pids))
+        idx = np.concatenate([rng.choice(len(x), 20000, replace=False), [0, len(x) - 1]])
+        idx_t = torch.from_numpy(idx).to(DEV)
+        o = out[idx_t].cpu().numpy().astype(np.float64)
+        ref = pdfmi.xfxq2_f32(m, g.pids, xd[idx_t].contiguous(), qd[idx_t].contiguous()).cpu().numpy()
+        xs, qs = x[idx], q2[idx]
+        tm = trusted_mask(g, xs, qs)
+        assert np.array_equal(o[~tm], ref[~tm].astype(np.float64))
+        y = mlp.forward_bf16(p.astype(np.float64), normalise(g, xs, qs).astype(np.float64))[:, :len(g.pids)]
+        E = envelope(g, xs)
+        ratio = (np.abs(o - y * E) / ((np.abs(y) + 0.05) * E))[tm]
+        assert np.mean(ratio <= 2e-2) >= 0.995, np.mean(ratio <= 2e-2)
+        assert np.all(ratio <= 1e-1), ratio.max()
+    finally:
+        s.destroy()
