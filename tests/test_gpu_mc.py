@@ -179,3 +179,35 @@ def test_chunk_sum_any_width(P, f32):
     ref = math.fsum(terms)
     scale = math.fsum(np.abs(w) * np.sum(np.abs(a.astype(np.float64) * b.astype(np.float64)), axis=1))
     assert abs(s1 - ref) <= 1e-12 * scale
+
+
+def test_full_workload_fused_equals_unfused():
+    """The benchmarked load: 100 chunks of 1e6 points (1e8 points), every
+    chunk sum of the fused kernel bit-identical to the unfused calls (FP64),
+    and the total within the summation bound of the oracle on three chunks."""
+    g = synth.config1_grid()
+    qk, a = synth.config1_alphas()
+    m = pdfmi.load_synth(g)
+    pdfmi.load_alphas(qk, a)
+    try:
+        n = 1_000_000
+        ws = pdfmi.mc_workspace(n, DEV)
+        f1 = torch.empty((n, len(PIDS)), dtype=torch.float64, device=DEV)
+        f2 = torch.empty_like(f1)
+        al = torch.empty(n, dtype=torch.float64, device=DEV)
+        unf = torch.empty(100, dtype=torch.float64, device=DEV)
+        fus = torch.empty(100, dtype=torch.float64, device=DEV)
+        for c in range(100):
+            x1, x2, q2 = (dev(v) for v in synth.config5_chunk(c))
+            pdfmi.xfxq2(m, PIDS, x1, q2, out=f1)
+            pdfmi.xfxq2(m, PIDS, x2, q2, out=f2)
+            pdfmi.alphas_q2(q2, out=al)
+            pdfmi.mc_chunk_sum(f1, f2, al, workspace=ws, out=unf[c:c + 1])
+            pdfmi.mc_fused(m, PIDS, x1, x2, q2, workspace=ws, out=fus[c:c + 1])
+        assert torch.equal(unf.view(torch.int64), fus.view(torch.int64))
+        got = fus.cpu().numpy()
+        for c in (0, 57, 99):
+            s, absum = oracle_chunk(g, qk, a, *synth.config5_chunk(c))
+            assert abs(got[c] - s) <= 1e-11 * absum, c
+    finally:
+        pdfmi.unload(m)
