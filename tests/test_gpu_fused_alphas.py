@@ -154,3 +154,33 @@ def test_fused_arguments(grids):
     rc = pdfmi.library().pdf_xfxq2_alphas(int(m), None, 0, xd.data_ptr(), xd.data_ptr(), 1, o.data_ptr(), None,
                                           None)
     assert rc == pdfmi.PDF_ERR_ARG
+
+
+def test_fused_call_in_a_captured_graph(grids):
+    """The fused call recorded into a HIP graph (torch.cuda.graph) and replayed
+    with eager work between the replays: every replay equals the eager call."""
+    gs, ms = grids
+    g, m = gs["cfg2"], ms["cfg2"]
+    pdfmi.load_alphas(*synth.config2_alphas())
+    x, q2 = synth.config2_queries(n=300_000, seed=950, out_fraction=0.05)
+    xd, qd = dev(x), dev(q2)
+    want_o, want_a = pdfmi.xfxq2_alphas(m, g.pids, xd, qd)
+    o = torch.empty_like(want_o)
+    a = torch.empty_like(want_a)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pdfmi.xfxq2_alphas(m, g.pids, xd, qd, out=o, alphas_out=a)   # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        pdfmi.xfxq2_alphas(m, g.pids, xd, qd, out=o, alphas_out=a)
+    for rep in range(4):
+        o.fill_(float(rep))
+        a.fill_(float(rep))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(torch.nan_to_num(o, nan=7.0), torch.nan_to_num(want_o, nan=7.0)), rep
+        assert torch.equal(torch.nan_to_num(a, nan=7.0), torch.nan_to_num(want_a, nan=7.0)), rep
