@@ -12,6 +12,9 @@ the timed region.  `value` counts PDF evaluations (points x flavours).
              (pdf_xfxq2_alphas_f32)
   separate   the headline step as two launches (pdf_xfxq2, pdf_alphas_q2)
   small      the 1e5-point one-sub-grid workload (latency-bound), FP64
+  points     evaluations per second against the number of points (1e3..1e7,
+             headline grid, all flavours + alpha_s, FP64 and FP32), the
+             shape of the paper's throughput-versus-points measurement
   batched    101 members, 200 requests (log-normal sizes, random flavour
              subsets), one persistent hipGraph-replayed launch with autotuned
              tiles, FP32 arithmetic; speed-up over per-request FP64 calls
@@ -220,6 +223,21 @@ def main():
                 r = (np.abs(o - ora) / np.abs(ora))[ok]
                 return {"median_rel": float(np.median(r)), "p99_rel": float(np.percentile(r, 99)),
                         "max_rel": float(r.max()), "frac_le_1e-3": float((r <= 1e-3).mean())}
+
+            # ---------------------------------------------------------- throughput against n
+            log("throughput against the number of points")
+            sweep = []
+            for n_pts in (1_000, 10_000, 100_000, 1_000_000, 10_000_000):
+                xs_n, qs_n = xd[:n_pts], qd[:n_pts]
+                t64 = dtime(lambda: pdfmi.xfxq2_alphas(member, g.pids, xs_n, qs_n, out=out64[:n_pts],
+                                                       alphas_out=aout[:n_pts]), reps=20)
+                o32 = torch.empty((n_pts, P), dtype=torch.float32, device=dev)
+                t32 = dtime(lambda: pdfmi.xfxq2_alphas(member, g.pids, xs_n, qs_n, out=o32, alphas_out=aout[:n_pts],
+                                                       f32=True), reps=20)
+                sweep.append({"n_points": n_pts, "f64_ms": t64, "f64_evals_per_s": n_pts * P / (t64 * 1e-3),
+                              "f32_ms": t32, "f32_evals_per_s": n_pts * P / (t32 * 1e-3)})
+                del o32
+            V["points"] = sweep
 
             # ---------------------------------------------------------- small (1e5)
             log("small workload")
