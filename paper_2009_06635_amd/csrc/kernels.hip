@@ -468,7 +468,7 @@ static hipError_t launch_one(const MemberDev& m, const ReqCols& rc, const double
                              T* out, unsigned long long* nerr, int lds_grid_elems, double invL01, int64_t nb,
                              size_t shm, const AsOut& ao, hipStream_t s) {
   const void* fn = reinterpret_cast<const void*>(&k_xfxq2<T, kLdsGrid, G, BS, kLdsTables, kAlphas>);
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipError_t e = allow_dynamic_lds(fn, shm);
   if (e != hipSuccess) return e;
   const AlphasDev A = ao.A ? *ao.A : AlphasDev{};
   hipLaunchKernelGGL((k_xfxq2<T, kLdsGrid, G, BS, kLdsTables, kAlphas>), dim3((unsigned)nb), dim3(BS), shm, s, m, rc, x, q2,
@@ -651,8 +651,7 @@ hipError_t launch_mc_sum(const T* xf1, const T* xf2, int P, const double* as, in
   if (np > 0) {
     const size_t shm = (size_t)2 * kMcThreads * P * sizeof(T);
     if (shm <= 96 * 1024) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mc_partial<T>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_mc_partial<T>), shm);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k_mc_partial<T>, dim3((unsigned)np), dim3(kMcThreads), shm, s, xf1, xf2, P, as, n, partial);
     } else {
@@ -848,7 +847,7 @@ hipError_t launch_mc_fused(const MemberDev& m, const ReqCols& rc, const AlphasDe
     const size_t shm = lds ? lds_all : mc_fused_shared_bytes(m, A, 0, f32);
     const void* fn = lds ? reinterpret_cast<const void*>(&k_mc_fused<T, true>)
                          : reinterpret_cast<const void*>(&k_mc_fused<T, false>);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipError_t e = allow_dynamic_lds(fn, shm);
     if (e != hipSuccess) return e;
     const int per_cu = max(1, (int)(160 * 1024 / shm));
     const int64_t nb = min((np + 3) / 4, (int64_t)n_cu * per_cu);
@@ -985,7 +984,7 @@ BatchLaunch batch_launch_params(bool f32, bool lds, int max_tbl, int64_t max_ele
 }
 
 hipError_t batch_prepare(const BatchLaunch& L) {
-  return hipFuncSetAttribute(L.main_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.shm);
+  return allow_dynamic_lds(L.main_fn, L.shm);
 }
 
 hipError_t batch_launch(const BatchLaunch& L, void** args, unsigned* counter, hipStream_t s) {

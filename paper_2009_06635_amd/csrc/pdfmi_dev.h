@@ -3,6 +3,12 @@
 #pragma once
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include <hip/hip_runtime.h>
+
 namespace pdfmi {
 
 constexpr int kMaxSub = 16;      // Q^2 sub-grids per member
@@ -167,5 +173,23 @@ struct SurBufs {
   float* partial;           // [256]
   float* wpart;             // split-reduction partial sums, 64 slices x 64 x 64
 };
+
+// hipFuncSetAttribute(MaxDynamicSharedMemorySize) only when a launch needs
+// more dynamic LDS than the kernel was last allowed on this device: repeated
+// launches of the same shape make no extra runtime call (it costs several
+// microseconds, the whole duration of a small evaluation).
+inline hipError_t allow_dynamic_lds(const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, size_t> allowed;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& a = allowed[{fn, dev}];
+  if (bytes <= a) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) a = bytes;
+  return e;
+}
 
 }  // namespace pdfmi

@@ -582,8 +582,7 @@ hipError_t sur_infer(const SurDev& S, const MemberDev& m, const SurBufs& b, cons
   const int64_t blocks = min((tiles + kSurWaves - 1) / kSurWaves, (int64_t)n_cu * 8);
   if (blocks > 0) {
     const size_t shm = sur_infer_shared_bytes(S.nx);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sur_infer),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_sur_infer), shm);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sur_infer, dim3((unsigned)blocks), dim3(64 * kSurWaves), shm, s, S, m, b.Pb, b.P, x, q2, n,
                        out, invL01, nerr);
