@@ -140,6 +140,7 @@ __global__ void k_col_sum(const float* __restrict__ X, int B, int ncols, int kch
   if (c >= ncols) return;
   const int b0 = blockIdx.y * kchunk, b1 = min(B, b0 + kchunk);
   float s = 0.0f;
+#pragma unroll 16
   for (int b = b0; b < b1; ++b) s += X[(int64_t)b * ncols + c];
   out[(int64_t)blockIdx.y * ncols + c] = s;
 }
@@ -153,6 +154,7 @@ __global__ void k_dw1(const unsigned short* __restrict__ dZb, const float* __res
   const int j = o / 2, t = o % 2;
   const int b0 = blockIdx.y * kchunk, b1 = min(B, b0 + kchunk);
   float s = 0.0f;
+#pragma unroll 16
   for (int b = b0; b < b1; ++b) s = fmaf(bf16_float(dZb[(int64_t)b * kH + j]), bf16_float(bf16_bits(in[2 * b + t])), s);
   dW1[(int64_t)blockIdx.y * kH * 2 + o] = s;
 }
@@ -484,26 +486,41 @@ static void gemm(const unsigned short* A, int sam, int sak, const unsigned short
                      act, K);
 }
 
+// Sum of 256 per-thread values of a 256-thread block by a fixed pairwise tree
+// (the same order on every call); the result is valid in thread 0.
+__device__ float block_tree_sum(float v, float* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// 256 blocks of 256 threads: block j sums its contiguous share of x, its
+// threads striding through it (coalesced), into partial[j].
 __global__ void k_sum_partial(const float* __restrict__ x, int64_t n, float* __restrict__ partial) {
-  // 256 threads, each sums a contiguous chunk in order
+  __shared__ float red[256];
   const int64_t per = (n + 255) / 256;
-  const int64_t b = threadIdx.x * per, e = min(b + per, n);
+  const int64_t b = blockIdx.x * per, e = min(b + per, n);
   float s = 0.0f;
-  for (int64_t i = b; i < e; ++i) s += x[i];
-  partial[threadIdx.x] = s;
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) s += x[i];
+  s = block_tree_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 __global__ void k_sum_final(const float* __restrict__ partial, float scale, float* __restrict__ out) {
-  if (threadIdx.x == 0) {
-    float s = 0.0f;
-    for (int i = 0; i < 256; ++i) s += partial[i];
-    *out = s * scale;
-  }
+  __shared__ float red[256];
+  const float s = block_tree_sum(partial[threadIdx.x], red);
+  if (threadIdx.x == 0) *out = s * scale;
 }
 
 // Column sums and the first-layer weight gradient over the batch, in row
-// slices added in order (the same slicing as the weight-gradient GEMMs).
+// slices of at least kColRows rows added in order (a thread per column and
+// slice: short slices give the few columns enough waves to hide latency).
+constexpr int kColRows = 64;
 static void col_sum(const float* X, int B, int ncols, float* out, float* ws, hipStream_t s) {
-  const int S = min(kMaxSlices, (B + kSplitK - 1) / kSplitK);
+  const int S = min(kMaxSlices, (B + kColRows - 1) / kColRows);
   const int kchunk = (B + S - 1) / S;
   hipLaunchKernelGGL(k_col_sum, dim3((unsigned)((ncols + 63) / 64), (unsigned)S), dim3(64), 0, s, X, B, ncols, kchunk,
                      ws);
@@ -511,7 +528,7 @@ static void col_sum(const float* X, int B, int ncols, float* out, float* ws, hip
 }
 
 static void dw1(const unsigned short* dZb, const float* in, int B, float* out, float* ws, hipStream_t s) {
-  const int S = min(kMaxSlices, (B + kSplitK - 1) / kSplitK);
+  const int S = min(kMaxSlices, (B + kColRows - 1) / kColRows);
   const int kchunk = (B + S - 1) / S;
   hipLaunchKernelGGL(k_dw1, dim3(1, (unsigned)S), dim3(128), 0, s, dZb, in, B, kchunk, ws);
   hipLaunchKernelGGL(k_sum_slices, dim3(1), dim3(256), 0, s, ws, S, kH * 2, out);
@@ -529,8 +546,8 @@ hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* 
   gemm(b.h2b, kH, 1, W3, 1, kH, b.h3, kH, b.h3b, B, kH, kH, b.P + kOffB3, 1, b.wpart, s);
   gemm(b.h3b, kH, 1, W4, 1, kH, b.y, kO, nullptr, B, kO, kH, b.P + kOffB4, 0, b.wpart, s);
   hipLaunchKernelGGL(k_loss_grad, dim3(nb((int64_t)B * kO, 256)), dim3(256), 0, s, b.y, T, B, b.dy, b.dyb, b.sq);
-  hipLaunchKernelGGL(k_sum_partial, dim3(1), dim3(256), 0, s, b.sq, (int64_t)B * kO, b.partial);
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, s, b.partial, 1.0f / (float)((int64_t)B * kO), b.loss);
+  hipLaunchKernelGGL(k_sum_partial, dim3(256), dim3(256), 0, s, b.sq, (int64_t)B * kO, b.partial);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, b.partial, 1.0f / (float)((int64_t)B * kO), b.loss);
   // layer 4: dW4[o][i] = sum_b dy[b][o] h3[b][i]; db4; dh3 = dy W4
   gemm(b.dyb, 1, kO, b.h3b, kH, 1, b.G + kOffW4, kH, nullptr, kO, kH, B, nullptr, 0, b.wpart, s);
   col_sum(b.dy, B, kO, b.G + kOffB4, b.wpart, s);
