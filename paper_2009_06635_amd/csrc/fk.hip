@@ -9,10 +9,13 @@
 // Tiling: a workgroup of 8 waves computes a 64 x 128 tile of T (64 members x
 // 128 table rows); each wave a 32 x 32 part as 2 x 2 MFMA tiles of 16 x 16
 // (two workgroups per compute unit: 4 waves per SIMD).
-// K is walked in steps of 32 staged in LDS as rows of 36 doubles (the 16 rows
-// x 4 k read by one MFMA operand then fall on distinct bank pairs), with the
+// K is walked in steps of 32 staged in LDS as rows of 33 doubles, with the
 // next step's global loads (32 consecutive k per half-wave: 256-byte
-// segments) issued before the current step's MFMAs.  Out-of-range rows and k
+// segments) issued before the current step's MFMAs.  An operand read (lane =
+// row r + 16 k-column q) is served 16 lanes (128 bytes) at a time; with a row
+// stride of 33 doubles the 16 rows of one q land on 16 distinct 8-byte bank
+// slots (a stride of 36 put rows r and r + 8 on the same slot and cost ~45 %
+// of the kernel's cycles in bank conflicts).  Out-of-range rows and k
 // read as zero.  K is split into S slices (chosen from the sizes and the
 // number of compute units only) whose partial sums are added in slice order,
 // so the summation order is fixed (deterministic results).
@@ -25,7 +28,7 @@ namespace pdfmi {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kFkBM = 64, kFkBN = 128, kFkBK = 32, kFkLd = kFkBK + 4, kFkThreads = 512;
+constexpr int kFkBM = 64, kFkBN = 128, kFkBK = 32, kFkLd = kFkBK + 1, kFkThreads = 512;
 constexpr int kFkRowsA = kFkBM * kFkBK / kFkThreads, kFkRowsB = kFkBN * kFkBK / kFkThreads;  // loads per thread
 
 // One (64 x 128 tile, K slice) per workgroup: the slice [blockIdx.z * kslice,
