@@ -32,6 +32,7 @@ The dominant kernel's roofline uses its algorithmic bytes (16 B of (x, Q^2) in
 with HIP events on the launch stream.  cpu_baseline times the FP64 oracle on the host cores.
 """
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -114,11 +115,16 @@ def main():
             fn(None)
         evs = [(ev(), ev()) for _ in range(steps)]
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for e in evs:
-            fn(e)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) / steps
+        gc.collect()
+        gc.disable()  # a collection inside the timed region stalls the launches for tens of ms
+        try:
+            t0 = time.perf_counter()
+            for e in evs:
+                fn(e)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / steps
+        finally:
+            gc.enable()
         kern = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
         return wall, kern
 
@@ -126,11 +132,16 @@ def main():
         fn()
         torch.cuda.synchronize()
         e0, e1 = ev(), ev()
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
+        gc.collect()
+        gc.disable()
+        try:
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+        finally:
+            gc.enable()
         return e0.elapsed_time(e1) / reps
 
     # ---------------------------------------------------------------- headline

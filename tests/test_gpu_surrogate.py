@@ -57,7 +57,7 @@ def trusted_mask(g, x, q2):
     return (x >= xk[1]) & (x < xk[-2]) & (q2 >= qk[1]) & (q2 < qk[-2])
 
 
-@pytest.mark.parametrize("B", [16, 48, 256])
+@pytest.mark.parametrize("B", [16, 48, 256, 4096])
 def test_gradients_match_oracle(cfg1, B):
     g, m = cfg1
     s = pdfmi.Surrogate(m, seed=7)
