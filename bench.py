@@ -111,13 +111,16 @@ def main():
 
     def timed(fn, steps, warmup):
         """(wall seconds per step, mean kernel ms between fn's own events)."""
-        for _ in range(warmup):
-            fn(None)
-        evs = [(ev(), ev()) for _ in range(steps)]
-        torch.cuda.synchronize()
+        # The garbage collector is paused over warm-up and timed steps: a collection
+        # inside the timed region stalls the launches for tens of ms, and one between
+        # warm-up and timing idles the GPU long enough for its clocks to drop.
         gc.collect()
-        gc.disable()  # a collection inside the timed region stalls the launches for tens of ms
+        gc.disable()
         try:
+            evs = [(ev(), ev()) for _ in range(steps)]
+            for _ in range(warmup):
+                fn(None)
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
             for e in evs:
                 fn(e)
@@ -129,12 +132,13 @@ def main():
         return wall, kern
 
     def dtime(fn, reps=5):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = ev(), ev()
-        gc.collect()
+        # no collection here: the single warm-up call cannot bring the clocks back up
+        # after the GPU idles through one
         gc.disable()
         try:
+            e0, e1 = ev(), ev()
+            fn()
+            torch.cuda.synchronize()
             e0.record()
             for _ in range(reps):
                 fn()
