@@ -155,6 +155,26 @@ def test_lds_staged_grid_matches_global(cfg1):
     assert check_f32(outs[2][1], ora, scale)[0].all()
 
 
+def test_tables_in_place_below_threshold_match_staged(cfg2):
+    """Calls under 32 768 points read the location tables in place, larger ones
+    stage them in LDS per workgroup: the same points give bit-identical values."""
+    g, m = cfg2
+    n = 32_768
+    x, q2 = synth.config2_queries(n=n, seed=13, out_fraction=0.05)
+    xd, qd = dev(x), dev(q2)
+    pdfmi.load_alphas(*synth.config2_alphas())
+    big, a_big = pdfmi.xfxq2_alphas(m, g.pids, xd, qd)
+    small, a_small = pdfmi.xfxq2_alphas(m, g.pids, xd[:n - 1], qd[:n - 1])
+    assert torch.equal(big[:n - 1], small)
+    assert torch.equal(a_big[:n - 1], a_small)
+    assert torch.equal(pdfmi.xfxq2(m, g.pids, xd[:n - 1], qd[:n - 1]), small)
+    sub = g.pids[::2]
+    big32 = pdfmi.xfxq2_f32(m, sub, xd, qd)
+    assert torch.equal(big32[:n - 1], pdfmi.xfxq2_f32(m, sub, xd[:n - 1], qd[:n - 1]))
+    ora, scale = oracle.xfxq2(ogrid(g), g.pids, x[:4096], q2[:4096], with_scale=True)
+    assert check_f64(small[:4096].cpu().numpy(), ora, scale, grid_L(g))[0].all()
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_tiny_grids_all_regions(seed):
     rng = np.random.default_rng(500 + seed)
