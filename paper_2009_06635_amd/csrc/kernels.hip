@@ -65,22 +65,29 @@ __device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t r, int voff, int
   }
 }
 
-template <typename T, int G>
+// Cache policy of the output stores: 0 (default) or kStoreStream, the
+// non-temporal hint.  While the grid is gathered through L2, the streamed
+// output rows then displace fewer grid lines (measured 5-9 % faster for 1e7
+// points); with the grid staged in LDS the hint made the same call slower
+// (0.31 -> 0.55 ms in FP32), so those kernels keep the default.
+constexpr int kStoreStream = 2;
+
+template <typename T, int G, int kPolicy = 0>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int voff, const T* src) {
   constexpr int kBytes = G * (int)sizeof(T);
   if constexpr (kBytes == 16) {
     unsigned int u[4];
     __builtin_memcpy(u, src, 16);
-    __builtin_amdgcn_raw_buffer_store_b128(u32x4{u[0], u[1], u[2], u[3]}, r, voff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{u[0], u[1], u[2], u[3]}, r, voff, 0, kPolicy);
   } else if constexpr (kBytes == 8) {
     unsigned int u[2];
     __builtin_memcpy(u, src, 8);
-    __builtin_amdgcn_raw_buffer_store_b64(u32x2{u[0], u[1]}, r, voff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2{u[0], u[1]}, r, voff, 0, kPolicy);
   } else {
     static_assert(kBytes == 4, "unsupported store width");
     unsigned int u;
     __builtin_memcpy(&u, src, 4);
-    __builtin_amdgcn_raw_buffer_store_b32(u, r, voff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(u, r, voff, 0, kPolicy);
   }
 }
 
@@ -236,10 +243,11 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, 
       }
       const int ob = (p * R + c0) * (int)sizeof(T);
       if (kOverlap || G * j + G <= R) {
-        buf_store<T, G>(orr, ob, res);
+        buf_store<T, G, kLdsGrid ? 0 : kStoreStream>(orr, ob, res);
       } else {
         // last group of a point without overlap: only the columns below R
-        for (int i = 0; i < R - G * j; ++i) buf_store<T, 1>(orr, ob + i * (int)sizeof(T), res + i);
+        for (int i = 0; i < R - G * j; ++i)
+          buf_store<T, 1, kLdsGrid ? 0 : kStoreStream>(orr, ob + i * (int)sizeof(T), res + i);
       }
     }
     p += e_dp;
