@@ -380,6 +380,23 @@ int pdf_mc_fused_f32(int32_t member, const int32_t* pids, int32_t n_pids,
 int pdf_fk_contract(const double* pdf, const double* fk, int32_t nrep, int32_t ndat, int64_t K,
                     double* out, pdf_stream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code recorded into a HIP
+ * graph, serving loops, harnesses that forbid hipMalloc): pdf_fk_contract
+ * with the partial sums of its K slices kept in a fixed 64 MiB device array
+ * that the library holds on each GPU it runs on until the process ends,
+ * instead of a workspace it allocates.  Same arguments, kernels and results
+ * (bit-identical to pdf_fk_contract); no allocation, no free and no
+ * synchronisation.  PDF_ERR_ARG when the partial sums (S slices x nrep x ndat
+ * doubles, S chosen from the sizes and the number of compute units, at most
+ * 64; S = 1 needs none) exceed 64 MiB: nothing is queued then.  Every call on
+ * a GPU shares that array and leaves its partial sums there: calls that
+ * overlap on one GPU (different streams or threads) race and must not be
+ * issued.  Asynchronous on stream.
+ */
+int pdf_fk_contract_noalloc(const double* pdf, const double* fk, int32_t nrep, int32_t ndat, int64_t K,
+                            double* out, pdf_stream_t stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* pdf_last_error(void);
 

@@ -122,6 +122,34 @@ int fk_slices(int nrep, int ndat, int64_t K, int n_cu) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(S, 64));
 }
 
+// Partial sums of the K slices for callers that cannot allocate
+// (pdf_fk_contract_noalloc): a fixed array in device memory, one per GPU the
+// library runs on, held until the process ends.  Host code never passes the
+// array's name to a kernel: fk_scratch_setup looks up its device address once
+// per device and the launches take that pointer.
+constexpr size_t kFkScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) double scratch[kFkScratchBytes / sizeof(double)];
+
+constexpr int kFkMaxDevices = 64;
+static double* g_scratch_ptr[kFkMaxDevices] = {};
+
+size_t fk_scratch_bytes() { return kFkScratchBytes; }
+
+// Device address of the scratch array on `device`, which must be the current
+// device; looked up on the first call for that device.
+hipError_t fk_scratch_setup(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kFkMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
 // ws: S * nrep * ndat doubles when S > 1 (unused otherwise).
 hipError_t launch_fk_contract(const double* F, const double* FK, int nrep, int ndat, int64_t K, double* T, int S,
                               double* ws, hipStream_t s) {

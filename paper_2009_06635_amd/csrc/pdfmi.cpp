@@ -55,6 +55,8 @@ size_t mc_fused_shared_bytes(const MemberDev& m, const AlphasDev& A, int64_t gri
 hipError_t launch_fk_contract(const double* F, const double* FK, int nrep, int ndat, int64_t K, double* T, int S,
                               double* ws, hipStream_t s);
 int fk_slices(int nrep, int ndat, int64_t K, int n_cu);
+size_t fk_scratch_bytes();
+hipError_t fk_scratch_setup(int device, double** out);
 }  // namespace pdfmi
 
 using namespace pdfmi;
@@ -109,16 +111,30 @@ int g_vector_cols = 1; // serve all-column requests with G-wide vector gathers
 int g_blocks_per_cu = 32;
 void* g_fk_ws = nullptr;      // partial sums of the K slices of pdf_fk_contract (grow-only)
 size_t g_fk_ws_bytes = 0;
+double* g_fk_scratch = nullptr;  // device address of the fixed scratch of pdf_fk_contract_noalloc
 constexpr size_t kLdsBytes = 160 * 1024;
 
-int ensure_init() {
-  if (g_init) return PDF_OK;
+// The part of the set-up that allocates nothing: the device, its compute
+// units and the device address of the fixed FK scratch array.
+bool g_dev_ready = false;
+int ensure_device() {
+  if (g_dev_ready) return PDF_OK;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
   e = hipDeviceGetAttribute(&g_ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute");
-  e = hipMalloc(&g_nerr, sizeof(unsigned long long));
+  e = fk_scratch_setup(dev, &g_fk_scratch);
+  if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(fk scratch)");
+  g_dev_ready = true;
+  return PDF_OK;
+}
+
+int ensure_init() {
+  if (g_init) return PDF_OK;
+  int rc = ensure_device();
+  if (rc != PDF_OK) return rc;
+  hipError_t e = hipMalloc(&g_nerr, sizeof(unsigned long long));
   if (e != hipSuccess) return fail_hip(e, "hipMalloc(error counter)");
   e = hipMemset(g_nerr, 0, sizeof(unsigned long long));
   if (e != hipSuccess) return fail_hip(e, "hipMemset(error counter)");
@@ -1482,6 +1498,26 @@ extern "C" int pdf_fk_contract(const double* pdf, const double* fk, int32_t nrep
   return PDF_OK;
 }
 
+extern "C" int pdf_fk_contract_noalloc(const double* pdf, const double* fk, int32_t nrep, int32_t ndat, int64_t K,
+                                       double* out, pdf_stream_t stream) {
+  if (nrep < 0 || ndat < 0 || K < 0) return fail(PDF_ERR_ARG, "negative size");
+  if (nrep > (1 << 22)) return fail(PDF_ERR_ARG, "nrep above 4194304");
+  if (nrep > 0 && ndat > 0 && (!out || (K > 0 && (!pdf || !fk)))) return fail(PDF_ERR_ARG, "null device pointer");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int rc = ensure_device();
+  if (rc != PDF_OK) return rc;
+  if (nrep == 0 || ndat == 0) return PDF_OK;
+  const int S = fk_slices(nrep, ndat, K, g_ncu);
+  const size_t need = S > 1 ? (size_t)S * nrep * ndat * sizeof(double) : 0;
+  if (need > fk_scratch_bytes())
+    return fail(PDF_ERR_ARG, "partial sums of %d K slices x %d x %d doubles need %zu bytes, above the %zu-byte scratch",
+                S, nrep, ndat, need, fk_scratch_bytes());
+  // every partial sum is written by the contraction kernel before the reduction reads it: nothing to clear
+  hipError_t e = launch_fk_contract(pdf, fk, nrep, ndat, K, out, S, g_fk_scratch, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "launch fk contraction");
+  return PDF_OK;
+}
+
 extern "C" int pdf_set_lds_policy(int32_t policy) {
   if (policy < 0 || policy > 2) return fail(PDF_ERR_ARG, "policy must be 0, 1 or 2");
   std::lock_guard<std::mutex> lock(g_mu);
@@ -1510,6 +1546,8 @@ extern "C" int pdf_shutdown(void) {
   if (g_fk_ws) (void)hipFree(g_fk_ws);
   g_fk_ws = nullptr;
   g_fk_ws_bytes = 0;
+  g_fk_scratch = nullptr;  // the array itself stays with the process
+  g_dev_ready = false;
   g_init = false;
   return PDF_OK;
 }

@@ -60,6 +60,7 @@ _SIGS = {
     "pdf_mc_fused": [_i32, _P, _i32, _P, _P, _P, _i64, _P, _P, _P],
     "pdf_mc_fused_f32": [_i32, _P, _i32, _P, _P, _P, _i64, _P, _P, _P],
     "pdf_fk_contract": [_P, _P, _i32, _i32, _i64, _P, _P],
+    "pdf_fk_contract_noalloc": [_P, _P, _i32, _i32, _i64, _P, _P],
     "pdf_lhapdf_read": [ctypes.c_char_p, _P, _P, _P, _P, _P],
     "pdf_load_lhapdf": [ctypes.c_char_p, _P],
     "pdf_lhapdf_read_alphas": [ctypes.c_char_p, _P, _P, _P],
@@ -332,10 +333,13 @@ def mc_fused(member, pids, x1, x2, q2, f32=False, workspace=None, out=None, stre
     return out
 
 
-def fk_contract(pdf, fk, out=None, stream=None):
+def fk_contract(pdf, fk, out=None, stream=None, noalloc=False):
     """out[r][d] = sum_k pdf[r][k] fk[d][k] (FP64 matrix cores); pdf [nrep][K]
     and fk [ndat][K] contiguous float64 CUDA tensors (2-D, or more dimensions
-    flattened after the first)."""
+    flattened after the first).  noalloc=True calls pdf_fk_contract_noalloc
+    (partial sums in the library's fixed scratch array; out must be given)."""
+    if noalloc and out is None:
+        raise ValueError("noalloc needs a caller-provided out tensor")
     for t, nm in ((pdf, "pdf"), (fk, "fk")):
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
             raise TypeError("%s must be a contiguous float64 CUDA tensor" % nm)
@@ -345,8 +349,8 @@ def fk_contract(pdf, fk, out=None, stream=None):
         raise ValueError("pdf and fk rows differ in length")
     if out is None:
         out = torch.empty((nrep, ndat), dtype=torch.float64, device=pdf.device)
-    _check(_lib.pdf_fk_contract(_P(pdf.data_ptr()), _P(fk.data_ptr()), nrep, ndat, K, _P(out.data_ptr()),
-                                _stream(stream)))
+    fn = _lib.pdf_fk_contract_noalloc if noalloc else _lib.pdf_fk_contract
+    _check(fn(_P(pdf.data_ptr()), _P(fk.data_ptr()), nrep, ndat, K, _P(out.data_ptr()), _stream(stream)))
     return out
 
 
