@@ -96,10 +96,12 @@ struct Member {
   std::vector<int> h_shape;       // host copy of the load arguments (surrogate envelopes)
   std::vector<double> h_knots, h_values;
   double invL01 = 0.0;
+  uint64_t gen = 0;        // load generation: a slot reused by a later load gets a new one
 };
 
 std::mutex g_mu;
 std::vector<Member> g_members;
+uint64_t g_load_gen = 0;
 bool g_init = false;
 int g_ncu = 0;
 unsigned long long* g_nerr = nullptr;
@@ -437,6 +439,7 @@ extern "C" int pdf_load_grid(int32_t K, const int32_t* shape, int32_t P, const i
   d.v64 = reinterpret_cast<const double*>(base + bt);
   d.v32 = reinterpret_cast<const float*>(base + bt + b64);
 
+  M.gen = ++g_load_gen;
   for (size_t i = 0; i < g_members.size(); ++i) {
     if (!g_members[i].used) {
       g_members[i] = M;
@@ -679,6 +682,7 @@ struct Plan {
   std::vector<BatchReq> reqs;
   std::vector<int> cols;
   std::vector<MemberDev> members;
+  std::vector<std::pair<int32_t, uint64_t>> member_ids;  // (member id, load generation) behind members
   std::vector<double> invL01;
   int ntiles = 0;
   void* dmem = nullptr;        // reqs, cols, members, invL01, counter
@@ -816,6 +820,17 @@ Plan* get_plan(int32_t id) {
   return &g_plans[id];
 }
 
+// A plan holds copies of its members' device pointers: every member must still
+// be the one loaded when the plan was built (not unloaded, slot not reused).
+int plan_members_live(const Plan& P) {
+  for (const auto& mg : P.member_ids) {
+    const Member* M = get_member(mg.first);
+    if (!M || M->gen != mg.second)
+      return fail(PDF_ERR_MEMBER, "member %d was unloaded after the plan was built", mg.first);
+  }
+  return PDF_OK;
+}
+
 std::map<std::string, std::pair<int, int>> g_tune_cache;
 
 }  // namespace
@@ -840,6 +855,7 @@ extern "C" int pdf_batch_create(const pdf_request* reqs, int32_t n_req, int32_t 
     if (!slot.count(q.member)) {
       slot[q.member] = (int)P.members.size();
       P.members.push_back(M->dev);
+      P.member_ids.push_back({q.member, M->gen});
       P.invL01.push_back(M->invL01);
       P.max_tbl = std::max(P.max_tbl, M->dev.tbl_bytes);
       P.max_elems = std::max(P.max_elems, P.out_f64 ? M->dev.elems64 : M->dev.elems32);
@@ -928,6 +944,8 @@ extern "C" int pdf_batch_run(int32_t plan, pdf_stream_t stream) {
   std::lock_guard<std::mutex> lock(g_mu);
   Plan* P = get_plan(plan);
   if (!P) return fail(PDF_ERR_ARG, "unknown plan %d", plan);
+  const int rc = plan_members_live(*P);
+  if (rc != PDF_OK) return rc;
   return plan_run(*P, (hipStream_t)stream);
 }
 
@@ -937,6 +955,7 @@ extern "C" int pdf_batch_autotune(int32_t plan, int32_t reps, pdf_stream_t strea
   std::lock_guard<std::mutex> lock(g_mu);
   Plan* P = get_plan(plan);
   if (!P) return fail(PDF_ERR_ARG, "unknown plan %d", plan);
+  if (plan_members_live(*P) != PDF_OK) return PDF_ERR_MEMBER;
   hipStream_t s = (hipStream_t)stream;
   // signature of the work: request count, point total, flavour total, precision
   int64_t pts = 0, evals = 0;
@@ -1033,6 +1052,7 @@ namespace {
 struct Surrogate {
   bool used = false;
   int member = -1;
+  uint64_t member_gen = 0;   // load generation of the member the surrogate was built on
   SurDev sd{};
   SurBufs b{};
   void* pmem = nullptr;      // parameters, moments, gradients, envelope tables
@@ -1050,6 +1070,12 @@ std::vector<Surrogate> g_surs;
 Surrogate* get_sur(int32_t id) {
   if (id < 0 || id >= (int32_t)g_surs.size() || !g_surs[id].used) return nullptr;
   return &g_surs[id];
+}
+
+// The surrogate's member, or null once it was unloaded (or its slot reused).
+Member* sur_member(const Surrogate& S) {
+  Member* M = get_member(S.member);
+  return M && M->gen == S.member_gen ? M : nullptr;
 }
 
 void sur_release(Surrogate& S) {
@@ -1170,6 +1196,7 @@ extern "C" int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_
   Surrogate S;
   S.used = true;
   S.member = member;
+  S.member_gen = M->gen;
   S.seed = seed;
   S.sd.P = P;
   S.sd.nx = nx0;
@@ -1245,27 +1272,38 @@ extern "C" int pdf_surrogate_set_data(int32_t sid, const double* x, const double
   std::lock_guard<std::mutex> lock(g_mu);
   Surrogate* S = get_sur(sid);
   if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
-  Member* M = get_member(S->member);
+  Member* M = sur_member(*S);
   if (!M) return fail(PDF_ERR_MEMBER, "surrogate's member %d was unloaded", S->member);
   hipStream_t s = (hipStream_t)stream;
   const int O = sur_out_width(), P = (int)M->pids.size();
+  // the old set is released first; until the new one is complete, training finds no data
   if (S->d_in) (void)hipFree(S->d_in);
   S->d_in = nullptr;
-  hipError_t e = hipMalloc(&S->d_in, (size_t)n * (2 + O) * 4);
+  S->d_t = nullptr;
+  S->n_train = 0;
+  float* din = nullptr;
+  hipError_t e = hipMalloc(&din, (size_t)n * (2 + O) * 4);
   if (e != hipSuccess) return fail_hip(e, "hipMalloc(training data)");
-  S->d_t = S->d_in + 2 * n;
   double* xf = nullptr;
-  if ((e = hipMalloc(&xf, (size_t)n * P * 8)) != hipSuccess) return fail_hip(e, "hipMalloc(targets)");
+  if ((e = hipMalloc(&xf, (size_t)n * P * 8)) != hipSuccess) {
+    (void)hipFree(din);
+    return fail_hip(e, "hipMalloc(targets)");
+  }
   ReqCols rc{};
   build_req(*M, nullptr, 0, rc);
   // targets from this library's FP64 interpolator
   const LaunchCfg cfg{g_ncu, g_blocks_per_cu, g_vector_cols};
   e = launch_xfxq2_f64(M->dev, rc, x, q2, n, xf, g_nerr, lds_grid_elems(*M, false, n), M->invL01, cfg, nullptr,
                        nullptr, s);
-  if (e == hipSuccess) e = sur_prep(S->sd, x, q2, xf, n, S->d_in, S->d_t, s);
+  if (e == hipSuccess) e = sur_prep(S->sd, x, q2, xf, n, din, din + 2 * n, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(xf);
-  if (e != hipSuccess) return fail_hip(e, "surrogate targets");
+  if (e != hipSuccess) {
+    (void)hipFree(din);
+    return fail_hip(e, "surrogate targets");
+  }
+  S->d_in = din;
+  S->d_t = din + 2 * n;
   S->n_train = n;
   return PDF_OK;
 }
@@ -1340,7 +1378,7 @@ extern "C" int pdf_surrogate_xfxq2(int32_t sid, const double* x, const double* q
   std::lock_guard<std::mutex> lock(g_mu);
   Surrogate* S = get_sur(sid);
   if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
-  Member* M = get_member(S->member);
+  Member* M = sur_member(*S);
   if (!M) return fail(PDF_ERR_MEMBER, "surrogate's member %d was unloaded", S->member);
   if (n == 0) return PDF_OK;
   hipError_t e = sur_infer(S->sd, M->dev, S->b, x, q2, n, out, M->invL01, g_nerr, g_ncu, (hipStream_t)stream);

@@ -211,3 +211,32 @@ def test_full_size_workload_as_benchmarked():
     finally:
         for m in ids:
             pdfmi.unload(m)
+
+
+def test_plan_refuses_unloaded_members():
+    """A plan copies its members' device pointers: after one of them is
+    unloaded (and its slot reused by a new load) running or tuning the plan
+    fails with PDF_ERR_MEMBER instead of reading freed memory."""
+    g = synth.config1_grid()
+    m = pdfmi.load_synth(g)
+    x, q2 = synth.config1_queries(n=500, seed=7)
+    out = torch.empty((500, len(g.pids)), dtype=torch.float32, device=DEV)
+    plan = pdfmi.BatchPlan([(m, None, dev(x), dev(q2), out)])
+    try:
+        plan.run()
+        torch.cuda.synchronize()
+        pdfmi.unload(m)
+        with pytest.raises(pdfmi.PdfError) as ei:
+            plan.run()
+        assert ei.value.code == pdfmi.PDF_ERR_MEMBER
+        m2 = pdfmi.load_synth(g)   # takes the freed slot: same id, new load
+        try:
+            assert m2 == m
+            for fn in (plan.run, lambda: plan.autotune(reps=1)):
+                with pytest.raises(pdfmi.PdfError) as ei:
+                    fn()
+                assert ei.value.code == pdfmi.PDF_ERR_MEMBER
+        finally:
+            pdfmi.unload(m2)
+    finally:
+        plan.destroy()

@@ -240,3 +240,29 @@ def test_full_size_inference_sampled(cfg1):
         assert np.all(ratio <= 1e-1), ratio.max()
     finally:
         s.destroy()
+
+
+def test_surrogate_refuses_unloaded_member():
+    """A surrogate reads its member's grid (fallback, training targets): once
+    the member is unloaded, even if a new load reuses its id, the calls fail
+    with PDF_ERR_MEMBER."""
+    g = synth.config1_grid()
+    m = pdfmi.load_synth(g)
+    s = pdfmi.Surrogate(m, seed=1)
+    try:
+        x, q2 = synth.config1_queries(n=256, seed=3)
+        xd, qd = dev(x), dev(q2)
+        s.xfxq2(xd, qd, len(g.pids))
+        torch.cuda.synchronize()
+        pdfmi.unload(m)
+        m2 = pdfmi.load_synth(g)
+        try:
+            assert m2 == m
+            for fn in (lambda: s.xfxq2(xd, qd, len(g.pids)), lambda: s.set_data(xd, qd)):
+                with pytest.raises(pdfmi.PdfError) as ei:
+                    fn()
+                assert ei.value.code == pdfmi.PDF_ERR_MEMBER
+        finally:
+            pdfmi.unload(m2)
+    finally:
+        s.destroy()
