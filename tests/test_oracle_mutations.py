@@ -64,10 +64,19 @@ MLP_MUTATIONS = {
     "mlp_loss_normalisation": ("dy = 2.0 * d / (B * O)", "dy = 2.0 * d / B"),
     "mlp_bias_gradient_mean": ('g["b4"] = dy.sum(0)', 'g["b4"] = dy.mean(0)'),
     "mlp_wrong_layer_input": ('g["W2"] = dzr.T @ a1', 'g["W2"] = dzr.T @ a2'),
-    "mlp_transposed_backprop": ('dh = dzr @ W["W3"]', 'dh = dzr @ W["W3"].T'),
+    "mlp_transposed_backprop": ('dh = dzr @ hi(W["W3"])', 'dh = dzr @ hi(W["W3"].T)'),
+    "split_drops_lo_activation": ("return ah @ Wh.T + al @ Wh.T + ah @ Wl.T", "return ah @ Wh.T + ah @ Wl.T"),
+    "split_lo_not_residual": ("return hi, bf16(a - hi)", "return hi, bf16(a)"),
     "mlp_first_layer_bias_missing": ('z1 = x @ W["W1"].T + P["b1"]', 'z1 = x @ W["W1"].T'),
     "bf16_ties_away_from_zero": ("r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16",
                                  "r = ((u + 0x8000) >> 16) << 16"),
+    "adam_no_bias_correction": ("m_hat = m / (1.0 - b1 ** t)", "m_hat = m"),
+    "adam_eps_inside_sqrt": ("lr * m_hat / (np.sqrt(v_hat) + eps)", "lr * m_hat / np.sqrt(v_hat + eps)"),
+    "adam_second_moment_of_abs": ("v = b2 * np.asarray(v, np.float64) + (1.0 - b2) * g * g",
+                                  "v = b2 * np.asarray(v, np.float64) + (1.0 - b2) * np.abs(g)"),
+    "cosine_schedule_reversed": ("(1.0 + math.cos(math.pi * frac))", "(1.0 - math.cos(math.pi * frac))"),
+    "train_schedule_off_by_one": ("cosine_lr(t, lr0, lr_final, total), t + 1)",
+                                  "cosine_lr(t + 1, lr0, lr_final, total), t + 1)"),
 }
 
 MUTATIONS = {k: ("oracle.c",) + v for k, v in C_MUTATIONS.items()}
