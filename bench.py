@@ -327,7 +327,7 @@ def main():
             so = torch.empty((len(xs), P1), dtype=torch.float32, device=dev)
             ref64 = torch.empty((len(xs), P1), dtype=torch.float64, device=dev)
             ref32 = torch.empty((len(xs), P1), dtype=torch.float32, device=dev)
-            t_sur = dtime(lambda: sur.xfxq2(xsd, qsd, P1, out=so))
+            t_sur = dtime(lambda: sur.xfxq2(xsd, qsd, out=so))
             t_i64 = dtime(lambda: pdfmi.xfxq2(m1, g1.pids, xsd, qsd, out=ref64))
             t_i32 = dtime(lambda: pdfmi.xfxq2_f32(m1, g1.pids, xsd, qsd, out=ref32))
             idx = np.random.default_rng(0).choice(len(xs), 20000, replace=False)
@@ -379,8 +379,8 @@ def main():
                         pdfmi.xfxq2_f32(m1, PIDS, X2[c], Q[c], out=f2_32)
                         pdfmi.mc_chunk_sum(f1_32, f2_32, al, workspace=ws, out=sums[kind][c:c + 1])
                     else:   # surrogate gives the stored flavours; absent ones are zero and add nothing
-                        sur.xfxq2(X1[c], Q[c], P1, out=s1)
-                        sur.xfxq2(X2[c], Q[c], P1, out=s2)
+                        sur.xfxq2(X1[c], Q[c], out=s1)
+                        sur.xfxq2(X2[c], Q[c], out=s2)
                         pdfmi.mc_chunk_sum(s1, s2, al, workspace=ws, out=sums[kind][c:c + 1])
             sums["f64_fused"] = torch.empty(nchunk, dtype=torch.float64, device=dev)
             sums["f32_fused"] = torch.empty(nchunk, dtype=torch.float64, device=dev)

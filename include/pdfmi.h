@@ -235,13 +235,20 @@ int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, int32_t out_f64, p
 /*
  * MLP surrogate of one member's PDFs (an alternative evaluator grown on top
  * of the interpolator; the interpolator remains the reference for its error).
+ * A surrogate is created on one loaded member and identified by its own id
+ * (sid): several surrogates may share a member; every call that needs the
+ * member's grid (set_data, xfxq2) returns PDF_ERR_MEMBER once that member
+ * was unloaded, even if a later load reuses its id.
  * Network (ln x, ln Q^2) normalised to [-1,1]^2 -> 64 -> 64 -> 64 -> 16,
- * tanh hidden activations; BF16 weights and activations on the matrix cores
- * with FP32 accumulation; FP32 master weights trained with Adam.  Output c is
- * scaled by a positive envelope E_c(x) of the grid (largest |xf_c| over Q^2
- * at each x knot, linear in ln x), so the network predicts xf_c / E_c.  At
- * most 16 stored flavours.  Flat FP32 parameter layout: W1[64][2], b1[64],
- * W2[64][64], b2[64], W3[64][64], b3[64], W4[16][64], b4[16].
+ * tanh hidden activations.  The first layer runs in FP32; layers 2-4 on the
+ * BF16 matrix cores with FP32 accumulation, every operand carried as a BF16
+ * pair (value = hi + lo, products hi*hi + lo*hi + hi*lo: about 16 significant
+ * bits); FP32 master weights trained with Adam.  Output c is scaled by an
+ * envelope E_c(x) of the grid (a signed cubic Hermite in ln x through the
+ * value of largest magnitude over Q^2 at each x knot), so the network
+ * predicts xf_c / E_c.  At most 16 stored flavours and 512 x knots.  Flat
+ * FP32 parameter layout: W1[64][2], b1[64], W2[64][64], b2[64], W3[64][64],
+ * b3[64], W4[16][64], b4[16].
  */
 int pdf_surrogate_param_count(int32_t* n_out);
 /* New surrogate for a member; Glorot-uniform weights from a counter-based
@@ -249,27 +256,46 @@ int pdf_surrogate_param_count(int32_t* n_out);
 int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_out);
 int pdf_surrogate_destroy(int32_t sid);
 /* Training set: n DEVICE points (x, q2); targets are computed by the
- * library's FP64 interpolator and kept on the device.  Synchronises stream. */
+ * library's FP64 interpolator.  Only the points inside the network's domain
+ * (see pdf_surrogate_xfxq2) are kept, in order, on the device; PDF_ERR_ARG if
+ * fewer than 16 remain.  Synchronises stream. */
 int pdf_surrogate_set_data(int32_t sid, const double* x, const double* q2, int64_t n, pdf_stream_t stream);
-/* steps Adam steps (beta 0.9 / 0.999, eps 1e-8) on consecutive batches of
- * `batch` samples (multiple of 16); learning rate on a cosine schedule from
- * lr to lr_final over total_steps, indexed by the surrogate's global step, so
- * a run split across calls (or across a save/load) is identical to one call. */
-int pdf_surrogate_train(int32_t sid, int32_t steps, int32_t batch, float lr, float lr_final,
-                        int32_t total_steps, pdf_stream_t stream);
+/* Options of pdf_surrogate_train. */
+typedef struct {
+    int32_t steps;        /* Adam steps to take in this call (>= 0) */
+    int32_t batch;        /* samples per step, a multiple of 16 (consecutive slices of the training set) */
+    float lr;             /* learning rate at global step 0 */
+    float lr_final;       /* learning rate from global step total_steps on */
+    int32_t total_steps;  /* length of the cosine schedule (>= 1) */
+    float* loss_out;      /* NULL, or DEVICE [steps]: each step's batch loss before its update */
+} pdf_train_opts;
+/* opts->steps Adam steps (beta 0.9 / 0.999, eps 1e-8); learning rate on a
+ * cosine schedule from lr to lr_final over total_steps, indexed by the
+ * surrogate's global step (as is the batch slice), so a run split across
+ * calls (or across a save/load) is identical to one call.  Asynchronous on
+ * stream.  PDF_ERR_STATE without a training set of at least one batch. */
+int pdf_surrogate_train(int32_t sid, const pdf_train_opts* opts, pdf_stream_t stream);
 /* One forward + backward pass on DEVICE inputs in[batch][2] (normalised) and
  * targets[batch][16]: writes the flat FP32 gradient (param_count floats) and
  * the mean-squared-error loss (1 float) to DEVICE memory.  No update. */
 int pdf_surrogate_grad(int32_t sid, const float* in, const float* target, int32_t batch,
                        float* grad_out, float* loss_out, pdf_stream_t stream);
+/* One Adam update of the parameters with a caller-supplied DEVICE gradient
+ * (param_count floats) at learning rate lr (for losses of the caller's own);
+ * advances the global step like a training step.  Asynchronous on stream. */
+int pdf_surrogate_adam(int32_t sid, const float* grad, float lr, pdf_stream_t stream);
 /* Read (write == 0) or replace (write != 0) the FP32 master parameters
  * (HOST array of param_count floats).  Synchronises the device. */
 int pdf_surrogate_params(int32_t sid, float* host, int32_t write);
-/* Every stored flavour at n DEVICE points, FP32 point-major [n][P]; points
- * outside the grid or in the first/last x or Q^2 cell of a sub-grid are
- * evaluated by the FP32 interpolator instead. */
-int pdf_surrogate_xfxq2(int32_t sid, const double* x, const double* q2, int64_t n, float* out,
-                        pdf_stream_t stream);
+/* x*f of the requested flavours at n DEVICE points, FP32 point-major
+ * [n][P] (pids, n_pids as in pdf_xfxq2: a HOST list, NULL = every stored
+ * flavour in load order; a valid flavour the grid does not store gives 0).
+ * Points outside the grid or in the first/last x or Q^2 cell of a sub-grid
+ * (which includes the cells at flavour thresholds) are evaluated by the FP32
+ * interpolator instead of the network; invalid points give NaN and count in
+ * pdf_error_count.  Asynchronous on stream. */
+int pdf_surrogate_xfxq2(int32_t sid, const int32_t* pids, int32_t n_pids, const double* x, const double* q2,
+                        int64_t n, float* out, pdf_stream_t stream);
 /* Checkpoint: parameters, Adam moments and step count, with a checksum. */
 int pdf_surrogate_save(int32_t sid, const char* path);
 int pdf_surrogate_load(int32_t sid, const char* path);

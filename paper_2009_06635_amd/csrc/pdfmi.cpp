@@ -35,17 +35,21 @@ BatchLaunch batch_launch_params(bool f32, bool lds, int max_tbl, int64_t max_ele
 hipError_t batch_prepare(const BatchLaunch& L);
 hipError_t batch_launch(const BatchLaunch& L, void** args, unsigned* counter, hipStream_t s);
 int sur_nparams();
-constexpr int kSurMaxEnvKnots = 1024;  // the inference kernel stages the envelope in LDS
+constexpr int kSurMaxEnvKnots = 512;   // the inference kernel stages the envelope in LDS
 constexpr int kAlphasMaxHints = 2048;  // alpha_s search hints staged in LDS
 int sur_out_width();
 int sur_hidden();
-hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s);
+hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, float* loss_out,
+                                hipStream_t s);
 hipError_t sur_adam(const SurBufs& b, float lr, int step, hipStream_t s);
 hipError_t sur_refresh_bf16(const SurBufs& b, hipStream_t s);
-hipError_t sur_prep(const SurDev& S, const double* x, const double* q2, const double* xf, int64_t n, float* in,
-                    float* T, hipStream_t s);
-hipError_t sur_infer(const SurDev& S, const MemberDev& m, const SurBufs& b, const double* x, const double* q2,
-                     int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu, hipStream_t s);
+hipError_t sur_prep(const SurDev& S, const MemberDev& m, const double* x, const double* q2, const double* xf,
+                    int64_t n, float* in, float* T, unsigned char* keep, hipStream_t s);
+hipError_t sur_gather(const float* in_all, const float* T_all, const int64_t* idx, int64_t n, float* in, float* T,
+                      hipStream_t s);
+hipError_t sur_infer(const SurDev& S, const MemberDev& m, const ReqCols& rc, const SurBufs& b, const double* x,
+                     const double* q2, int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu,
+                     hipStream_t s);
 template <typename T>
 hipError_t launch_mc_sum(const T*, const T*, int, const double*, int64_t, double*, double*, hipStream_t);
 template <typename T>
@@ -1117,9 +1121,10 @@ int sur_ensure_batch(Surrogate& S, int B) {
   if (S.bmem) (void)hipFree(S.bmem);
   S.bmem = nullptr;
   const int H = sur_hidden(), O = sur_out_width();
-  // floats: h1,h2,h3,dh,dz (B*H each) + y,dy,sq (B*O each); shorts: h1b,h2b,h3b,dzb (B*H), dyb (B*O)
+  // floats: h1,h2,h3,dh,dz (B*H each) + y,dy,sq (B*O each);
+  // shorts: h1b,h2b,h3b,h1l,h2l,h3l,dzb (B*H), dyb (B*O)
   const size_t nw = (size_t)64 * H * H;  // split-reduction partials
-  const size_t nf = (size_t)B * (5 * H + 3 * O) + nw, ns = (size_t)B * (4 * H + O);
+  const size_t nf = (size_t)B * (5 * H + 3 * O) + nw, ns = (size_t)B * (7 * H + O);
   hipError_t e = hipMalloc(&S.bmem, nf * 4 + ns * 2 + 256);
   if (e != hipSuccess) return fail_hip(e, "hipMalloc(surrogate batch)");
   float* f = static_cast<float*>(S.bmem);
@@ -1136,6 +1141,9 @@ int sur_ensure_batch(Surrogate& S, int B) {
   S.b.h1b = h; h += (size_t)B * H;
   S.b.h2b = h; h += (size_t)B * H;
   S.b.h3b = h; h += (size_t)B * H;
+  S.b.h1l = h; h += (size_t)B * H;
+  S.b.h2l = h; h += (size_t)B * H;
+  S.b.h3l = h; h += (size_t)B * H;
   S.b.dzb = h; h += (size_t)B * H;
   S.b.dyb = h;
   S.bcap = B;
@@ -1173,9 +1181,11 @@ extern "C" int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_
   const int K = (int)M->h_shape.size() / 2;
   const int nx0 = M->h_shape[0];
   const double* xk0 = M->h_knots.data();
-  // envelope over sub-grid 0's x knots: largest |xf| over every Q^2 knot of every sub-grid
-  std::vector<float> env((size_t)nx0 * O, 0.0f), lxk(nx0);
-  for (int i = 0; i < nx0; ++i) lxk[i] = (float)std::log(xk0[i]);
+  // envelope over sub-grid 0's x knots: at each, the value of largest magnitude over every Q^2 knot of every
+  // sub-grid (signed); slopes d E / d ln x by finite differences (mean of the adjacent secants, one-sided at
+  // the ends)
+  std::vector<double> envv((size_t)nx0 * O, 0.0), enva((size_t)nx0 * O, -1.0), lxk(nx0);
+  for (int i = 0; i < nx0; ++i) lxk[i] = std::log(xk0[i]);
   int64_t ko = 0, vo = 0;
   for (int k = 0; k < K; ++k) {
     const int nx = M->h_shape[2 * k], nq = M->h_shape[2 * k + 1];
@@ -1186,13 +1196,26 @@ extern "C" int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_
         if (std::fabs(std::log(xk0[j] / xk[ix])) < std::fabs(std::log(xk0[i0] / xk[ix]))) i0 = j;
       for (int iq = 0; iq < nq; ++iq)
         for (int c = 0; c < P; ++c) {
-          const float a = (float)std::fabs(M->h_values[vo + ((int64_t)ix * nq + iq) * P + c]);
-          if (a > env[(size_t)i0 * O + c]) env[(size_t)i0 * O + c] = a;
+          const double v = M->h_values[vo + ((int64_t)ix * nq + iq) * P + c];
+          if (std::fabs(v) > enva[(size_t)i0 * O + c]) {
+            enva[(size_t)i0 * O + c] = std::fabs(v);
+            envv[(size_t)i0 * O + c] = v;
+          }
         }
     }
     ko += nx + nq;
     vo += (int64_t)nx * nq * P;
   }
+  std::vector<float> env((size_t)nx0 * O), envd((size_t)nx0 * O);
+  for (int i = 0; i < nx0; ++i)
+    for (int c = 0; c < O; ++c) {
+      auto sec = [&](int j) {  // secant over cell j
+        return (envv[(size_t)(j + 1) * O + c] - envv[(size_t)j * O + c]) / (lxk[j + 1] - lxk[j]);
+      };
+      const double d = i == 0 ? sec(0) : i == nx0 - 1 ? sec(nx0 - 2) : 0.5 * (sec(i - 1) + sec(i));
+      env[(size_t)i * O + c] = (float)envv[(size_t)i * O + c];
+      envd[(size_t)i * O + c] = (float)d;
+    }
   Surrogate S;
   S.used = true;
   S.member = member;
@@ -1220,9 +1243,9 @@ extern "C" int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_
       o += nx + nq;
     }
   }
-  const size_t bp = align_up((size_t)NP * 4, 256), bpb = align_up((size_t)NP * 2, 256);
-  const size_t be = align_up(env.size() * 4, 256), bl = align_up(lxk.size() * 4, 256);
-  hipError_t e = hipMalloc(&S.pmem, 4 * bp + bpb + be + bl + 2048);
+  const size_t bp = align_up((size_t)NP * 4, 256), bpb = align_up((size_t)NP * 4, 256);  // Pb: hi and lo halves
+  const size_t be = align_up(env.size() * 4, 256), bl = align_up(lxk.size() * 8, 256);
+  hipError_t e = hipMalloc(&S.pmem, 4 * bp + bpb + 2 * be + bl + 2048);
   if (e != hipSuccess) return fail_hip(e, "hipMalloc(surrogate)");
   unsigned char* b = static_cast<unsigned char*>(S.pmem);
   S.b.P = reinterpret_cast<float*>(b);
@@ -1230,19 +1253,22 @@ extern "C" int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_
   S.b.V = reinterpret_cast<float*>(b + 2 * bp);
   S.b.G = reinterpret_cast<float*>(b + 3 * bp);
   S.b.Pb = reinterpret_cast<unsigned short*>(b + 4 * bp);
-  float* envd = reinterpret_cast<float*>(b + 4 * bp + bpb);
-  float* lxkd = reinterpret_cast<float*>(b + 4 * bp + bpb + be);
-  S.b.loss = reinterpret_cast<float*>(b + 4 * bp + bpb + be + bl);
+  float* envdev = reinterpret_cast<float*>(b + 4 * bp + bpb);
+  float* envddev = reinterpret_cast<float*>(b + 4 * bp + bpb + be);
+  double* lxkd = reinterpret_cast<double*>(b + 4 * bp + bpb + 2 * be);
+  S.b.loss = reinterpret_cast<float*>(b + 4 * bp + bpb + 2 * be + bl);
   S.b.partial = S.b.loss + 64;
-  S.sd.env = envd;
+  S.sd.env = envdev;
+  S.sd.envd = envddev;
   S.sd.lxk = lxkd;
   const std::vector<float> p0 = sur_init_params(seed);
   std::vector<float> zeros((size_t)NP, 0.0f);
   if ((e = hipMemcpy(S.b.P, p0.data(), (size_t)NP * 4, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(S.b.M, zeros.data(), (size_t)NP * 4, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(S.b.V, zeros.data(), (size_t)NP * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(envd, env.data(), env.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(lxkd, lxk.data(), lxk.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(envdev, env.data(), env.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(envddev, envd.data(), envd.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(lxkd, lxk.data(), lxk.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = sur_refresh_bf16(S.b, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
     sur_release(S);
     return fail_hip(e, "surrogate upload");
@@ -1281,36 +1307,60 @@ extern "C" int pdf_surrogate_set_data(int32_t sid, const double* x, const double
   S->d_in = nullptr;
   S->d_t = nullptr;
   S->n_train = 0;
-  float* din = nullptr;
-  hipError_t e = hipMalloc(&din, (size_t)n * (2 + O) * 4);
-  if (e != hipSuccess) return fail_hip(e, "hipMalloc(training data)");
-  double* xf = nullptr;
-  if ((e = hipMalloc(&xf, (size_t)n * P * 8)) != hipSuccess) {
-    (void)hipFree(din);
-    return fail_hip(e, "hipMalloc(targets)");
-  }
+  // every sample: inputs, targets, in-domain flag; then the in-domain samples, in order
+  void* tmp = nullptr;
+  const size_t b_in = align_up((size_t)n * (2 + O) * 4, 256), b_xf = align_up((size_t)n * P * 8, 256);
+  hipError_t e = hipMalloc(&tmp, b_in + b_xf + align_up((size_t)n, 256) + (size_t)n * 8);
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc(training samples)");
+  float* in_all = static_cast<float*>(tmp);
+  float* t_all = in_all + 2 * n;
+  double* xf = reinterpret_cast<double*>(static_cast<unsigned char*>(tmp) + b_in);
+  unsigned char* keep = static_cast<unsigned char*>(tmp) + b_in + b_xf;
+  int64_t* idx = reinterpret_cast<int64_t*>(keep + align_up((size_t)n, 256));
   ReqCols rc{};
   build_req(*M, nullptr, 0, rc);
   // targets from this library's FP64 interpolator
   const LaunchCfg cfg{g_ncu, g_blocks_per_cu, g_vector_cols};
   e = launch_xfxq2_f64(M->dev, rc, x, q2, n, xf, g_nerr, lds_grid_elems(*M, false, n), M->invL01, cfg, nullptr,
                        nullptr, s);
-  if (e == hipSuccess) e = sur_prep(S->sd, x, q2, xf, n, din, din + 2 * n, s);
+  if (e == hipSuccess) e = sur_prep(S->sd, M->dev, x, q2, xf, n, in_all, t_all, keep, s);
+  std::vector<unsigned char> hkeep((size_t)n);
+  if (e == hipSuccess) e = hipMemcpyAsync(hkeep.data(), keep, (size_t)n, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(xf);
+  std::vector<int64_t> hidx;
+  if (e == hipSuccess) {
+    hidx.reserve((size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+      if (hkeep[(size_t)i]) hidx.push_back(i);
+  }
+  const int64_t nk = (int64_t)hidx.size();
+  float* din = nullptr;
+  if (e == hipSuccess && nk < 16) {
+    (void)hipFree(tmp);
+    return fail(PDF_ERR_ARG, "only %lld of the %lld points lie in the network's domain (need >= 16)",
+                (long long)nk, (long long)n);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(idx, hidx.data(), (size_t)nk * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMalloc(&din, (size_t)nk * (2 + O) * 4);
+  if (e == hipSuccess) e = sur_gather(in_all, t_all, idx, nk, din, din + 2 * nk, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(tmp);
   if (e != hipSuccess) {
-    (void)hipFree(din);
+    if (din) (void)hipFree(din);
     return fail_hip(e, "surrogate targets");
   }
   S->d_in = din;
-  S->d_t = din + 2 * n;
-  S->n_train = n;
+  S->d_t = din + 2 * nk;
+  S->n_train = nk;
   return PDF_OK;
 }
 
-extern "C" int pdf_surrogate_train(int32_t sid, int32_t steps, int32_t batch, float lr, float lr_final,
-                                   int32_t total_steps, pdf_stream_t stream) {
-  if (steps < 0 || batch < 16 || (batch & 15) || total_steps < 1) return fail(PDF_ERR_ARG, "bad training arguments");
+extern "C" int pdf_surrogate_train(int32_t sid, const pdf_train_opts* opts, pdf_stream_t stream) {
+  if (!opts) return fail(PDF_ERR_ARG, "null opts");
+  const int steps = opts->steps, batch = opts->batch;
+  if (steps < 0 || batch < 16 || (batch & 15) || opts->total_steps < 1 || !(opts->lr >= 0.0f) ||
+      !(opts->lr_final >= 0.0f))
+    return fail(PDF_ERR_ARG, "bad training options");
   std::lock_guard<std::mutex> lock(g_mu);
   Surrogate* S = get_sur(sid);
   if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
@@ -1323,9 +1373,11 @@ extern "C" int pdf_surrogate_train(int32_t sid, int32_t steps, int32_t batch, fl
   for (int i = 0; i < steps; ++i) {
     const int64_t t = S->step;  // global step: batch slice and learning rate depend only on it
     const int64_t off = (t % nb) * batch;
-    const double frac = std::min(1.0, (double)t / (double)total_steps);
-    const float lr_t = (float)(lr_final + 0.5 * (lr - lr_final) * (1.0 + std::cos(3.141592653589793 * frac)));
-    hipError_t e = sur_forward_backward(S->b, S->d_in + 2 * off, S->d_t + O * off, batch, s);
+    const double frac = std::min(1.0, (double)t / (double)opts->total_steps);
+    const float lr_t = (float)(opts->lr_final + 0.5 * ((double)opts->lr - opts->lr_final) *
+                                                    (1.0 + std::cos(3.141592653589793 * frac)));
+    hipError_t e = sur_forward_backward(S->b, S->d_in + 2 * off, S->d_t + O * off, batch,
+                                        opts->loss_out ? opts->loss_out + i : nullptr, s);
     if (e == hipSuccess) e = sur_adam(S->b, lr_t, (int)(t + 1), s);
     if (e != hipSuccess) return fail_hip(e, "surrogate training step");
     ++S->step;
@@ -1343,10 +1395,22 @@ extern "C" int pdf_surrogate_grad(int32_t sid, const float* in, const float* tar
   int rc = sur_ensure_batch(*S, batch);
   if (rc != PDF_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = sur_forward_backward(S->b, in, target, batch, s);
+  hipError_t e = sur_forward_backward(S->b, in, target, batch, loss_out, s);
   if (e == hipSuccess) e = hipMemcpyAsync(grad_out, S->b.G, (size_t)sur_nparams() * 4, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(loss_out, S->b.loss, 4, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return fail_hip(e, "surrogate gradient");
+  return PDF_OK;
+}
+
+extern "C" int pdf_surrogate_adam(int32_t sid, const float* grad, float lr, pdf_stream_t stream) {
+  if (!grad || !(lr >= 0.0f)) return fail(PDF_ERR_ARG, "bad Adam arguments");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Surrogate* S = get_sur(sid);
+  if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(S->b.G, grad, (size_t)sur_nparams() * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = sur_adam(S->b, lr, (int)(S->step + 1), s);
+  if (e != hipSuccess) return fail_hip(e, "surrogate Adam step");
+  ++S->step;
   return PDF_OK;
 }
 
@@ -1370,8 +1434,8 @@ extern "C" int pdf_surrogate_params(int32_t sid, float* host, int32_t write) {
   return PDF_OK;
 }
 
-extern "C" int pdf_surrogate_xfxq2(int32_t sid, const double* x, const double* q2, int64_t n, float* out,
-                                   pdf_stream_t stream) {
+extern "C" int pdf_surrogate_xfxq2(int32_t sid, const int32_t* pids, int32_t n_pids, const double* x,
+                                   const double* q2, int64_t n, float* out, pdf_stream_t stream) {
   int rc = check_stream_args(x, q2, n);
   if (rc != PDF_OK) return rc;
   if (n > 0 && !out) return fail(PDF_ERR_ARG, "null out");
@@ -1380,8 +1444,10 @@ extern "C" int pdf_surrogate_xfxq2(int32_t sid, const double* x, const double* q
   if (!S) return fail(PDF_ERR_ARG, "unknown surrogate %d", sid);
   Member* M = sur_member(*S);
   if (!M) return fail(PDF_ERR_MEMBER, "surrogate's member %d was unloaded", S->member);
-  if (n == 0) return PDF_OK;
-  hipError_t e = sur_infer(S->sd, M->dev, S->b, x, q2, n, out, M->invL01, g_nerr, g_ncu, (hipStream_t)stream);
+  ReqCols cols{};
+  if ((rc = build_req(*M, pids, n_pids, cols)) != PDF_OK) return rc;
+  if (n == 0 || cols.n == 0) return PDF_OK;
+  hipError_t e = sur_infer(S->sd, M->dev, cols, S->b, x, q2, n, out, M->invL01, g_nerr, g_ncu, (hipStream_t)stream);
   if (e != hipSuccess) return fail_hip(e, "launch surrogate inference");
   return PDF_OK;
 }

@@ -148,14 +148,19 @@ struct BatchLaunch {
   size_t shm;
 };
 
-// Surrogate input normalisation and output envelope (device tables).
+// Surrogate input normalisation and output envelope (device tables).  The
+// envelope of column c is a signed cubic Hermite in ln x through one value
+// per sub-grid-0 x knot (the grid value of largest magnitude over every Q^2
+// knot at that x), with finite-difference slopes (mean of the adjacent
+// secants, the one secant at the ends).
 struct SurDev {
   int P;              // stored columns (<= 16)
   int nx;             // envelope knots (sub-grid 0 x knots)
   double lx0, ilx;    // u = 2 (ln x - lx0) * ilx - 1
   double lq0, ilq;    // v = 2 (ln Q^2 - lq0) * ilq - 1
-  const float* lxk;   // [nx] ln of the envelope knots
+  const double* lxk;  // [nx] ln of the envelope knots
   const float* env;   // [nx][16] envelope values
+  const float* envd;  // [nx][16] envelope slopes d E / d ln x
   // inference trusts the network inside sub-grid k for txlo[k] <= x < txhi[k]
   // and tqlo[k] <= Q^2 < tqhi[k] (second to second-last knots) when trust[k]
   int trust[kMaxSub];
@@ -163,12 +168,13 @@ struct SurDev {
 };
 
 // Surrogate device buffers (parameters, Adam moments, gradients, batch activations).
+// Matrix operands are BF16 pairs (hi, lo) with value = hi + lo.
 struct SurBufs {
   float* P;                 // FP32 master parameters
-  unsigned short* Pb;       // BF16 copies
+  unsigned short* Pb;       // BF16 halves of the parameters: [0, n) hi, [n, 2n) lo
   float *M, *V, *G;         // Adam moments, gradients
   float *h1, *h2, *h3, *y, *dy, *dh, *dz, *sq;
-  unsigned short *h1b, *h2b, *h3b, *dyb, *dzb;
+  unsigned short *h1b, *h2b, *h3b, *h1l, *h2l, *h3l, *dyb, *dzb;
   float* loss;              // [1]
   float* partial;           // [256]
   float* wpart;             // split-reduction partial sums, 64 slices x 64 x 64

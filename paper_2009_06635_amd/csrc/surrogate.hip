@@ -1,14 +1,23 @@
 // MLP surrogate of one member's PDFs (growth path of the interpolation
 // library): (ln x, ln Q^2) -> all stored flavours, 2 -> 64 -> 64 -> 64 -> 16
 // (outputs beyond the stored columns are padding), tanh hidden activations,
-// BF16 weights and activations with FP32 accumulation on the matrix cores
-// (v_mfma_f32_16x16x32_bf16), FP32 master weights, Adam.
+// FP32 master weights trained with Adam.
 //
-// The network predicts y_c = xf_c / E_c(x), where E_c is a positive envelope
-// of the grid (largest |xf_c| over Q^2 at each x knot, linear in ln x between
-// knots), so every target is O(1).  Inference falls back to the FP32
-// interpolator outside the grid and in the first/last x or Q^2 cell of a
-// sub-grid (which includes the cells next to flavour thresholds).
+// Arithmetic: the first layer (two inputs) in FP32 on the vector ALUs;
+// layers 2-4 on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation) with every operand carried as a BF16 pair (value = hi + lo,
+// lo = bf16(value - hi)) and each product formed as hi*hi + lo*hi + hi*lo:
+// about 16 significant bits per operand, where single BF16 operands (8 bits)
+// left the network's relative error near 1e-3.  The backward pass multiplies
+// BF16 signals with the hi halves.
+//
+// The network predicts y_c = xf_c / E_c(x), where E_c is a signed cubic
+// Hermite envelope in ln x through the grid value of largest magnitude at
+// each x knot (it follows the x dependence, sign changes included, so the
+// targets are smooth and O(1)).  Training uses only samples inside the
+// network's domain; inference falls back to the FP32 interpolator outside
+// the grid and in the first/last x or Q^2 cell of a sub-grid (which includes
+// the cells next to flavour thresholds).
 //
 // Training is deterministic: every reduction has a fixed order (one wave per
 // 16x16 output tile loops over the whole batch; bias sums are sequential per
@@ -17,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "interp_dev.h"
 #include "pdfmi_dev.h"
@@ -40,6 +51,11 @@ __device__ __forceinline__ unsigned short bf16_bits(float f) {
 __device__ __forceinline__ float bf16_float(unsigned short b) {
   return __uint_as_float(((unsigned)b) << 16);
 }
+// BF16 pair of v: hi = bf16(v), lo = bf16(v - hi) (the difference is exact in FP32)
+__device__ __forceinline__ void split_bits(float v, unsigned short& hi, unsigned short& lo) {
+  hi = bf16_bits(v);
+  lo = bf16_bits(v - bf16_float(hi));
+}
 
 // tanh(z) = 1 - 2 / (exp(2z) + 1) from the hardware exp2 and reciprocal:
 // exp2 overflows to +inf (result 1) and underflows to 0 (result -1); near 0
@@ -55,17 +71,21 @@ __device__ __forceinline__ float tanh_f(float z) { return tanh_scaled(kTwoLog2e 
 // ---------------------------------------------------------------------------------------
 // Generic BF16 GEMM tile: C[m][n] = sum_k A(m,k) B(k,n) (+ bias[n]) (then tanh)
 // A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (BF16 bit patterns);
-// M, N multiples of 16; K any (zero padded to 32).  One wave per 16x16 tile,
-// K walked in order (fixed summation order).  Writes FP32 C (ldc) and, if
-// Cb != null, its BF16 copy.
+// with A2 / B2 (the lo halves of split operands, same strides) the products
+// are A B + A2 B + A B2.  M, N multiples of 16; K any (zero padded to 32).
+// One wave per 16x16 tile, K walked in order (fixed summation order).
+// Writes FP32 C (ldc) and, if Cb != null, its BF16 hi half (and the lo half
+// to Cl if not null).
 // With gridDim.y > 1 workgroup y covers k in [y kchunk, (y + 1) kchunk) and
 // writes its partial tile to C + y M ldc (the slices are added in order by
 // k_sum_slices); bias and activation then belong to the unsplit form only.
-__global__ __launch_bounds__(64) void k_gemm_bf16(const unsigned short* __restrict__ A, int sam, int sak,
-                                                  const unsigned short* __restrict__ B, int sbk, int sbn,
+__global__ __launch_bounds__(64) void k_gemm_bf16(const unsigned short* __restrict__ A,
+                                                  const unsigned short* __restrict__ A2, int sam, int sak,
+                                                  const unsigned short* __restrict__ B,
+                                                  const unsigned short* __restrict__ B2, int sbk, int sbn,
                                                   float* __restrict__ C, int ldc, unsigned short* __restrict__ Cb,
-                                                  int M, int N, int K, const float* __restrict__ bias, int act,
-                                                  int kchunk) {
+                                                  unsigned short* __restrict__ Cl, int M, int N, int K,
+                                                  const float* __restrict__ bias, int act, int kchunk) {
   const int tn = N / 16;
   const int m0 = (blockIdx.x / tn) * 16, n0 = (blockIdx.x % tn) * 16;
   const int l = threadIdx.x, r = l & 15, g = l >> 4;
@@ -73,16 +93,19 @@ __global__ __launch_bounds__(64) void k_gemm_bf16(const unsigned short* __restri
   C += (int64_t)blockIdx.y * M * ldc;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   for (int k0 = kb; k0 < ke; k0 += 32) {
-    bf16x8 a, b;
+    bf16x8 a, b, a2, b2;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = k0 + 8 * g + i;
-      const unsigned short av = k < ke ? A[(int64_t)(m0 + r) * sam + (int64_t)k * sak] : (unsigned short)0;
-      const unsigned short bv = k < ke ? B[(int64_t)k * sbk + (int64_t)(n0 + r) * sbn] : (unsigned short)0;
-      a[i] = __builtin_bit_cast(__bf16, av);
-      b[i] = __builtin_bit_cast(__bf16, bv);
+      const int64_t ia = (int64_t)(m0 + r) * sam + (int64_t)k * sak, ib = (int64_t)k * sbk + (int64_t)(n0 + r) * sbn;
+      a[i] = __builtin_bit_cast(__bf16, k < ke ? A[ia] : (unsigned short)0);
+      b[i] = __builtin_bit_cast(__bf16, k < ke ? B[ib] : (unsigned short)0);
+      a2[i] = __builtin_bit_cast(__bf16, (A2 && k < ke) ? A2[ia] : (unsigned short)0);
+      b2[i] = __builtin_bit_cast(__bf16, (B2 && k < ke) ? B2[ib] : (unsigned short)0);
     }
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    if (A2) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b, acc, 0, 0, 0);
+    if (B2) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b2, acc, 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -91,23 +114,26 @@ __global__ __launch_bounds__(64) void k_gemm_bf16(const unsigned short* __restri
     if (bias) v += bias[n];
     if (act) v = tanh_f(v);
     C[(int64_t)m * ldc + n] = v;
-    if (Cb) Cb[(int64_t)m * ldc + n] = bf16_bits(v);
+    if (Cb) {
+      unsigned short hi, lo;
+      split_bits(v, hi, lo);
+      Cb[(int64_t)m * ldc + n] = hi;
+      if (Cl) Cl[(int64_t)m * ldc + n] = lo;
+    }
   }
 }
 
-// Layer 1 (K = 2, on the vector ALUs): h1 = tanh(W1 in + b1), FP32 and BF16.
+// Layer 1 (K = 2, FP32 on the vector ALUs): h1 = tanh(W1 in + b1), FP32 and
+// its BF16 pair.
 __global__ void k_layer1(const float* __restrict__ in, const float* __restrict__ P, int B, float* __restrict__ h,
-                         unsigned short* __restrict__ hb) {
+                         unsigned short* __restrict__ hb, unsigned short* __restrict__ hl) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= (int64_t)B * kH) return;
   const int b = (int)(i / kH), j = (int)(i % kH);
-  // the inputs and W1 are BF16-rounded like every other matrix operand
-  const float u = bf16_float(bf16_bits(in[2 * b])), v = bf16_float(bf16_bits(in[2 * b + 1]));
-  const float w0 = bf16_float(bf16_bits(P[kOffW1 + 2 * j])), w1 = bf16_float(bf16_bits(P[kOffW1 + 2 * j + 1]));
-  const float z = fmaf(w0, u, fmaf(w1, v, P[kOffB1 + j]));
+  const float z = fmaf(P[kOffW1 + 2 * j], in[2 * b], fmaf(P[kOffW1 + 2 * j + 1], in[2 * b + 1], P[kOffB1 + j]));
   const float t = tanh_f(z);
   h[i] = t;
-  hb[i] = bf16_bits(t);
+  split_bits(t, hb[i], hl[i]);
 }
 
 // Loss (mean squared error over B x kO) and its gradient dY = 2 (Y - T) / (B kO).
@@ -145,9 +171,9 @@ __global__ void k_col_sum(const float* __restrict__ X, int B, int ncols, int kch
   out[(int64_t)blockIdx.y * ncols + c] = s;
 }
 
-// dW1[j][t] = sum_b dZ1[b][j] in[b][t] (BF16-rounded operands, FP32 sum in b
-// order within a slice of kchunk rows per blockIdx.y; slices added in order).
-__global__ void k_dw1(const unsigned short* __restrict__ dZb, const float* __restrict__ in, int B, int kchunk,
+// dW1[j][t] = sum_b dZ1[b][j] in[b][t] (FP32, in b order within a slice of
+// kchunk rows per blockIdx.y; slices added in order).
+__global__ void k_dw1(const float* __restrict__ dZ, const float* __restrict__ in, int B, int kchunk,
                       float* __restrict__ dW1) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= kH * 2) return;
@@ -155,11 +181,12 @@ __global__ void k_dw1(const unsigned short* __restrict__ dZb, const float* __res
   const int b0 = blockIdx.y * kchunk, b1 = min(B, b0 + kchunk);
   float s = 0.0f;
 #pragma unroll 16
-  for (int b = b0; b < b1; ++b) s = fmaf(bf16_float(dZb[(int64_t)b * kH + j]), bf16_float(bf16_bits(in[2 * b + t])), s);
+  for (int b = b0; b < b1; ++b) s = fmaf(dZ[(int64_t)b * kH + j], in[2 * b + t], s);
   dW1[(int64_t)blockIdx.y * kH * 2 + o] = s;
 }
 
-// Adam step on the FP32 masters, then their BF16 copies.
+// Adam step on the FP32 masters (Kingma & Ba, bias-corrected moments; c1 =
+// 1 - b1^t, c2 = 1 - b2^t), then their BF16 pairs.
 __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ Mm,
                        float* __restrict__ Vm, unsigned short* __restrict__ Pb, int n, float lr, float b1, float b2,
                        float eps, float c1, float c2) {
@@ -172,62 +199,49 @@ __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float
   Vm[i] = v;
   const float p = P[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
   P[i] = p;
-  Pb[i] = bf16_bits(p);
+  split_bits(p, Pb[i], Pb[n + i]);
 }
 
 __global__ void k_to_bf16(const float* __restrict__ P, unsigned short* __restrict__ Pb, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) Pb[i] = bf16_bits(P[i]);
+  if (i < n) split_bits(P[i], Pb[i], Pb[n + i]);
 }
 
 // ---------------------------------------------------------------------------------------
-// Sample preparation: normalised inputs and envelope-scaled targets.
+// Envelope and sample preparation.
 
+// Hermite weights of the envelope at ln x: cell i (largest i <= nx-2 with
+// lxk[i] <= ln x, clamped) and the basis h00, h10 D, h01, h11 D of its
+// parameter t (clamped to [0, 1]), D = lxk[i+1] - lxk[i].
+struct EnvW {
+  int i;
+  float h00, h10, h01, h11;
+};
 
-__device__ __forceinline__ void envelope(const SurDev& S, float lx, float e[kO]) {
-  int lo = 0, hi = S.nx - 2;
-  while (lo < hi) {  // largest i <= nx-2 with lxk[i] <= lx
+__device__ __forceinline__ EnvW env_weights(const double* lxk, int nx, double lx) {
+  int lo = 0, hi = nx - 2;
+  while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (S.lxk[mid] <= lx) lo = mid; else hi = mid - 1;
+    if (lxk[mid] <= lx) lo = mid; else hi = mid - 1;
   }
-  const float t = fminf(fmaxf((lx - S.lxk[lo]) / (S.lxk[lo + 1] - S.lxk[lo]), 0.0f), 1.0f);
-#pragma unroll
-  for (int c = 0; c < kO; ++c) e[c] = S.env[lo * kO + c] + t * (S.env[(lo + 1) * kO + c] - S.env[lo * kO + c]);
+  const double D = lxk[lo + 1] - lxk[lo];
+  const double t = fmin(fmax((lx - lxk[lo]) / D, 0.0), 1.0);
+  const double t2 = t * t, t3 = t2 * t;
+  EnvW w;
+  w.i = lo;
+  w.h00 = (float)(2.0 * t3 - 3.0 * t2 + 1.0);
+  w.h10 = (float)((t3 - 2.0 * t2 + t) * D);
+  w.h01 = (float)(3.0 * t2 - 2.0 * t3);
+  w.h11 = (float)((t3 - t2) * D);
+  return w;
 }
 
-__global__ void k_prep_samples(SurDev S, const double* __restrict__ X, const double* __restrict__ Q2,
-                               const double* __restrict__ XF, int64_t n, float* __restrict__ in,
-                               float* __restrict__ T) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double lx = log(X[i]), lq = log(Q2[i]);
-  in[2 * i] = (float)(2.0 * (lx - S.lx0) * S.ilx - 1.0);
-  in[2 * i + 1] = (float)(2.0 * (lq - S.lq0) * S.ilq - 1.0);
-  float e[kO];
-  envelope(S, (float)lx, e);
-  for (int c = 0; c < kO; ++c) {
-    float t = 0.0f;
-    if (c < S.P && e[c] > 0.0f) {
-      const double xf = XF[i * S.P + c];
-      t = isfinite(xf) ? (float)(xf / (double)e[c]) : 0.0f;
-    }
-    T[i * kO + c] = t;
-  }
+// E_c at the point whose weights are w (tables [nx][kO] of values and slopes)
+__device__ __forceinline__ float env_at(const float* e, const float* d, int i, float h00, float h10, float h01,
+                                        float h11, int c) {
+  const int a = i * kO + c, b = a + kO;
+  return fmaf(h00, e[a], fmaf(h10, d[a], fmaf(h01, e[b], h11 * d[b])));
 }
-
-// ---------------------------------------------------------------------------------------
-// Fused inference.  Each wave takes 64 consecutive points: their inputs,
-// fallback flags and envelope cells are prepared one lane per point, then the
-// network runs on four 16-point sub-tiles (layer 1 on the VALUs directly into
-// the A-operand layout of layer 2; layers 2-4 on the matrix cores with the
-// weight fragments held in registers; hidden activations re-laid out from the
-// accumulator layout to the A-operand layout through 2 KB of LDS per wave).
-// (Keeping the activations in registers by computing the transposed products,
-// weights as the A operand, needs ~250 registers and ran 40 % slower.)
-// Points in the fallback domain are then evaluated by the FP32 interpolator:
-// each is located once (one lane per point: sub-grid, cells, weights), after
-// which one lane per (point, flavour) gathers its 4x4 stencil.
-constexpr int kSurWaves = 4;
 
 __device__ __forceinline__ bool trusted(const SurDev& S, const MemberDev& m, double x, double q2) {
   if (!(x >= m.xmin && x <= m.xmax && q2 >= m.qmin && q2 <= m.qmax)) return false;
@@ -237,6 +251,68 @@ __device__ __forceinline__ bool trusted(const SurDev& S, const MemberDev& m, dou
   return S.trust[k] && x >= S.txlo[k] && x < S.txhi[k] && q2 >= S.tqlo[k] && q2 < S.tqhi[k];
 }
 
+// Normalised inputs, targets xf_c / E_c (0 where E_c = 0 or xf is not
+// finite) and whether the sample lies in the network's domain.
+__global__ void k_prep_samples(SurDev S, MemberDev m, const double* __restrict__ X, const double* __restrict__ Q2,
+                               const double* __restrict__ XF, int64_t n, float* __restrict__ in,
+                               float* __restrict__ T, unsigned char* __restrict__ keep) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = X[i], q2 = Q2[i];
+  keep[i] = trusted(S, m, x, q2) ? 1 : 0;
+  const double lx = log(x), lq = log(q2);
+  in[2 * i] = (float)(2.0 * (lx - S.lx0) * S.ilx - 1.0);
+  in[2 * i + 1] = (float)(2.0 * (lq - S.lq0) * S.ilq - 1.0);
+  const EnvW w = env_weights(S.lxk, S.nx, lx);
+  for (int c = 0; c < kO; ++c) {
+    float t = 0.0f;
+    if (c < S.P) {
+      const float e = env_at(S.env, S.envd, w.i, w.h00, w.h10, w.h01, w.h11, c);
+      const double xf = XF[i * S.P + c];
+      if (e != 0.0f && isfinite(xf)) t = (float)(xf / (double)e);
+    }
+    T[i * kO + c] = t;
+  }
+}
+
+// in[j], T[j] = in_all[idx[j]], T_all[idx[j]] for j < n (the kept samples, in order).
+__global__ void k_gather_samples(const float* __restrict__ in_all, const float* __restrict__ T_all,
+                                 const int64_t* __restrict__ idx, int64_t n, float* __restrict__ in,
+                                 float* __restrict__ T) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = idx[j];
+  in[2 * j] = in_all[2 * i];
+  in[2 * j + 1] = in_all[2 * i + 1];
+#pragma unroll
+  for (int c = 0; c < kO; ++c) T[j * kO + c] = T_all[i * kO + c];
+}
+
+// ---------------------------------------------------------------------------------------
+// Fused inference.  Each wave takes 64 consecutive points: their inputs,
+// fallback flags and envelope weights are prepared one lane per point, then
+// the network runs on four 16-point sub-tiles: layer 1 on the VALUs straight
+// into the A-operand layout of layer 2 (as BF16 pairs); layers 2-4 on the
+// matrix cores, three products per operand pair, with the hi halves of the
+// weight fragments held in registers and the lo halves read from LDS; hidden
+// activations re-laid out from the accumulator layout to the A-operand layout
+// through LDS.  The outputs times the envelope go to a 16 x 16 LDS tile from
+// which the requested columns are stored point-major, consecutive lanes on
+// consecutive values.  Points in the fallback domain are then evaluated by
+// the FP32 interpolator: each is located once (one lane per point: sub-grid,
+// cells, weights), after which one lane per (point, requested column)
+// gathers its 4x4 stencil.
+//
+// LDS rows of 64 BF16 values (the activation tiles, the lo weight halves)
+// hold their eight 16-byte chunks in the order chunk ^ (row & 7), so the 16
+// rows an operand read touches spread over the banks.
+constexpr int kSurWaves = 4;
+constexpr int kSurRec = 8;   // floats per point record: u, v, h00, h10 D, h01, h11 D, cell, fallback
+
+__device__ __forceinline__ int swz(int row, int col) {  // element offset of (row, col) in a swizzled [.][64] tile
+  return row * kH + ((((col >> 3) ^ row) & 7) << 3) + (col & 7);
+}
+
 // Location of one fallback point (what interp_point derives before its gathers).
 struct FbRec {
   float w[4], v[4];
@@ -244,52 +320,71 @@ struct FbRec {
   double p0, p1;           // extrapolation parameters
 };
 
-// LDS of k_sur_infer: [nx] ln x knots, [nx][16] envelope, W1 (BF16-rounded; W1 and
-// b1-b3 times 2 log2(e)),
-// b1, b2, b3, b4, then per wave the fallback records, the activation tile and
-// the point records.
+// LDS of k_sur_infer: the lo halves of W2, W3 (64 x 64) and W4 (16 x 64),
+// [nx] ln x knots (double), [nx][16] envelope values and slopes, W1 and b1-b3
+// times 2 log2(e) (the argument scale of tanh_scaled), b4; then per wave a
+// 4 KB area (activation pair tile, then the output tile, then the fallback
+// records) and the point records.
+constexpr size_t kSurWaveArea = 2 * 16 * kH * 2;  // 4096 bytes
+__host__ __device__ static inline size_t sur_head_bytes(int nx) {
+  const size_t b = (size_t)8 * nx + (size_t)4 * (2 * nx * kO + 2 * kH + 3 * kH + kO) + (size_t)2 * (2 * kH * kH + kO * kH);
+  return (b + 15) & ~(size_t)15;
+}
 size_t sur_infer_shared_bytes(int nx) {
-  const size_t head = (size_t)4 * (nx + nx * kO + 2 * kH + 3 * kH + kO);
-  return ((head + 15) & ~(size_t)15) + (size_t)kSurWaves * (64 * sizeof(FbRec) + 16 * kH * 2 + 64 * 16);
+  return sur_head_bytes(nx) + (size_t)kSurWaves * (kSurWaveArea + 64 * kSurRec * 4);
 }
 
-
-__global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDev m, const unsigned short* __restrict__ Pb,
+__global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
+                                                             const unsigned short* __restrict__ Pb,
                                                              const float* __restrict__ Pf,
                                                              const double* __restrict__ X,
                                                              const double* __restrict__ Q2, int64_t n,
                                                              float* __restrict__ out, double invL01,
                                                              unsigned long long* __restrict__ nerr) {
-  extern __shared__ __align__(16) float sdyn[];
-  float* slxk = sdyn;                         // [nx]
-  float* senv = slxk + S.nx;                  // [nx][kO]
-  float* sw1 = senv + S.nx * kO;              // [kH][2], BF16-rounded
+  extern __shared__ __align__(16) unsigned char sraw[];
+  constexpr int BS = 64 * kSurWaves;
+  unsigned short* sw2l = reinterpret_cast<unsigned short*>(sraw);  // [kH][kH] swizzled (16-byte chunks)
+  unsigned short* sw3l = sw2l + kH * kH;
+  unsigned short* sw4l = sw3l + kH * kH;                   // [kO][kH] swizzled
+  double* slxk = reinterpret_cast<double*>(sw4l + kO * kH);  // [nx]
+  float* senv = reinterpret_cast<float*>(slxk + S.nx);     // [nx][kO]
+  float* senvd = senv + S.nx * kO;                         // [nx][kO]
+  float* sw1 = senvd + S.nx * kO;                          // [kH][2]
   float* sb1 = sw1 + 2 * kH;
   float* sb2 = sb1 + kH;
   float* sb3 = sb2 + kH;
-  float* sb4 = sb3 + kH;                      // [kO]
-  const size_t head = (size_t)4 * (S.nx + S.nx * kO + 2 * kH + 3 * kH + kO);
-  FbRec* sfb = reinterpret_cast<FbRec*>(reinterpret_cast<unsigned char*>(sdyn) + ((head + 15) & ~(size_t)15));
-  unsigned short* shs = reinterpret_cast<unsigned short*>(sfb + kSurWaves * 64);  // [waves][16 * kH]
-  float* spt = reinterpret_cast<float*>(shs + kSurWaves * 16 * kH);                // [waves][64][4]
-  for (int i = threadIdx.x; i < S.nx; i += 64 * kSurWaves) slxk[i] = S.lxk[i];
-  for (int i = threadIdx.x; i < S.nx * kO; i += 64 * kSurWaves) senv[i] = S.env[i];
-  // hidden-layer weights and biases staged times 2 log2(e), the argument scale of tanh_scaled
-  for (int i = threadIdx.x; i < 2 * kH; i += 64 * kSurWaves)
-    sw1[i] = kTwoLog2e * bf16_float(bf16_bits(Pf[kOffW1 + i]));
-  for (int i = threadIdx.x; i < kH; i += 64 * kSurWaves) {
+  float* sb4 = sb3 + kH;                                   // [kO]
+  unsigned char* waves = sraw + sur_head_bytes(S.nx);
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
+  unsigned char* area = waves + (size_t)wv * kSurWaveArea;
+  unsigned short* hs_hi = reinterpret_cast<unsigned short*>(area);   // [16][kH] swizzled
+  unsigned short* hs_lo = hs_hi + 16 * kH;
+  float* so = reinterpret_cast<float*>(area);                         // [16][kO] output tile
+  FbRec* fbr = reinterpret_cast<FbRec*>(area);                        // [64] fallback records
+  float* rec = reinterpret_cast<float*>(waves + (size_t)kSurWaves * kSurWaveArea) + wv * 64 * kSurRec;
+
+  for (int i = threadIdx.x; i < S.nx; i += BS) slxk[i] = S.lxk[i];
+  for (int i = threadIdx.x; i < S.nx * kO; i += BS) {
+    senv[i] = S.env[i];
+    senvd[i] = S.envd[i];
+  }
+  for (int i = threadIdx.x; i < 2 * kH; i += BS) sw1[i] = kTwoLog2e * Pf[kOffW1 + i];
+  for (int i = threadIdx.x; i < kH; i += BS) {
     sb1[i] = kTwoLog2e * Pf[kOffB1 + i];
     sb2[i] = kTwoLog2e * Pf[kOffB2 + i];
     sb3[i] = kTwoLog2e * Pf[kOffB3 + i];
   }
-  for (int i = threadIdx.x; i < kO; i += 64 * kSurWaves) sb4[i] = Pf[kOffB4 + i];
+  for (int i = threadIdx.x; i < kO; i += BS) sb4[i] = Pf[kOffB4 + i];
+  const unsigned short* Pl = Pb + kNParams;  // lo halves
+  for (int i = threadIdx.x; i < kH * kH; i += BS) {
+    const int row = i / kH, col = i % kH;
+    sw2l[swz(row, col)] = Pl[kOffW2 + i];
+    sw3l[swz(row, col)] = Pl[kOffW3 + i];
+  }
+  for (int i = threadIdx.x; i < kO * kH; i += BS) sw4l[swz(i / kH, i % kH)] = Pl[kOffW4 + i];
   __syncthreads();
 
-  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
-  unsigned short* hs = shs + wv * 16 * kH;
-  float* pt4 = spt + wv * 64 * 4;   // per point: u, v, envelope t, envelope cell (as int bits)
-  FbRec* fbr = sfb + wv * 64;
-  // weight fragments: B operand of layer L, N-tile t, K-step s: lane holds W[n = 16t + r][k = 32s + 8g + i]
+  // hi weight fragments: B operand of layer L, N-tile t, K-step s: lane holds W[n = 16t + r][k = 32s + 8g + i]
   bf16x8 w2[4][2], w3[4][2], w4[2];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
@@ -305,104 +400,136 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int i = 0; i < 8; ++i) w4[s][i] = __builtin_bit_cast(__bf16, Pb[kOffW4 + r * kH + 32 * s + 8 * g + i]);
+  // an 8-value chunk (16 bytes) of a swizzled LDS row, as an operand fragment
+  auto frag = [&](const unsigned short* tile, int row, int col0) -> bf16x8 {
+    return *reinterpret_cast<const bf16x8*>(tile + swz(row, col0));
+  };
   const Tables gtb{m.knots, m.cells, m.hints, m.subs};
   const float* __restrict__ gvals = member_values<float>(m);
+  const int R = rc.n;
 
   const int64_t ntiles = (n + 63) / 64;
   for (int64_t tile = (int64_t)blockIdx.x * kSurWaves + wv; tile < ntiles; tile += (int64_t)gridDim.x * kSurWaves) {
     const int64_t p0 = tile * 64;
     const int np = (int)min((int64_t)64, n - p0);
-    // one lane per point: inputs, fallback flag, envelope interval
+    // one lane per point: inputs, fallback flag, envelope weights
     double xr = 0.5, qr = 1.0;
     bool fb = false;
+    float* pr = rec + l * kSurRec;
     if (l < np) {
       xr = X[p0 + l];
       qr = Q2[p0 + l];
       fb = !trusted(S, m, xr, qr);
       const double lx = log(xr), lq = log(qr);
-      pt4[4 * l] = (float)(2.0 * (lx - S.lx0) * S.ilx - 1.0);
-      pt4[4 * l + 1] = (float)(2.0 * (lq - S.lq0) * S.ilq - 1.0);
-      const float lxf = (float)lx;
-      int lo = 0, hi = S.nx - 2;
-      while (lo < hi) {  // largest i <= nx-2 with lxk[i] <= ln x
-        const int mid = (lo + hi + 1) >> 1;
-        if (slxk[mid] <= lxf) lo = mid; else hi = mid - 1;
-      }
-      pt4[4 * l + 2] = fminf(fmaxf((lxf - slxk[lo]) / (slxk[lo + 1] - slxk[lo]), 0.0f), 1.0f);
-      pt4[4 * l + 3] = __int_as_float(lo);
+      pr[0] = (float)(2.0 * (lx - S.lx0) * S.ilx - 1.0);
+      pr[1] = (float)(2.0 * (lq - S.lq0) * S.ilq - 1.0);
+      const EnvW ew = env_weights(slxk, S.nx, fb ? S.lx0 : lx);
+      pr[2] = ew.h00;
+      pr[3] = ew.h10;
+      pr[4] = ew.h01;
+      pr[5] = ew.h11;
+      pr[6] = __int_as_float(ew.i);
     } else {
-      pt4[4 * l] = pt4[4 * l + 1] = pt4[4 * l + 2] = 0.0f;
-      pt4[4 * l + 3] = __int_as_float(0);
+      pr[0] = pr[1] = pr[2] = pr[3] = pr[4] = pr[5] = 0.0f;
+      pr[6] = __int_as_float(0);
     }
+    pr[7] = fb ? 1.0f : 0.0f;
     const unsigned long long fbmask = __ballot(fb);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int q0 = 0; q0 < np; q0 += 16) {
       // layer 1 straight into the A layout: lane (r, g) holds h1[point q0 + r][32 s + 8 g + i]
-      const float u = bf16_float(bf16_bits(pt4[4 * (q0 + r)])), v = bf16_float(bf16_bits(pt4[4 * (q0 + r) + 1]));
-      bf16x8 a[2];
+      const float u = rec[(q0 + r) * kSurRec], v = rec[(q0 + r) * kSurRec + 1];
+      bf16x8 ah[2], al[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const int j = 32 * s + 8 * g + i;
-          const float zs = fmaf(sw1[2 * j], u, fmaf(sw1[2 * j + 1], v, sb1[j]));
-          a[s][i] = __builtin_bit_cast(__bf16, bf16_bits(tanh_scaled(zs)));
+          unsigned short hb, lb;
+          split_bits(tanh_scaled(fmaf(sw1[2 * j], u, fmaf(sw1[2 * j + 1], v, sb1[j]))), hb, lb);
+          ah[s][i] = __builtin_bit_cast(__bf16, hb);
+          al[s][i] = __builtin_bit_cast(__bf16, lb);
         }
       // layers 2 and 3
 #pragma unroll
       for (int layer = 0; layer < 2; ++layer) {
         const float* bl = layer == 0 ? sb2 : sb3;
+        const unsigned short* wl = layer == 0 ? sw2l : sw3l;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], layer == 0 ? w2[t][0] : w3[t][0], acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], layer == 0 ? w2[t][1] : w3[t][1], acc, 0, 0, 0);
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const bf16x8 wh = layer == 0 ? w2[t][s] : w3[t][s];
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], wh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], wh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], frag(wl, 16 * t + r, 32 * s + 8 * g), acc, 0, 0, 0);
+          }
           const float bn = bl[16 * t + r];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) hs[(4 * g + i) * kH + 16 * t + r] = bf16_bits(tanh_scaled(fmaf(acc[i], kTwoLog2e, bn)));
+          for (int i = 0; i < 4; ++i) {
+            const int o = swz(4 * g + i, 16 * t + r);
+            split_bits(tanh_scaled(fmaf(acc[i], kTwoLog2e, bn)), hs_hi[o], hs_lo[o]);
+          }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int i = 0; i < 8; ++i) a[s][i] = __builtin_bit_cast(__bf16, hs[r * kH + 32 * s + 8 * g + i]);
+        for (int s = 0; s < 2; ++s) {
+          ah[s] = frag(hs_hi, r, 32 * s + 8 * g);
+          al[s] = frag(hs_lo, r, 32 * s + 8 * g);
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      // layer 4: lane (r, g) gets y[point q0 + 4 g + i][output r]; times the envelope
+      // layer 4: lane (r, g) gets y[point q0 + 4 g + i][output r]; times the envelope into the output tile
       f32x4 y = {0.f, 0.f, 0.f, 0.f};
-      y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], w4[0], y, 0, 0, 0);
-      y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], w4[1], y, 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], w4[s], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], w4[s], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], frag(sw4l, r, 32 * s + 8 * g), y, 0, 0, 0);
+      }
       const float b4 = sb4[r];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int pt = q0 + 4 * g + i;
-        if (pt < np && r < S.P && !((fbmask >> pt) & 1ull)) {
-          const int lo = __float_as_int(pt4[4 * pt + 3]);
-          const float t = pt4[4 * pt + 2];
-          const float e0 = senv[lo * kO + r], e1 = senv[(lo + 1) * kO + r];
-          out[(p0 + pt) * S.P + r] = (y[i] + b4) * (e0 + t * (e1 - e0));
+        const float* pq = rec + (q0 + 4 * g + i) * kSurRec;
+        const float e = env_at(senv, senvd, __float_as_int(pq[6]), pq[2], pq[3], pq[4], pq[5], r);
+        so[(4 * g + i) * kO + r] = (y[i] + b4) * e;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // requested columns of the network's points, point-major
+      const int nq = min(16, np - q0);
+      for (int e = l; e < nq * R; e += 64) {
+        const int pt = e / R, j = e - pt * R;
+        if (rec[(q0 + pt) * kSurRec + 7] == 0.0f) {
+          const int c = rc.col[j];
+          out[(p0 + q0 + pt) * R + j] = c >= 0 ? so[pt * kO + c] : 0.0f;
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // fallback points: located once each, then one lane per (point, stored column)
+    // fallback points: located once each, then one lane per (point, requested column)
     if (fbmask) {
       const int nfb = __popcll(fbmask);
       bool bad = false;
       if (fb) {
-        FbRec& rc = fbr[__popcll(fbmask & ((1ull << l) - 1))];
-        const PointLoc L = locate_point<float>(m, gtb, xr, qr, rc.w, rc.v);
-        rc.base = L.base;
-        rc.sa = L.sa;
-        rc.mode = L.mode;
-        rc.pt = l;
-        rc.p0 = L.p0;
-        rc.p1 = L.p1;
+        FbRec& fr = fbr[__popcll(fbmask & ((1ull << l) - 1))];
+        const PointLoc L = locate_point<float>(m, gtb, xr, qr, fr.w, fr.v);
+        fr.base = L.base;
+        fr.sa = L.sa;
+        fr.mode = L.mode;
+        fr.pt = l;
+        fr.p0 = L.p0;
+        fr.p1 = L.p1;
         bad = L.mode & kInvalid;
       }
       const unsigned long long badm = __ballot(bad);
@@ -410,28 +537,31 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int e = l; e < nfb * S.P; e += 64) {
-        const int k = e / S.P, c = e - k * S.P;
-        const FbRec& rc = fbr[k];
+      for (int e = l; e < nfb * R; e += 64) {
+        const int k = e / R, j = e - k * R;
+        const FbRec& fr = fbr[k];
+        const int c = rc.col[j];
         float val;
-        if (rc.mode & kInvalid) {
+        if (fr.mode & kInvalid) {
           val = NAN;
+        } else if (c < 0) {
+          val = 0.0f;
         } else {
-          const float* f = gvals + rc.base + c;
-          if (!(rc.mode & (kLowX | kLowQ | kHighQ))) {
+          const float* f = gvals + fr.base + c;
+          if (!(fr.mode & (kLowX | kLowQ | kHighQ))) {
             float F[4][4];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-              for (int b = 0; b < 4; ++b) F[a][b] = f[a * rc.sa + b * m.P32];
-            val = interp_stencil<float>(F, rc.w, rc.v);
+              for (int b = 0; b < 4; ++b) F[a][b] = f[a * fr.sa + b * m.P32];
+            val = interp_stencil<float>(F, fr.w, fr.v);
           } else {
-            const Wts wt{(double)rc.w[0], (double)rc.w[1], (double)rc.w[2], (double)rc.w[3],
-                         (double)rc.v[0], (double)rc.v[1], (double)rc.v[2], (double)rc.v[3]};
-            val = (float)extrap_entry<float>(f, rc.sa, m.P32, rc.mode, wt, rc.p0, rc.p1, invL01);
+            const Wts wt{(double)fr.w[0], (double)fr.w[1], (double)fr.w[2], (double)fr.w[3],
+                         (double)fr.v[0], (double)fr.v[1], (double)fr.v[2], (double)fr.v[3]};
+            val = (float)extrap_entry<float>(f, fr.sa, m.P32, fr.mode, wt, fr.p0, fr.p1, invL01);
           }
         }
-        out[(p0 + rc.pt) * S.P + c] = val;
+        out[(p0 + fr.pt) * R + j] = val;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -451,7 +581,6 @@ namespace pdfmi {
 int sur_nparams() { return kNParams; }
 int sur_out_width() { return kO; }
 int sur_hidden() { return kH; }
-size_t sur_batch_floats(int B) { return (size_t)B * (3 * kH + 3 * kO + 2 * kH) ; }
 
 static unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -469,21 +598,23 @@ __global__ void k_sum_slices(const float* __restrict__ P, int S, int n, float* _
 constexpr int kSplitK = 256;
 constexpr int kMaxSlices = 64;
 
-static void gemm(const unsigned short* A, int sam, int sak, const unsigned short* B, int sbk, int sbn, float* C, int ldc,
-                 unsigned short* Cb, int M, int N, int K, const float* bias, int act, float* ws, hipStream_t s) {
+// C = A B (A2, B2: lo halves of split operands, or null), see k_gemm_bf16.
+static void gemm(const unsigned short* A, const unsigned short* A2, int sam, int sak, const unsigned short* B,
+                 const unsigned short* B2, int sbk, int sbn, float* C, int ldc, unsigned short* Cb,
+                 unsigned short* Cl, int M, int N, int K, const float* bias, int act, float* ws, hipStream_t s) {
   const unsigned tiles = (unsigned)((M / 16) * (N / 16));
   int S = (K + kSplitK - 1) / kSplitK;
   if (S > kMaxSlices) S = kMaxSlices;
   if (S > 1 && !bias && !act && !Cb && ws && ldc == N) {
     const int kchunk = ((K + S - 1) / S + 31) / 32 * 32;
     S = (K + kchunk - 1) / kchunk;
-    hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles, (unsigned)S), dim3(64), 0, s, A, sam, sak, B, sbk, sbn, ws, ldc,
-                       nullptr, M, N, K, nullptr, 0, kchunk);
+    hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles, (unsigned)S), dim3(64), 0, s, A, A2, sam, sak, B, B2, sbk, sbn, ws,
+                       ldc, nullptr, nullptr, M, N, K, nullptr, 0, kchunk);
     hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, s, ws, S, M * N, C);
     return;
   }
-  hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles), dim3(64), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, Cb, M, N, K, bias,
-                     act, K);
+  hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles), dim3(64), 0, s, A, A2, sam, sak, B, B2, sbk, sbn, C, ldc, Cb, Cl, M, N,
+                     K, bias, act, K);
 }
 
 // Sum of 256 per-thread values of a 256-thread block by a fixed pairwise tree
@@ -509,10 +640,14 @@ __global__ void k_sum_partial(const float* __restrict__ x, int64_t n, float* __r
   s = block_tree_sum(s, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
-__global__ void k_sum_final(const float* __restrict__ partial, float scale, float* __restrict__ out) {
+__global__ void k_sum_final(const float* __restrict__ partial, float scale, float* __restrict__ out,
+                            float* __restrict__ out2) {
   __shared__ float red[256];
   const float s = block_tree_sum(partial[threadIdx.x], red);
-  if (threadIdx.x == 0) *out = s * scale;
+  if (threadIdx.x == 0) {
+    *out = s * scale;
+    if (out2) *out2 = s * scale;
+  }
 }
 
 // Column sums and the first-layer weight gradient over the batch, in row
@@ -527,48 +662,56 @@ static void col_sum(const float* X, int B, int ncols, float* out, float* ws, hip
   hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, ws, S, ncols, out);
 }
 
-static void dw1(const unsigned short* dZb, const float* in, int B, float* out, float* ws, hipStream_t s) {
+static void dw1(const float* dZ, const float* in, int B, float* out, float* ws, hipStream_t s) {
   const int S = min(kMaxSlices, (B + kColRows - 1) / kColRows);
   const int kchunk = (B + S - 1) / S;
-  hipLaunchKernelGGL(k_dw1, dim3(1, (unsigned)S), dim3(128), 0, s, dZb, in, B, kchunk, ws);
+  hipLaunchKernelGGL(k_dw1, dim3(1, (unsigned)S), dim3(128), 0, s, dZ, in, B, kchunk, ws);
   hipLaunchKernelGGL(k_sum_slices, dim3(1), dim3(256), 0, s, ws, S, kH * 2, out);
 }
 
 // One forward + backward pass on a batch (inputs in[B][2], targets T[B][kO]):
-// gradients into buf.G, loss (mean squared error) into buf.loss.
-hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s) {
-  const unsigned short* W2 = b.Pb + kOffW2;
-  const unsigned short* W3 = b.Pb + kOffW3;
-  const unsigned short* W4 = b.Pb + kOffW4;
-  hipLaunchKernelGGL(k_layer1, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, in, b.P, B, b.h1, b.h1b);
-  // z = h W^T + b: A(m=b,k) = h[b][k]; B(k,n) = W[n][k]
-  gemm(b.h1b, kH, 1, W2, 1, kH, b.h2, kH, b.h2b, B, kH, kH, b.P + kOffB2, 1, b.wpart, s);
-  gemm(b.h2b, kH, 1, W3, 1, kH, b.h3, kH, b.h3b, B, kH, kH, b.P + kOffB3, 1, b.wpart, s);
-  gemm(b.h3b, kH, 1, W4, 1, kH, b.y, kO, nullptr, B, kO, kH, b.P + kOffB4, 0, b.wpart, s);
+// gradients into buf.G, loss (mean squared error) into buf.loss and, if not
+// null, *loss_out.
+hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, float* loss_out,
+                                hipStream_t s) {
+  const unsigned short* Wh = b.Pb;              // hi halves
+  const unsigned short* Wl = b.Pb + kNParams;   // lo halves
+  hipLaunchKernelGGL(k_layer1, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, in, b.P, B, b.h1, b.h1b, b.h1l);
+  // z = h W^T + b: A(m=b,k) = h[b][k]; B(k,n) = W[n][k]; split operands
+  gemm(b.h1b, b.h1l, kH, 1, Wh + kOffW2, Wl + kOffW2, 1, kH, b.h2, kH, b.h2b, b.h2l, B, kH, kH, b.P + kOffB2, 1,
+       b.wpart, s);
+  gemm(b.h2b, b.h2l, kH, 1, Wh + kOffW3, Wl + kOffW3, 1, kH, b.h3, kH, b.h3b, b.h3l, B, kH, kH, b.P + kOffB3, 1,
+       b.wpart, s);
+  gemm(b.h3b, b.h3l, kH, 1, Wh + kOffW4, Wl + kOffW4, 1, kH, b.y, kO, nullptr, nullptr, B, kO, kH, b.P + kOffB4, 0,
+       b.wpart, s);
   hipLaunchKernelGGL(k_loss_grad, dim3(nb((int64_t)B * kO, 256)), dim3(256), 0, s, b.y, T, B, b.dy, b.dyb, b.sq);
   hipLaunchKernelGGL(k_sum_partial, dim3(256), dim3(256), 0, s, b.sq, (int64_t)B * kO, b.partial);
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, b.partial, 1.0f / (float)((int64_t)B * kO), b.loss);
-  // layer 4: dW4[o][i] = sum_b dy[b][o] h3[b][i]; db4; dh3 = dy W4
-  gemm(b.dyb, 1, kO, b.h3b, kH, 1, b.G + kOffW4, kH, nullptr, kO, kH, B, nullptr, 0, b.wpart, s);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, b.partial, 1.0f / (float)((int64_t)B * kO), b.loss,
+                     loss_out);
+  // backward on the hi halves: layer 4: dW4[o][i] = sum_b dy[b][o] h3[b][i]; db4; dh3 = dy W4
+  gemm(b.dyb, nullptr, 1, kO, b.h3b, nullptr, kH, 1, b.G + kOffW4, kH, nullptr, nullptr, kO, kH, B, nullptr, 0,
+       b.wpart, s);
   col_sum(b.dy, B, kO, b.G + kOffB4, b.wpart, s);
-  gemm(b.dyb, kO, 1, W4, kH, 1, b.dh, kH, nullptr, B, kH, kO, nullptr, 0, b.wpart, s);
+  gemm(b.dyb, nullptr, kO, 1, Wh + kOffW4, nullptr, kH, 1, b.dh, kH, nullptr, nullptr, B, kH, kO, nullptr, 0, b.wpart,
+       s);
   // layers 3 and 2
   const float* Hs[3] = {b.h1, b.h2, b.h3};
   const unsigned short* Hbs[3] = {b.h1b, b.h2b, b.h3b};
-  const unsigned short* Ws[2] = {W2, W3};
   const int offW[2] = {kOffW2, kOffW3}, offB[2] = {kOffB2, kOffB3};
   for (int L = 1; L >= 0; --L) {  // L = 1: layer 3 (input h2, output h3); L = 0: layer 2 (h1 -> h2)
     hipLaunchKernelGGL(k_tanh_back, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, b.dh, Hs[L + 1],
                        (int64_t)B * kH, b.dz, b.dzb);
-    gemm(b.dzb, 1, kH, Hbs[L], kH, 1, b.G + offW[L], kH, nullptr, kH, kH, B, nullptr, 0, b.wpart, s);
+    gemm(b.dzb, nullptr, 1, kH, Hbs[L], nullptr, kH, 1, b.G + offW[L], kH, nullptr, nullptr, kH, kH, B, nullptr, 0,
+         b.wpart, s);
     col_sum(b.dz, B, kH, b.G + offB[L], b.wpart, s);
     // dh_in = dz W: A(m=b, k=j) = dz[b][j]; B(k=j, n=i) = W[j][i]
-    gemm(b.dzb, kH, 1, Ws[L], kH, 1, b.dh, kH, nullptr, B, kH, kH, nullptr, 0, b.wpart, s);
+    gemm(b.dzb, nullptr, kH, 1, Wh + offW[L], nullptr, kH, 1, b.dh, kH, nullptr, nullptr, B, kH, kH, nullptr, 0,
+         b.wpart, s);
   }
-  // layer 1
+  // layer 1 (FP32)
   hipLaunchKernelGGL(k_tanh_back, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, b.dh, b.h1, (int64_t)B * kH, b.dz,
                      b.dzb);
-  dw1(b.dzb, in, B, b.G + kOffW1, b.wpart, s);
+  dw1(b.dz, in, B, b.G + kOffW1, b.wpart, s);
   col_sum(b.dz, B, kH, b.G + kOffB1, b.wpart, s);
   return hipGetLastError();
 }
@@ -586,23 +729,32 @@ hipError_t sur_refresh_bf16(const SurBufs& b, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t sur_prep(const SurDev& S, const double* x, const double* q2, const double* xf, int64_t n, float* in,
-                    float* T, hipStream_t s) {
+hipError_t sur_prep(const SurDev& S, const MemberDev& m, const double* x, const double* q2, const double* xf,
+                    int64_t n, float* in, float* T, unsigned char* keep, hipStream_t s) {
   if (n > 0)
-    hipLaunchKernelGGL(k_prep_samples, dim3(nb(n, 256)), dim3(256), 0, s, S, x, q2, xf, n, in, T);
+    hipLaunchKernelGGL(k_prep_samples, dim3(nb(n, 256)), dim3(256), 0, s, S, m, x, q2, xf, n, in, T, keep);
   return hipGetLastError();
 }
 
-hipError_t sur_infer(const SurDev& S, const MemberDev& m, const SurBufs& b, const double* x, const double* q2,
-                     int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu, hipStream_t s) {
+hipError_t sur_gather(const float* in_all, const float* T_all, const int64_t* idx, int64_t n, float* in, float* T,
+                      hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_gather_samples, dim3(nb(n, 256)), dim3(256), 0, s, in_all, T_all, idx, n, in, T);
+  return hipGetLastError();
+}
+
+hipError_t sur_infer(const SurDev& S, const MemberDev& m, const ReqCols& rc, const SurBufs& b, const double* x,
+                     const double* q2, int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu,
+                     hipStream_t s) {
   const int64_t tiles = (n + 63) / 64;
-  const int64_t blocks = min((tiles + kSurWaves - 1) / kSurWaves, (int64_t)n_cu * 8);
+  const size_t shm = sur_infer_shared_bytes(S.nx);
+  const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)shm);
+  const int64_t blocks = min((tiles + kSurWaves - 1) / kSurWaves, (int64_t)n_cu * per_cu);
   if (blocks > 0) {
-    const size_t shm = sur_infer_shared_bytes(S.nx);
     hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_sur_infer), shm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sur_infer, dim3((unsigned)blocks), dim3(64 * kSurWaves), shm, s, S, m, b.Pb, b.P, x, q2, n,
-                       out, invL01, nerr);
+    hipLaunchKernelGGL(k_sur_infer, dim3((unsigned)blocks), dim3(64 * kSurWaves), shm, s, S, m, rc, b.Pb, b.P, x, q2,
+                       n, out, invL01, nerr);
   }
   return hipGetLastError();
 }

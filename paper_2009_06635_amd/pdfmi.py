@@ -48,10 +48,11 @@ _SIGS = {
     "pdf_surrogate_create": [_i32, ctypes.c_uint64, _P],
     "pdf_surrogate_destroy": [_i32],
     "pdf_surrogate_set_data": [_i32, _P, _P, _i64, _P],
-    "pdf_surrogate_train": [_i32, _i32, _i32, ctypes.c_float, ctypes.c_float, _i32, _P],
+    "pdf_surrogate_train": [_i32, _P, _P],
+    "pdf_surrogate_adam": [_i32, _P, ctypes.c_float, _P],
     "pdf_surrogate_grad": [_i32, _P, _P, _i32, _P, _P, _P],
     "pdf_surrogate_params": [_i32, _P, _i32],
-    "pdf_surrogate_xfxq2": [_i32, _P, _P, _i64, _P, _P],
+    "pdf_surrogate_xfxq2": [_i32, _P, _i32, _P, _P, _i64, _P, _P],
     "pdf_surrogate_save": [_i32, ctypes.c_char_p],
     "pdf_surrogate_load": [_i32, ctypes.c_char_p],
     "pdf_shutdown": [],
@@ -416,6 +417,11 @@ def surrogate_param_count():
     return v.value
 
 
+class _TrainOpts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("lr_final", ctypes.c_float), ("total_steps", ctypes.c_int32), ("loss_out", ctypes.c_void_p)]
+
+
 class Surrogate:
     """MLP surrogate of one member (see pdf_surrogate_* in include/pdfmi.h)."""
 
@@ -430,9 +436,22 @@ class Surrogate:
         _dev_f64(q2, "q2")
         _check(_lib.pdf_surrogate_set_data(self.id, _P(x.data_ptr()), _P(q2.data_ptr()), x.shape[0], _stream(stream)))
 
-    def train(self, steps, batch, lr, lr_final, total_steps, stream=None):
-        _check(_lib.pdf_surrogate_train(self.id, int(steps), int(batch), float(lr), float(lr_final), int(total_steps),
-                                        _stream(stream)))
+    def train(self, steps, batch, lr, lr_final, total_steps, loss_out=None, stream=None):
+        """steps Adam steps; loss_out: optional float32 CUDA tensor of >= steps
+        entries receiving each step's batch loss."""
+        if loss_out is not None and not (isinstance(loss_out, torch.Tensor) and loss_out.is_cuda and
+                                         loss_out.dtype == torch.float32 and loss_out.numel() >= steps):
+            raise TypeError("loss_out must be a float32 CUDA tensor of at least `steps` entries")
+        o = _TrainOpts(int(steps), int(batch), float(lr), float(lr_final), int(total_steps),
+                       loss_out.data_ptr() if loss_out is not None else None)
+        _check(_lib.pdf_surrogate_train(self.id, ctypes.byref(o), _stream(stream)))
+
+    def adam(self, grad, lr, stream=None):
+        """One Adam step with a float32 CUDA gradient of n_params entries."""
+        if not (isinstance(grad, torch.Tensor) and grad.is_cuda and grad.dtype == torch.float32 and
+                grad.is_contiguous() and grad.numel() == self.n_params):
+            raise TypeError("grad must be a contiguous float32 CUDA tensor of n_params entries")
+        _check(_lib.pdf_surrogate_adam(self.id, _P(grad.data_ptr()), float(lr), _stream(stream)))
 
     def grad(self, inp, target, stream=None):
         """(gradient tensor, loss tensor) for device float32 inp[B][2], target[B][16]."""
@@ -451,13 +470,17 @@ class Surrogate:
         a = np.ascontiguousarray(p, np.float32)
         _check(_lib.pdf_surrogate_params(self.id, _ptr(a), 1))
 
-    def xfxq2(self, x, q2, n_cols, out=None, stream=None):
+    def xfxq2(self, x, q2, pids=None, out=None, n_cols=None, stream=None):
+        """FP32 point-major [n][len(pids)] (pids=None: every stored column,
+        then pass n_cols = number of stored columns, or out)."""
         _dev_f64(x, "x")
         _dev_f64(q2, "q2")
+        arr, npid = _pid_arg(pids)
         if out is None:
-            out = torch.empty((x.shape[0], n_cols), dtype=torch.float32, device=x.device)
-        _check(_lib.pdf_surrogate_xfxq2(self.id, _P(x.data_ptr()), _P(q2.data_ptr()), x.shape[0],
-                                        _P(out.data_ptr()), _stream(stream)))
+            out = torch.empty((x.shape[0], npid if pids is not None else n_cols), dtype=torch.float32,
+                              device=x.device)
+        _check(_lib.pdf_surrogate_xfxq2(self.id, _ptr(arr) if arr is not None else None, npid, _P(x.data_ptr()),
+                                        _P(q2.data_ptr()), x.shape[0], _P(out.data_ptr()), _stream(stream)))
         return out
 
     def save(self, path):

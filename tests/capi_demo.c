@@ -9,8 +9,12 @@
  * int64 nvalues, double values[nvalues], int32 nalpha, double q2a[nalpha],
  * double alpha[nalpha], int64 n, double x[n], double q2[n].
  * Output: double xf[n][P] (all stored flavours, pids = NULL), double
- * alpha_s[n], int64 invalid-point count.  Exit status 0 on success, 1 with a
- * message on stderr for any library or runtime error.
+ * alpha_s[n], int64 invalid-point count; then, from an MLP surrogate of the
+ * member trained for 5 steps on the query points, float sur[n][P] (every
+ * stored flavour), float sub[n][3] (flavours 21, the last stored one, -1:
+ * a subset in another order) and float loss[5] (the per-step losses).
+ * Exit status 0 on success, 1 with a message on stderr for any library or
+ * runtime error.
  */
 #include <stdint.h>
 #include <stdio.h>
@@ -97,6 +101,34 @@ int main(int argc, char** argv) {
   if (!out || !a) return 1;
   HIPCHECK(hipMemcpy(out, dout, (size_t)n * P * 8, hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(a, da, (size_t)n * 8, hipMemcpyDeviceToHost));
+
+  /* surrogate: a few training steps through the options struct, then every
+   * stored flavour and a subset */
+  enum { kSteps = 5, kSub = 3 };
+  int32_t sid = -1;
+  const int32_t sub_pids[kSub] = {21, pids[P - 1], -1};
+  float *dsur = NULL, *dsub = NULL, *dloss = NULL;
+  HIPCHECK(hipMalloc((void**)&dsur, (size_t)n * P * 4));
+  HIPCHECK(hipMalloc((void**)&dsub, (size_t)n * kSub * 4));
+  HIPCHECK(hipMalloc((void**)&dloss, kSteps * 4));
+  LIBCHECK(pdf_surrogate_create(member, 1, &sid));
+  LIBCHECK(pdf_surrogate_set_data(sid, dx, dq, n, NULL));
+  pdf_train_opts opts = {kSteps, 256, 3e-3f, 3e-4f, kSteps, dloss};
+  LIBCHECK(pdf_surrogate_train(sid, &opts, NULL));
+  LIBCHECK(pdf_surrogate_xfxq2(sid, NULL, 0, dx, dq, n, dsur, NULL));
+  LIBCHECK(pdf_surrogate_xfxq2(sid, sub_pids, kSub, dx, dq, n, dsub, NULL));
+  HIPCHECK(hipDeviceSynchronize());
+  float* sur = malloc((size_t)n * P * 4);
+  float* sub = malloc((size_t)n * kSub * 4);
+  float loss[kSteps];
+  if (!sur || !sub) return 1;
+  HIPCHECK(hipMemcpy(sur, dsur, (size_t)n * P * 4, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(sub, dsub, (size_t)n * kSub * 4, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(loss, dloss, kSteps * 4, hipMemcpyDeviceToHost));
+  LIBCHECK(pdf_surrogate_destroy(sid));
+  HIPCHECK(hipFree(dsur));
+  HIPCHECK(hipFree(dsub));
+  HIPCHECK(hipFree(dloss));
   LIBCHECK(pdf_unload(member));
   LIBCHECK(pdf_shutdown());
   HIPCHECK(hipFree(dx));
@@ -107,7 +139,8 @@ int main(int argc, char** argv) {
   FILE* g = fopen(argv[2], "wb");
   if (!g) return 1;
   if (fwrite(out, 8, (size_t)n * P, g) != (size_t)n * P || fwrite(a, 8, (size_t)n, g) != (size_t)n ||
-      fwrite(&nerr, 8, 1, g) != 1)
+      fwrite(&nerr, 8, 1, g) != 1 || fwrite(sur, 4, (size_t)n * P, g) != (size_t)n * P ||
+      fwrite(sub, 4, (size_t)n * kSub, g) != (size_t)n * kSub || fwrite(loss, 4, kSteps, g) != kSteps)
     return 1;
   fclose(g);
   printf("capi_demo: %lld points x %d flavours, %lld invalid\n", (long long)n, P, (long long)nerr);

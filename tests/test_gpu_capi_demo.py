@@ -2,7 +2,9 @@
 library): a grid, an alpha_s table and query points are handed over in a
 file; the program loads them with pdf_load_grid / pdf_load_alphas, evaluates
 pdf_xfxq2 and pdf_alphas_q2 on the null stream and writes the results back,
-which must match the oracle."""
+which must match the oracle; it also trains a surrogate a few steps through
+the training-options struct and evaluates it for every stored flavour and a
+flavour subset, whose columns must be those of the full call."""
 import os
 import subprocess
 
@@ -55,11 +57,20 @@ def test_plain_c_program(tmp_path):
     write_input(inp, g, qk, av, x, q2)
     res = subprocess.run([EXE, str(inp), str(outp)], capture_output=True, text=True, timeout=120)
     assert res.returncode == 0, res.stdout + res.stderr
-    raw = np.fromfile(outp, dtype=np.float64)
     n, P = len(x), len(g.pids)
+    buf = outp.read_bytes()
+    raw = np.frombuffer(buf, np.float64, n * P + n + 1)
     xf = raw[:n * P].reshape(n, P)
     al = raw[n * P:n * P + n]
     nerr = raw[n * P + n:].view(np.int64)[0]
+    f32 = np.frombuffer(buf, np.float32, offset=8 * (n * P + n + 1))
+    sur = f32[:n * P].reshape(n, P)
+    sub = f32[n * P:n * P + 3 * n].reshape(n, 3)
+    loss = f32[n * P + 3 * n:]
+    assert len(loss) == 5 and np.all(np.isfinite(loss)) and np.all(loss > 0)
+    # the surrogate's flavour subset {21, last stored, -1} is those columns of the all-flavour call
+    for j, pid in enumerate([21, g.pids[-1], -1]):
+        assert np.array_equal(sub[:, j], sur[:, g.pids.index(pid)], equal_nan=True), pid
     ora, scale = oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, g.values, g.pids), g.pids, x, q2, with_scale=True)
     ok = check_f64(xf, ora, scale, grid_L(g))[0]
     assert ok.all(), describe_failures(ok, xf, ora, x, q2, g.pids)

@@ -1,8 +1,11 @@
-"""MLP surrogate: matrix-core gradients vs the FP64 oracle on the same BF16
-operands, fused inference vs the oracle forward, fallback points vs the
-interpolator, deterministic checkpoint/resume, and what a trained network
-gains over the interpolator (speed at its measured error)."""
+"""MLP surrogate against the oracle: matrix-core gradients vs the FP64 oracle
+on the kernels' operands, single Adam steps and a 50-step training
+trajectory vs the oracle's optimiser, fused inference vs the oracle forward
+on every network point, fallback points vs the interpolator, flavour
+selection, deterministic checkpoint/resume, and what a trained network gains
+(its error against the FP64 oracle and its speed against the interpolators)."""
 import os
+import struct
 import time
 
 import numpy as np
@@ -33,15 +36,31 @@ def cfg1():
     pdfmi.unload(m)
 
 
-def envelope(g, x):
-    """Independent restatement of the output envelope: largest |xf_c| over the
-    Q^2 knots at each x knot, linear in ln x."""
+def envelope(g, x, with_scale=False):
+    """Independent restatement of the output envelope: at each x knot the grid
+    value of largest magnitude over all Q^2 knots (signed), joined by a cubic
+    Hermite in ln x with finite-difference slopes (mean of the adjacent
+    secants, one secant at the ends).  with_scale also returns the sum of the
+    magnitudes of its four terms (the size of its rounding)."""
     xk = g.xknots[0]
-    E = np.max(np.abs(np.concatenate(g.values, axis=1)), axis=1)   # [nx][P]
+    V = np.concatenate(g.values, axis=1)                  # [nx][all Q^2 knots][P]
+    jm = np.argmax(np.abs(V), axis=1)
+    e = np.take_along_axis(V, jm[:, None, :], axis=1)[:, 0, :]
+    t = np.log(xk)
+    sec = (e[1:] - e[:-1]) / np.diff(t)[:, None]
+    d = np.empty_like(e)
+    d[0], d[-1] = sec[0], sec[-1]
+    d[1:-1] = 0.5 * (sec[:-1] + sec[1:])
     lx = np.log(x)
-    i = np.clip(np.searchsorted(np.log(xk), lx, side="right") - 1, 0, len(xk) - 2)
-    t = np.clip((lx - np.log(xk[i])) / (np.log(xk[i + 1]) - np.log(xk[i])), 0, 1)
-    return E[i] + t[:, None] * (E[i + 1] - E[i])
+    i = np.clip(np.searchsorted(t, lx, side="right") - 1, 0, len(xk) - 2)
+    D = (t[i + 1] - t[i])[:, None]
+    u = np.clip((lx - t[i])[:, None] / D, 0, 1)
+    h = [2 * u**3 - 3 * u**2 + 1, (u**3 - 2 * u**2 + u) * D, 3 * u**2 - 2 * u**3, (u**3 - u**2) * D]
+    terms = [h[0] * e[i], h[1] * d[i], h[2] * e[i + 1], h[3] * d[i + 1]]
+    E = terms[0] + terms[1] + terms[2] + terms[3]
+    if with_scale:
+        return E, sum(np.abs(tm) for tm in terms)
+    return E
 
 
 def normalise(g, x, q2):
@@ -57,6 +76,57 @@ def trusted_mask(g, x, q2):
     return (x >= xk[1]) & (x < xk[-2]) & (q2 >= qk[1]) & (q2 < qk[-2])
 
 
+def training_set(g, x, q2):
+    """What set_data keeps, restated: network-domain points in order, inputs
+    and targets xf / E from the FP64 oracle."""
+    tm = trusted_mask(g, x, q2)
+    x, q2 = x[tm], q2[tm]
+    ora = oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, g.values, g.pids), g.pids, x, q2)
+    E = envelope(g, x)
+    T = np.zeros((len(x), 16))
+    T[:, :len(g.pids)] = np.where(E != 0, ora / np.where(E != 0, E, 1), 0)
+    return normalise(g, x, q2).astype(np.float64), T.astype(np.float32).astype(np.float64)
+
+
+def read_checkpoint(path):
+    """(step, params, first moments, second moments) of a surrogate checkpoint
+    (magic, version, count, step, then 3 x count FP32 values)."""
+    raw = path.read_bytes()
+    n, = struct.unpack_from("<I", raw, 12)
+    step, = struct.unpack_from("<q", raw, 16)
+    a = np.frombuffer(raw, np.float32, 3 * n, 24).astype(np.float64)
+    return step, a[:n], a[n:2 * n], a[2 * n:]
+
+
+# Tolerances.  Backward: both sides round the back-propagated signals to BF16,
+# and a signal near a rounding tie can round the other way between the FP32
+# kernel and the FP64 oracle (one BF16 ulp, 2^-8 relative, in a few entries
+# per tensor); the per-tensor norm stays well within 1e-3.  Forward: a split
+# pair holds its value to 2^-17 relative, and the kernel splits FP32
+# activations where the oracle splits FP64 ones, so the lo halves can differ
+# by one BF16 ulp of lo (2^-17 of the activation) in any activation; the
+# output can then move by up to 2^-17 times its first-order sensitivity to
+# relative changes of all hidden activations, S = sum |dy/dh| |h| (computed
+# from the oracle's weights below), plus FP32 rounding.
+GRAD_RTOL = 1e-3
+
+
+def sensitivity(p, inp):
+    """S[b][o] = sum over the hidden activations h of |d y_o / d h| |h| (FP64)."""
+    P = mlp.unpack(p)
+    h1 = np.tanh(inp @ P["W1"].T + P["b1"])
+    h2 = np.tanh(h1 @ P["W2"].T + P["b2"])
+    h3 = np.tanh(h2 @ P["W3"].T + P["b3"])
+    J3 = np.broadcast_to(P["W4"][None], (len(inp),) + P["W4"].shape)
+    J2 = np.einsum("bok,kj->boj", J3 * (1 - h3 * h3)[:, None, :], P["W3"])
+    J1 = np.einsum("bok,kj->boj", J2 * (1 - h2 * h2)[:, None, :], P["W2"])
+    return sum((np.abs(J) * np.abs(h)[:, None, :]).sum(2) for J, h in ((J3, h3), (J2, h2), (J1, h1)))
+
+
+def forward_bound(p, inp, y):
+    return 2.0 ** -17 * sensitivity(p, inp) + 1e-5 * (np.abs(y) + 0.05)
+
+
 @pytest.mark.parametrize("B", [16, 48, 256, 4096])
 def test_gradients_match_oracle(cfg1, B):
     g, m = cfg1
@@ -69,13 +139,74 @@ def test_gradients_match_oracle(cfg1, B):
         tgt = rng.normal(0, 1, (B, 16)).astype(np.float32)
         gr, loss = s.grad(dev(inp, np.float32), dev(tgt, np.float32))
         gr = gr.cpu().numpy().astype(np.float64)
-        lo, go, _ = mlp.loss_grad_bf16(p.astype(np.float64), inp.astype(np.float64), tgt.astype(np.float64))
-        assert abs(loss.item() - lo) <= 1e-3 * lo
+        lo, go, _ = mlp.loss_grad_device(p.astype(np.float64), inp.astype(np.float64), tgt.astype(np.float64))
+        assert abs(loss.item() - lo) <= 1e-5 * lo
         d = mlp.unpack(gr)
         do = mlp.unpack(go)
-        for k in do:
-            err = np.linalg.norm(d[k] - do[k]) / (np.linalg.norm(do[k]) + 1e-30)
-            assert err < 5e-3, (k, err)
+        errs = {k: np.linalg.norm(d[k] - do[k]) / (np.linalg.norm(do[k]) + 1e-30) for k in do}
+        print("B=%d gradient relative errors per tensor: %s" % (B, {k: "%.1e" % v for k, v in errs.items()}))
+        for k, err in errs.items():
+            assert err < GRAD_RTOL, (k, err)
+    finally:
+        s.destroy()
+
+
+def test_adam_steps_match_oracle(cfg1, tmp_path):
+    """k_adam against the oracle's Adam: three steps with given gradients from
+    zero moments; parameters and both moments after each step."""
+    g, m = cfg1
+    s = pdfmi.Surrogate(m, seed=21)
+    try:
+        p = s.params().astype(np.float64)
+        mo, vo = np.zeros(mlp.NPARAMS), np.zeros(mlp.NPARAMS)
+        mscale = np.zeros(mlp.NPARAMS)   # sum of the magnitudes of the first moment's terms
+        rng = np.random.default_rng(21)
+        for t, lr in enumerate((3e-3, 1e-3, 2e-3), start=1):
+            gr = (rng.normal(0, 1, mlp.NPARAMS) * 10.0 ** rng.uniform(-6, 0, mlp.NPARAMS)).astype(np.float32)
+            s.adam(dev(gr, np.float32), lr)
+            p, mo, vo = mlp.adam_step(p, mo, vo, gr.astype(np.float64), float(np.float32(lr)), t)
+            mscale = 0.9 * mscale + 0.1 * np.abs(gr)
+            path = tmp_path / ("adam%d.ckpt" % t)
+            s.save(path)
+            step, pg, mg, vg = read_checkpoint(path)
+            assert step == t
+            # FP32 arithmetic: a few ulps of the parameter plus 1e-4 of the updates (FP32 holds
+            # 1 - 0.999 to 1.3e-5, and a first moment that cancels between steps loses digits)
+            assert np.all(np.abs(pg - p) <= 4 * np.spacing(np.float32(np.abs(p))).astype(np.float64) + 1e-4 * lr * t)
+            # FP32 holds 1 - 0.9 to 2.4e-7: relative to the terms' magnitudes (the moment may cancel)
+            assert np.all(np.abs(mg - mo) <= 1e-6 * mscale + 1e-30)
+            # FP32 holds 1 - 0.999 to 1.3e-5 relative: the second moment's coefficient carries that
+            assert np.all(np.abs(vg - vo) <= 5e-5 * np.abs(vo) + 1e-38)
+    finally:
+        s.destroy()
+
+
+def test_training_trajectory_matches_oracle(cfg1):
+    """50 training steps on the GPU (set_data, train with per-step losses)
+    against the oracle's train() from the same initial parameters on the same
+    training set and batches."""
+    g, m = cfg1
+    x, q2 = synth.config1_queries(n=8192, seed=35)
+    s = pdfmi.Surrogate(m, seed=23)
+    try:
+        p0 = s.params().astype(np.float64)
+        s.set_data(dev(x), dev(q2))
+        steps, B = 50, 256
+        loss = torch.zeros(steps, dtype=torch.float32, device=DEV)
+        s.train(steps, B, 3e-3, 3e-4, steps, loss_out=loss)
+        pg = s.params().astype(np.float64)
+        lg = loss.cpu().numpy().astype(np.float64)
+        inp, T = training_set(g, x, q2)
+        nb = len(inp) // B
+        batches = [(inp[(t % nb) * B:(t % nb + 1) * B], T[(t % nb) * B:(t % nb + 1) * B]) for t in range(steps)]
+        po, _, _, lo = mlp.train(p0, batches, float(np.float32(3e-3)), float(np.float32(3e-4)), steps)
+        lrel = np.abs(lg - lo) / lo
+        prel = np.linalg.norm(pg - po) / np.linalg.norm(po - p0)
+        print("trajectory: loss %.3e -> %.3e (oracle %.3e -> %.3e), max loss rel diff %.2e, "
+              "parameter diff / distance travelled %.2e" % (lg[0], lg[-1], lo[0], lo[-1], lrel.max(), prel))
+        assert lo[-1] < 0.5 * lo[0]
+        assert np.all(lrel <= 1e-2)
+        assert prel <= 1e-2
     finally:
         s.destroy()
 
@@ -88,19 +219,15 @@ def test_inference_matches_oracle_forward(cfg1):
         p = rng.normal(0, 0.3, mlp.NPARAMS).astype(np.float32)
         s.set_params(p)
         x, q2 = synth.config1_queries(n=4000, seed=31)
-        out = s.xfxq2(dev(x), dev(q2), len(g.pids)).cpu().numpy().astype(np.float64)
+        out = s.xfxq2(dev(x), dev(q2), n_cols=len(g.pids)).cpu().numpy().astype(np.float64)
         tm = trusted_mask(g, x, q2)
-        y = mlp.forward_bf16(p.astype(np.float64), normalise(g, x, q2).astype(np.float64))[:, :len(g.pids)]
-        want = y * envelope(g, x)
-        E = envelope(g, x)
-        err = np.abs(out - want)[tm]
-        scale = ((np.abs(y) + 0.05) * E)[tm]
-        # the kernel rounds FP32 pre-activations to BF16 where the oracle rounds FP64 ones: an
-        # activation near a BF16 rounding boundary can round the other way (one BF16 ulp, 2^-8
-        # relative) and move a few outputs by more than the typical bound -- rare, and bounded
-        ratio = err / scale
-        assert np.mean(ratio <= 2e-2) >= 0.995, np.mean(ratio <= 2e-2)
-        assert np.all(ratio <= 1e-1), ratio.max()
+        inp = normalise(g, x, q2).astype(np.float64)
+        y = mlp.forward_device(p.astype(np.float64), inp)[:, :len(g.pids)]
+        E, Es = envelope(g, x, with_scale=True)
+        bound = forward_bound(p.astype(np.float64), inp, mlp.forward_device(p.astype(np.float64), inp))[:, :len(g.pids)]
+        ratio = (np.abs(out - y * E) / (bound * Es))[tm]
+        print("inference vs oracle forward: max error / bound = %.3f" % ratio.max())
+        assert np.all(ratio <= 1.0), ratio.max()
     finally:
         s.destroy()
 
@@ -113,7 +240,7 @@ def test_fallback_points_use_interpolator(cfg1):
         x[:5] = [1e-8, 0.5, 0.999, 1e-6, -1.0]
         q2[:5] = [10.0, 1e9, 10.0, 1.0, 10.0]
         tm = trusted_mask(g, x, q2)
-        out = s.xfxq2(dev(x), dev(q2), len(g.pids)).cpu().numpy()
+        out = s.xfxq2(dev(x), dev(q2), n_cols=len(g.pids)).cpu().numpy()
         ref = pdfmi.xfxq2_f32(m, g.pids, dev(x), dev(q2)).cpu().numpy()
         assert (~tm).sum() > 100
         a, b = out[~tm], ref[~tm]
@@ -164,14 +291,18 @@ def _rel_err(out, ora, floor=1e-8):
 
 
 def test_trained_surrogate_gain(cfg1):
-    """Train on 2e6 interpolator samples; report the error against the FP64
-    oracle and the speed against the FP32 interpolator on 1e6 points."""
+    """What the trained network gains over the interpolator: trained on 2e6
+    interpolator samples (the benchmark's recipe), its values on 1e6 points
+    are held to the relative error bar of the surrogate (median <= 1e-3 and at
+    least 90 % of the values within 1e-3 of the FP64 oracle, eq. (1) where
+    |xf| > 1e-8), and its speed against the FP64 and FP32 interpolators is
+    measured and reported."""
     g, m = cfg1
     xt, qt = synth.config1_queries(n=2_000_000, seed=40)
     s = pdfmi.Surrogate(m, seed=3)
     try:
         s.set_data(dev(xt), dev(qt))
-        steps = int(os.environ.get("PDFMI_SUR_STEPS", "4000"))
+        steps = int(os.environ.get("PDFMI_SUR_STEPS", "20000"))
         t0 = time.perf_counter()
         s.train(steps, 4096, 3e-3, 3e-5, steps)
         torch.cuda.synchronize()
@@ -179,11 +310,13 @@ def test_trained_surrogate_gain(cfg1):
         x, q2 = synth.config1_queries(n=1_000_000, seed=41)
         xd, qd = dev(x), dev(q2)
         P = len(g.pids)
-        out = s.xfxq2(xd, qd, P)
-        ref = torch.empty_like(out)
+        out = s.xfxq2(xd, qd, n_cols=P)
+        ref32 = torch.empty_like(out)
+        ref64 = torch.empty(out.shape, dtype=torch.float64, device=DEV)
         for _ in range(2):
-            s.xfxq2(xd, qd, P, out=out)
-            pdfmi.xfxq2_f32(m, g.pids, xd, qd, out=ref)
+            s.xfxq2(xd, qd, out=out)
+            pdfmi.xfxq2_f32(m, g.pids, xd, qd, out=ref32)
+            pdfmi.xfxq2(m, g.pids, xd, qd, out=ref64)
         torch.cuda.synchronize()
 
         def ktime(fn, reps=5):
@@ -195,20 +328,25 @@ def test_trained_surrogate_gain(cfg1):
             torch.cuda.synchronize()
             return e0.elapsed_time(e1) / reps
 
-        t_sur = ktime(lambda: s.xfxq2(xd, qd, P, out=out))
-        t_int = ktime(lambda: pdfmi.xfxq2_f32(m, g.pids, xd, qd, out=ref))
+        t_sur = ktime(lambda: s.xfxq2(xd, qd, out=out))
+        t_32 = ktime(lambda: pdfmi.xfxq2_f32(m, g.pids, xd, qd, out=ref32))
+        t_64 = ktime(lambda: pdfmi.xfxq2(m, g.pids, xd, qd, out=ref64))
         idx = np.random.default_rng(0).choice(len(x), 20000, replace=False)
         ora = oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, g.values, g.pids), g.pids, x[idx], q2[idx])
         o = out.cpu().numpy()[idx].astype(np.float64)
         tm = trusted_mask(g, x[idx], q2[idx])
         e_all = _rel_err(o, ora)
-        e_tr = _rel_err(o[tm], ora[tm])
-        print("surrogate: train %.2f s (%d steps); infer %.3f ms vs FP32 interpolator %.3f ms (gain %.2fx); "
-              "rel err (|xf|>1e-8) median %.2e p99 %.2e max %.2e, trusted region median %.2e; fallback %.1f%%"
-              % (ttrain, steps, t_sur, t_int, t_int / t_sur, np.median(e_all), np.percentile(e_all, 99),
-                 e_all.max(), np.median(e_tr), 100 * (1 - tm.mean())))
+        e_net = _rel_err(o[tm], ora[tm])
+        frac = float((e_all <= 1e-3).mean())
+        print("surrogate: train %.2f s (%d steps); infer %.3f ms vs FP64 interpolator %.3f ms (speed-up %.2fx), "
+              "FP32 interpolator %.3f ms (%.2fx); rel err vs the FP64 oracle (|xf|>1e-8) median %.2e p90 %.2e "
+              "p99 %.2e, %.3f within 1e-3; network points only: median %.2e; fallback %.1f%%"
+              % (ttrain, steps, t_sur, t_64, t_64 / t_sur, t_32, t_32 / t_sur, np.median(e_all),
+                 np.percentile(e_all, 90), np.percentile(e_all, 99), frac, np.median(e_net), 100 * (1 - tm.mean())))
         assert np.all(np.isfinite(o))
-        assert np.median(e_tr) < 5e-2
+        assert np.median(e_all) <= 1e-3
+        assert frac >= 0.9
+        assert t_sur > 0 and np.isfinite(t_64 / t_sur)
     finally:
         s.destroy()
 
@@ -225,7 +363,7 @@ def test_full_size_inference_sampled(cfg1):
         s.set_params(p)
         x, q2 = synth.config1_queries(n=10_000_000, seed=41)
         xd, qd = dev(x), dev(q2)
-        out = s.xfxq2(xd, qd, len(g.pids))
+        out = s.xfxq2(xd, qd, n_cols=len(g.pids))
         idx = np.concatenate([rng.choice(len(x), 20000, replace=False), [0, len(x) - 1]])
         idx_t = torch.from_numpy(idx).to(DEV)
         o = out[idx_t].cpu().numpy().astype(np.float64)
@@ -233,11 +371,44 @@ def test_full_size_inference_sampled(cfg1):
         xs, qs = x[idx], q2[idx]
         tm = trusted_mask(g, xs, qs)
         assert np.array_equal(o[~tm], ref[~tm].astype(np.float64))
-        y = mlp.forward_bf16(p.astype(np.float64), normalise(g, xs, qs).astype(np.float64))[:, :len(g.pids)]
-        E = envelope(g, xs)
-        ratio = (np.abs(o - y * E) / ((np.abs(y) + 0.05) * E))[tm]
-        assert np.mean(ratio <= 2e-2) >= 0.995, np.mean(ratio <= 2e-2)
-        assert np.all(ratio <= 1e-1), ratio.max()
+        inp = normalise(g, xs, qs).astype(np.float64)
+        yf = mlp.forward_device(p.astype(np.float64), inp)
+        y = yf[:, :len(g.pids)]
+        E, Es = envelope(g, xs, with_scale=True)
+        ratio = (np.abs(o - y * E) / (forward_bound(p.astype(np.float64), inp, yf)[:, :len(g.pids)] * Es))[tm]
+        assert np.all(ratio <= 1.0), ratio.max()
+    finally:
+        s.destroy()
+
+
+def test_flavour_selection(cfg1):
+    """pids select output columns: each requested flavour equals the
+    all-flavour call's column (network and fallback points alike), the gluon
+    alias 0 is 21, flavours the grid does not store (+-6) give 0, invalid ids
+    are refused, and invalid points give NaN in every requested column."""
+    g, m = cfg1
+    s = pdfmi.Surrogate(m, seed=13)
+    try:
+        s.set_params(np.random.default_rng(5).normal(0, 0.3, mlp.NPARAMS).astype(np.float32))
+        x, q2 = synth.config1_queries(n=3001, seed=36)
+        x[:4] = [1e-8, 0.5, -1.0, 0.3]
+        q2[:4] = [10.0, 1e9, 10.0, float("nan")]
+        xd, qd = dev(x), dev(q2)
+        full = s.xfxq2(xd, qd, n_cols=len(g.pids)).cpu().numpy()
+        for pids in ([21], [6, 2, -6, 0, 2], synth.PIDS_13, [-5, 5]):
+            out = s.xfxq2(xd, qd, pids).cpu().numpy()
+            assert out.shape == (len(x), len(pids))
+            for j, pid in enumerate(pids):
+                pid = 21 if pid == 0 else pid
+                if pid in g.pids:
+                    want = full[:, g.pids.index(pid)]
+                    assert np.array_equal(out[:, j], want, equal_nan=True), pid
+                else:
+                    assert np.all(out[[0, 1]][:, j] == 0.0) and np.all(out[4:, j] == 0.0), pid
+                    assert np.all(np.isnan(out[[2, 3]][:, j])), pid
+        with pytest.raises(pdfmi.PdfError) as ei:
+            s.xfxq2(xd, qd, [7])
+        assert ei.value.code == pdfmi.PDF_ERR_PID
     finally:
         s.destroy()
 
@@ -252,13 +423,13 @@ def test_surrogate_refuses_unloaded_member():
     try:
         x, q2 = synth.config1_queries(n=256, seed=3)
         xd, qd = dev(x), dev(q2)
-        s.xfxq2(xd, qd, len(g.pids))
+        s.xfxq2(xd, qd, n_cols=len(g.pids))
         torch.cuda.synchronize()
         pdfmi.unload(m)
         m2 = pdfmi.load_synth(g)
         try:
             assert m2 == m
-            for fn in (lambda: s.xfxq2(xd, qd, len(g.pids)), lambda: s.set_data(xd, qd)):
+            for fn in (lambda: s.xfxq2(xd, qd, n_cols=len(g.pids)), lambda: s.set_data(xd, qd)):
                 with pytest.raises(pdfmi.PdfError) as ei:
                     fn()
                 assert ei.value.code == pdfmi.PDF_ERR_MEMBER
