@@ -83,15 +83,18 @@ static double fd_slope(const double* t, const double* f, long st, int n, int j)
 }
 
 /* Cubic Hermite on cell i (knots i, i+1) at parameter u in [0,1]:
- * h00 f_i + h10 D d_i + h01 f_{i+1} + h11 D d_{i+1}, D = ln(t_{i+1}/t_i). */
+ * h00 f_i + h10 D d_i + h01 f_{i+1} + h11 D d_{i+1}, D = ln(t_{i+1}/t_i),
+ * with the basis h00 = 2u^3 - 3u^2 + 1, h10 = u^3 - 2u^2 + u,
+ * h01 = -2u^3 + 3u^2, h11 = u^3 - u^2 evaluated in factored form (v = 1 - u
+ * is exact, so each keeps its relative precision at both ends of the cell). */
 static double hermite_cell(const double* t, const double* f, long st, int n, int i, double u)
 {
     double D = log(t[i + 1] / t[i]);
-    double u2 = u * u, u3 = u2 * u;
-    double h00 = 2 * u3 - 3 * u2 + 1;
-    double h10 = u3 - 2 * u2 + u;
-    double h01 = -2 * u3 + 3 * u2;
-    double h11 = u3 - u2;
+    double v = 1.0 - u, u2 = u * u, v2 = v * v;
+    double h00 = v2 * (1 + 2 * u);
+    double h10 = u * v2;
+    double h01 = u2 * (3 - 2 * u);
+    double h11 = -u2 * v;
     return h00 * f[(long)i * st] + h10 * D * fd_slope(t, f, st, n, i)
          + h01 * f[(long)(i + 1) * st] + h11 * D * fd_slope(t, f, st, n, i + 1);
 }

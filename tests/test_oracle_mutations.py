@@ -20,9 +20,10 @@ PINS = {"oracle.c": os.path.join(ROOT, "tests", "test_oracle_pins.py"),
 
 # name -> (text in oracle.c, replacement)
 C_MUTATIONS = {
-    "hermite_h10_sign": ("double h10 = u3 - 2 * u2 + u;", "double h10 = u3 - 2 * u2 - u;"),
-    "hermite_h11_sign": ("double h11 = u3 - u2;", "double h11 = u2 - u3;"),
-    "hermite_h01_term": ("double h01 = -2 * u3 + 3 * u2;", "double h01 = -2 * u3 + 2 * u2;"),
+    "hermite_h10_sign": ("double h10 = u * v2;", "double h10 = -u * v2;"),
+    "hermite_h11_sign": ("double h11 = -u2 * v;", "double h11 = u2 * v;"),
+    "hermite_h01_term": ("double h01 = u2 * (3 - 2 * u);", "double h01 = u2 * (2 - 2 * u);"),
+    "hermite_h00_factor": ("double h00 = v2 * (1 + 2 * u);", "double h00 = v2 * (1 + u);"),
     "hermite_drops_width": ("+ h01 * f[(long)(i + 1) * st] + h11 * D * fd_slope(t, f, st, n, i + 1);",
                             "+ h01 * f[(long)(i + 1) * st] + h11 * fd_slope(t, f, st, n, i + 1);"),
     "interior_slope_one_sided": ("return 0.5 * (secant(t, f, st, j - 1) + secant(t, f, st, j));",
