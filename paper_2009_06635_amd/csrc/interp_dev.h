@@ -53,12 +53,17 @@ __device__ __forceinline__ Tables tables_at(const unsigned char* base, const Mem
 // knot i - d (d = 0 left edge, 1 interior, 2 right edge).
 template <typename T>
 __device__ __forceinline__ void stencil_weights(double u64, const CellCoef& c, int d, T out[4]) {
+  // the Hermite basis in factored form: 1 - u is exact, so every basis value
+  // keeps its relative precision near u = 0 and u = 1 (the expanded forms
+  // cancel there, leaving absolute errors of one ulp that the large weights
+  // of a cell next to a much narrower one magnify)
   const T u = (T)u64;
-  const T u2 = u * u;
-  const T h00 = ((T)2 * u - (T)3) * u2 + (T)1;
-  const T h10 = ((u - (T)2) * u + (T)1) * u;
+  const T w = (T)1 - u;
+  const T u2 = u * u, w2 = w * w;
+  const T h00 = w2 * ((T)1 + (T)2 * u);
+  const T h10 = u * w2;
   const T h01 = ((T)3 - (T)2 * u) * u2;
-  const T h11 = (u - (T)1) * u2;
+  const T h11 = -(w * u2);
   const bool L = c.hl >= 0.0, R = c.hr >= 0.0;
   const double am1 = L ? -c.hl : 0.0, a0 = L ? c.hl - 0.5 : -1.0, a1 = L ? 0.5 : 1.0;
   const double b0 = R ? -0.5 : -1.0, b1 = R ? 0.5 - c.hr : 1.0, b2 = R ? c.hr : 0.0;

@@ -226,13 +226,13 @@ __device__ __forceinline__ EnvW env_weights(const double* lxk, int nx, double lx
   }
   const double D = lxk[lo + 1] - lxk[lo];
   const double t = fmin(fmax((lx - lxk[lo]) / D, 0.0), 1.0);
-  const double t2 = t * t, t3 = t2 * t;
+  const double s = 1.0 - t, t2 = t * t, s2 = s * s;  // factored basis: no cancellation near t = 0, 1
   EnvW w;
   w.i = lo;
-  w.h00 = (float)(2.0 * t3 - 3.0 * t2 + 1.0);
-  w.h10 = (float)((t3 - 2.0 * t2 + t) * D);
-  w.h01 = (float)(3.0 * t2 - 2.0 * t3);
-  w.h11 = (float)((t3 - t2) * D);
+  w.h00 = (float)(s2 * (1.0 + 2.0 * t));
+  w.h10 = (float)(t * s2 * D);
+  w.h01 = (float)(t2 * (3.0 - 2.0 * t));
+  w.h11 = (float)(-(s * t2) * D);
   return w;
 }
 

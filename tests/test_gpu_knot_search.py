@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_2009_06635_amd import synth
-from tolerance import check_f64, describe_failures
+from tolerance import EPS64, check_f64, describe_failures
 
 pytestmark = pytest.mark.gpu
 
@@ -99,7 +99,8 @@ def queries(g, rng):
 
 
 def grid_L_conditioned(g, floor=1e-6):
-    """grid_L over the knot spacings the compared stencils use (>= floor in ln)."""
+    """grid_L over the knot spacings of at least `floor` in ln (the cells of
+    the well-conditioned stencils)."""
     inv = []
     for t in list(g.xknots) + list(g.q2knots):
         d = np.diff(np.log(t))
@@ -109,6 +110,7 @@ def grid_L_conditioned(g, floor=1e-6):
 
 
 def well_conditioned(g, k, ix, iq, floor=1e-6):
+    """Stencils whose knot spacings are all >= floor in ln."""
     res = np.ones(len(k), bool)
     for i in range(len(k)):
         if k[i] < 0:
@@ -119,6 +121,73 @@ def well_conditioned(g, k, ix, iq, floor=1e-6):
             if hi > lo and np.min(np.diff(t[lo:hi + 1])) < floor:
                 res[i] = False
     return res
+
+
+def data_sensitivity(g, x, q2, k, ix, iq, h=1e-6):
+    """W[i][j] = sum over the grid values f that point i can read of
+    |d F_ij / d f| |f|, the first-order sensitivity of the oracle's value to
+    relative changes of the grid values, by central differences (one value
+    at a time).  A point reads, in its sub-grid, x knots ix-1..ix+2 and Q^2
+    knots iq-1..iq+2, and extrapolation anchors at the first two x knots, the
+    first two Q^2 knots of sub-grid 0 and the last two of the last sub-grid;
+    windows one knot wider on each side are perturbed."""
+    W = np.zeros((len(x), len(g.pids)))
+    K = len(g.values)
+    touch = [set() for _ in range(K)]
+    for i in range(len(x)):
+        nx, nq = g.values[k[i]].shape[:2]
+        xs = set(range(max(ix[i] - 2, 0), min(ix[i] + 4, nx))) | set(range(min(4, nx)))
+        qs = set(range(max(iq[i] - 2, 0), min(iq[i] + 4, nq)))
+        touch[k[i]].update((a, b) for a in xs for b in qs)
+        touch[0].update((a, b) for a in range(min(4, g.values[0].shape[0])) for b in range(min(4, g.values[0].shape[1])))
+        nxl, nql = g.values[K - 1].shape[:2]
+        touch[K - 1].update((a, b) for a in xs if a < nxl for b in range(max(nql - 4, 0), nql))
+        touch[0].update((a, b) for a in xs if a < g.values[0].shape[0] for b in range(min(4, g.values[0].shape[1])))
+    for kk in range(K):
+        for (a, b) in sorted(touch[kk]):
+            for c in range(g.values[kk].shape[2]):
+                f = g.values[kk][a, b, c]
+                if f == 0.0:
+                    continue
+                F = []
+                for sgn in (1.0, -1.0):
+                    vals = [v.copy() for v in g.values]
+                    vals[kk][a, b, c] = f * (1.0 + sgn * h)
+                    F.append(oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, vals, g.pids), g.pids, x, q2))
+                W += np.abs(F[0] - F[1]) / (2.0 * h)
+    return W
+
+
+def coord_sensitivity(g, x, q2, h=1e-9):
+    """|d F / d ln x| (1 + |ln x|) + |d F / d ln Q^2| (1 + |ln Q^2|): rounding the
+    cell parameter u (a log, a ratio, a product with 1/Delta) moves the value by
+    about eps times this.  Central differences of the oracle where both
+    neighbours are valid points, else the one-sided difference."""
+    og = oracle.Grid(g.xknots, g.q2knots, g.values, g.pids)
+    F0 = oracle.xfxq2(og, g.pids, x, q2)
+    xmax = g.xknots[0][-1]
+    out = np.zeros_like(F0)
+    for which, coord in ((0, x), (1, q2)):
+        d = []
+        for sgn in (1.0, -1.0):
+            c = coord * (1.0 + sgn * h)
+            xs, qs = (c, q2) if which == 0 else (x, c)
+            F = oracle.xfxq2(og, g.pids, xs, qs)
+            ok = ((xs <= xmax) if which == 0 else np.ones(len(x), bool))[:, None] & np.isfinite(F)
+            d.append(np.where(ok, np.abs(F - F0) / h, 0.0))
+        out += np.maximum(d[0], d[1]) * (1.0 + np.abs(np.log(coord)))[:, None]
+    return out
+
+
+def cell_L(g, k, ix, iq, x, q2):
+    """(1 + |ln x|) / Delta_x + (1 + |ln Q^2|) / Delta_Q of each point's own cells."""
+    L = np.zeros(len(x))
+    for i in range(len(x)):
+        if k[i] < 0:
+            continue
+        tx, tq = np.log(g.xknots[k[i]]), np.log(g.q2knots[k[i]])
+        L[i] = (1 + abs(np.log(x[i]))) / (tx[ix[i] + 1] - tx[ix[i]]) + (1 + abs(np.log(q2[i]))) / (tq[iq[i] + 1] - tq[iq[i]])
+    return L
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
@@ -141,14 +210,35 @@ def test_knot_search_bit_exact(case, separate_x):
         out = pdfmi.xfxq2(m, g.pids, dev(x), dev(q2)).cpu().numpy()
         # clustered Q^2 knots make the low-Q^2 exponent overflow: both sides must agree on +-inf/NaN
         fin = np.isfinite(ora)
-        # values are compared where the stencil's knot spacings are not degenerate: with ln-spacings
-        # below 1e-6 the Hermite coefficients (ratios of spacings) lose digits in FP64 on both sides
-        # in different ways, beyond the R14 tolerance; indices above are bit-exact everywhere
-        well = well_conditioned(g, ok_, oix, oiq)
-        fin &= well[:, None]
         assert np.array_equal(np.isnan(out), np.isnan(ora))
         assert np.array_equal(out[np.isinf(ora)], ora[np.isinf(ora)])
+        # stencils with ln-spacings >= 1e-6: the R14 criterion (largest stencil value, L over those cells)
+        well = well_conditioned(g, ok_, oix, oiq)
         ok, _, _ = check_f64(out, ora, scale, grid_L_conditioned(g))
+        # stencils with a tinier spacing: the Hermite weights are ratios of neighbouring spacings (up to
+        # ~1e16 here) and cancel, and the slopes at the knots of such a cell are as large, so the rounding
+        # of either evaluation scales with the weighted stencil, sum |w f| (W: the value's first-order
+        # sensitivity to relative changes of the grid values), and with the value's sensitivity to its
+        # coordinates (C: a rounding of the cell parameter u is a relative change of x or Q^2 of about
+        # eps (1 + |ln|)), not with the largest stencil value; both from the oracle by central differences
+        ill = ~well & (ok_ >= 0)
+        if ill.any():
+            W = data_sensitivity(g, x[ill], q2[ill], ok_[ill], oix[ill], oiq[ill])
+            L = cell_L(g, ok_[ill], oix[ill], oiq[ill], x[ill], q2[ill])[:, None]
+            o, r = ora[ill], out[ill]
+            C = coord_sensitivity(g, x[ill], q2[ill])
+            bound = 1e-12 * np.abs(o) + 4 * EPS64 * (W + scale[ill] * (1.0 + L) + C)
+            ok_ill = (np.abs(r - o) <= bound) | ~np.isfinite(o)
+            fb = np.isfinite(o) & (bound > 0)
+            print("%s separate_x=%s: %d stencils with spacings < 1e-6 compared, max error / bound %.3g, "
+                  "max W / M %.3g" % (case, separate_x, ill.sum(), (np.abs(r - o)[fb] / bound[fb]).max(),
+                                      (W / np.maximum(scale[ill], 1e-300))[fb].max()))
+            ratio = np.where(fb, np.abs(r - o) / np.where(fb, bound, 1.0), 0.0)
+            for i, j in np.argwhere(ratio > 1.0)[np.argsort(-ratio[ratio > 1.0])][:6]:
+                print("  x=%r q2=%r region=%d pid %d: oracle %r gpu %r W %.3g M %.3g L %.3g C %.3g bound %.3g"
+                      % (x[ill][i], q2[ill][i], oreg[ill][i], g.pids[j], o[i, j], r[i, j], W[i, j], scale[ill][i, j],
+                         L[i, 0], C[i, j], bound[i, j]))
+            ok[ill] = ok_ill
         ok |= ~fin
         assert ok.all(), describe_failures(ok, out, ora, x, q2, g.pids)
     finally:

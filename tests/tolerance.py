@@ -25,7 +25,7 @@ def grid_L(grid):
     return float(np.max(inv[0::2]) + np.max(inv[1::2]))
 
 
-def check_f64(gpu, ora, scale, L, rtol=1e-12, c=8.0):
+def check_f64(gpu, ora, scale, L, rtol=1e-12, c=4.0):
     """Returns (ok mask, literal-pass fraction, max eq.(1) difference)."""
     gpu = np.asarray(gpu, np.float64)
     both_nan = np.isnan(gpu) & np.isnan(ora)
@@ -37,7 +37,7 @@ def check_f64(gpu, ora, scale, L, rtol=1e-12, c=8.0):
     return ok, float(lit.mean()), float(r.max()) if r.size else 0.0
 
 
-def check_f32(gpu, ora, scale, rtol=1e-5, floor=1e-8, c=8.0):
+def check_f32(gpu, ora, scale, rtol=1e-5, floor=1e-8, c=4.0):
     gpu = np.asarray(gpu, np.float64)
     both_nan = np.isnan(gpu) & np.isnan(ora)
     diff = np.abs(gpu - ora)
