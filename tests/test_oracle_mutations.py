@@ -53,6 +53,8 @@ C_MUTATIONS = {
     "invalid_x_above_xmax_accepted": ("|| !(q2 > 0.0) || x > xmax) return REG_INVALID;",
                                       "|| !(q2 > 0.0)) return REG_INVALID;"),
     "gluon_alias_dropped": ("if (pid == 0) pid = 21;", ""),
+    "scale_sums_stencil": ("if (m > M) M = m;", "M += m;"),
+    "scale_drops_continuation_weights": ("return fabs(e0) * f0.s + fabs(e1) * f1.s;", "return f0.s + f1.s;"),
     "alphas_upper_constant_wrong": ("if (v > q2k[nk - 1]) { out[i] = a[nk - 1]; continue; }",
                                     "if (v > q2k[nk - 1]) { out[i] = a[nk - 2]; continue; }"),
     "alphas_threshold_to_lower_segment": ("if (q2k[j] == q2k[j - 1] && q2k[j] <= v) s0 = j;",

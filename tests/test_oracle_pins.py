@@ -396,3 +396,80 @@ def test_alphas_segments_at_repeated_knots():
     o = oracle.alphas_q2(qk, a, q2)
     b = np.array([brute.alphas(qk, a, v) for v in q2])
     assert np.max(relerr(o, b)) < 1e-13
+
+
+# ---------------------------------------------------------------------------------------------
+# The error scale s that the oracle returns beside each value (the floor of every
+# parity criterion) against quantities computed without it: the largest stencil
+# magnitude, found here by searchsorted, and the value's first-order sensitivity
+# to relative changes of the grid values, found by central differences of the
+# oracle's values.  Too small an s would make the parity floors too tight; too
+# large an s would loosen every parity test silently.
+
+def _data_sensitivity(g, x, q2, h=1e-6):
+    W = np.zeros((len(x), len(g.pids)))
+    for k in range(len(g.values)):
+        for idx in np.ndindex(g.values[k].shape):
+            f = g.values[k][idx]
+            if f == 0.0:
+                continue
+            F = []
+            for sgn in (1.0, -1.0):
+                vals = [v.copy() for v in g.values]
+                vals[k][idx] = f * (1.0 + sgn * h)
+                F.append(oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, vals, g.pids), g.pids, x, q2))
+            W += np.abs(F[0] - F[1]) / (2.0 * h)
+    return W
+
+
+def _scale_grid(r, positive):
+    """Two sub-grids with log-uniform knots; smooth positive data (varying by less
+    than a factor 2 across any stencil) or signed random data."""
+    xk = np.exp(np.linspace(np.log(1e-4), 0.0, 6))
+    q0 = np.exp(np.linspace(np.log(1.5), np.log(6.0), 5))
+    q1 = np.exp(np.linspace(np.log(6.0), np.log(200.0), 6))
+    q1[0] = q0[-1]
+    vals = []
+    for qk in (q0, q1):
+        lx, lq = np.log(xk)[:, None, None], np.log(qk)[None, :, None]
+        if positive:
+            a = r.uniform(-0.15, 0.15, (1, 1, 2))
+            b = r.uniform(-0.05, 0.05, (1, 1, 2))
+            vals.append(np.exp(a * lx + b * lq + 0.05 * np.sin(lx + lq)))
+        else:
+            vals.append(r.uniform(-1.0, 2.0, (len(xk), len(qk), 2)))
+    return synth.SynthGrid([xk, xk], [q0, q1], vals, [21, 2])
+
+
+@pytest.mark.parametrize("positive", [False, True])
+def test_error_scale_is_stencil_magnitude_inside(positive):
+    r = rng(31 + positive)
+    g = _scale_grid(r, positive)
+    x, q2 = _queries_everywhere(r, g)
+    out, s = oracle.xfxq2(ogrid(g), g.pids, x, q2, with_scale=True)
+    inside = (x >= g.xknots[0][0]) & (q2 >= g.q2knots[0][0]) & (q2 <= g.q2knots[-1][-1])
+    assert inside.sum() > 50
+    for i in np.flatnonzero(inside):
+        k = 1 if q2[i] >= g.q2knots[1][0] else 0
+        xk, qk = g.xknots[k], g.q2knots[k]
+        ix = min(max(np.searchsorted(xk, x[i], side="right") - 1, 0), len(xk) - 2)
+        iq = min(max(np.searchsorted(qk, q2[i], side="right") - 1, 0), len(qk) - 2)
+        win = g.values[k][max(ix - 1, 0):ix + 3, max(iq - 1, 0):iq + 3, :]
+        assert np.array_equal(s[i], np.max(np.abs(win), axis=(0, 1))), (x[i], q2[i])
+
+
+@pytest.mark.parametrize("positive", [False, True])
+def test_error_scale_bounds_data_sensitivity(positive):
+    """Every valid value, extrapolations included: its sensitivity to relative
+    changes of the grid values is at most 2 s (log-uniform knots: the weights of
+    a 4 x 4 stencil have sum |w| <= 1.25^2); on smooth positive data s is also at
+    most 3 times that sensitivity (not inflated)."""
+    r = rng(41 + positive)
+    g = _scale_grid(r, positive)
+    x, q2 = _queries_everywhere(r, g, n_rand=200)
+    out, s = oracle.xfxq2(ogrid(g), g.pids, x, q2, with_scale=True)
+    ok = np.isfinite(out) & (s > 0)
+    W = _data_sensitivity(g, x, q2)
+    assert np.all(W[ok] <= 2.0 * s[ok] * (1 + 1e-9)), np.max(W[ok] / s[ok])
+    if positive:
+        assert np.all(s[ok] <= 3.0 * W[ok]), np.max(s[ok] / W[ok])
