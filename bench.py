@@ -44,6 +44,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# L2 read bandwidth of the chip: 8 XCDs x 16 channels x 128 B per clock at 2.4 GHz
+L2_PEAK_GBS = 8 * 16 * 128 * 2.4
 
 
 def kernel_source_sha():
@@ -77,7 +79,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--n", type=int, default=10_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=10_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="skip the variants")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -212,16 +214,54 @@ def main():
         "roofline": {"bound": "hbm", "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach64 / HBM_PEAK_GBS, "traffic": measured_traffic("xfxq2_f64"),
                      "kernel": "k_xfxq2<double> with alpha_s output (pdf_xfxq2_alphas)", "kernel_ms": k64,
-                     "algorithmic_bytes_per_launch": bytes64},
+                     "algorithmic_bytes_per_launch": bytes64,
+                     # the ceiling that binds: every point gathers its 4 x 4 stencil, 16 grid rows of
+                     # 16 FP64 columns = 16 x 128-byte L2 lines, from the L2-resident grid
+                     "l2_gather": {"achieved": 16 * 128 * args.n / (k64 * 1e-3) / 1e9, "peak": L2_PEAK_GBS,
+                                   "unit": "GB/s", "frac": 16 * 128 * args.n / (k64 * 1e-3) / 1e9 / L2_PEAK_GBS,
+                                   "bytes_per_point": 16 * 128}},
         "variants": {
             "f64_kernel_evals_per_s": evals / (k64 * 1e-3),
             "f32": {"value": evals / wall32, "ms_per_step": wall32 * 1e3, "kernel_ms": k32,
                     "kernel_evals_per_s": evals / (k32 * 1e-3), "achieved_GBs": ach32,
                     "frac": ach32 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes32,
-                    "speedup_vs_f64_kernel": k64 / k32},
+                    "speedup_vs_f64_kernel": k64 / k32,
+                    # FP32 rows of 16 columns: the 4 rows of one x knot's Q^2 window span 2-3 lines
+                    "l2_gather_frac": 4 * 2.5 * 128 * args.n / (k32 * 1e-3) / 1e9 / L2_PEAK_GBS},
         },
     }
     V = res["variants"]
+
+    # parity of the timed outputs with the FP64 oracle on a sample (outside the timed region): the
+    # floored criterion the tests apply (R14: 1e-12 |o| + 4 eps64 S (1 + L); FP32: |o| <= 1e-8 or
+    # 1e-5 |o| + 4 eps32 S), the literal relative criterion without the floor, and the largest eq. (1)
+    # difference |g - o| / (|o| + 1e-16) where the oracle is finite (and |o| > 1e-8 for FP32)
+    import oracle
+    ns = min(args.n, 20000)
+    sidx = np.random.default_rng(7).choice(args.n, ns, replace=False)
+    sidx_t = torch.from_numpy(sidx).to(dev)
+    ora, oscale = oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, g.values, g.pids), g.pids, x[sidx], q2[sidx],
+                               with_scale=True, n_threads=max(1, os.cpu_count() or 1))
+    Lg = float(max(np.max(1.0 / np.diff(np.log(t))) for t in g.xknots) +
+               max(np.max(1.0 / np.diff(np.log(t))) for t in g.q2knots))
+    eps64, eps32 = float(np.finfo(np.float64).eps), float(np.finfo(np.float32).eps)
+
+    def parity(gv, rtol, floor_abs, c_eps, with_L, small):
+        gv = gv.astype(np.float64)
+        fin = np.isfinite(ora)
+        both_nan = np.isnan(gv) & np.isnan(ora)
+        d = np.abs(gv - ora)
+        tiny = np.abs(ora) <= small if small else np.zeros_like(fin)
+        floor = c_eps * oscale * ((1.0 + Lg) if with_L else 1.0)
+        floored = both_nan | tiny | (d <= rtol * np.abs(ora) + floor)
+        literal = both_nan | tiny | (d <= rtol * np.abs(ora))
+        sel = fin & ~tiny
+        r = d[sel] / (np.abs(ora[sel]) + 1e-16)
+        return {"sample": int(ns), "floored_pass_frac": float(floored.mean()), "literal_pass_frac": float(literal.mean()),
+                "max_eq1": float(r.max()) if r.size else 0.0, "literal_rtol": rtol}
+    res["parity_vs_oracle"] = {
+        "f64": parity(out64[sidx_t].cpu().numpy(), 1e-12, None, 4 * eps64, True, 0.0),
+        "f32": parity(out32[sidx_t].cpu().numpy(), 1e-5, None, 4 * eps32, False, 1e-8)}
     del out32
 
     if not args.only_headline:
@@ -459,19 +499,117 @@ def main():
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        import oracle
-        og = oracle.Grid(g.xknots, g.q2knots, g.values, g.pids)
-        cores = max(1, min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1))
-        sample = min(args.cpu_sample, args.n)
-        xs_, qs_ = np.ascontiguousarray(x[:sample]), np.ascontiguousarray(q2[:sample])
-        oracle.xfxq2(og, g.pids, xs_[:1000], qs_[:1000], n_threads=cores)
-        t0 = time.perf_counter()
-        oracle.xfxq2(og, g.pids, xs_, qs_, n_threads=cores)
-        dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": sample * P / dt, "unit": "PDF evals/s", "cores": cores, "kind": "oracle",
-                               "sample": "first %d of the %d headline points, all %d flavours, FP64 oracle "
-                                         "(OpenMP over points), %.1f s wall" % (sample, args.n, P, dt)}
+        res["cpu_baseline"] = cpu_baseline(args, g, x, q2, qk, a)
     print(json.dumps(res), flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args, g, x, q2, qk, a):
+    """The FP64 oracle timed on the host: x*f of every flavour plus alpha_s at
+    each point (the GPU step's work), all cores (OpenMP over points; alpha_s in
+    as many threads) and one core, wall time of the evaluation calls only,
+    median of 5 after one warm-up.  Bounded samples of each workload, scaled to
+    evaluations per second."""
+    import statistics
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    from paper_2009_06635_amd import synth
+
+    cores = max(1, min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1))
+    pool = ThreadPoolExecutor(max_workers=cores)
+
+    def alphas(qk_, a_, qq, threads):
+        if threads == 1:
+            return oracle.alphas_q2(qk_, a_, qq)
+        parts = np.array_split(qq, threads)
+        return np.concatenate(list(pool.map(lambda p: oracle.alphas_q2(qk_, a_, p), parts)))
+
+    def median_time(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
+    def leg(name, fn_of_threads, evals, sample_desc, n1_frac):
+        """fn_of_threads(threads, frac) runs the sample (frac of it on one core)."""
+        t_all = median_time(lambda: fn_of_threads(cores, 1.0))
+        t_one = median_time(lambda: fn_of_threads(1, n1_frac))
+        return {"evals_per_s_all_cores": evals / t_all, "evals_per_s_one_core": evals * n1_frac / t_one,
+                "sample": sample_desc, "all_cores_s": t_all, "one_core_s": t_one}
+
+    out = {"unit": "PDF evals/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
+           "timing": "median of 5 after one warm-up, evaluation calls only"}
+    # headline: three-sub-grid grid, all 13 flavours + alpha_s
+    og = oracle.Grid(g.xknots, g.q2knots, g.values, g.pids)
+    nh = min(args.cpu_sample, args.n)
+    xs_, qs_ = np.ascontiguousarray(x[:nh]), np.ascontiguousarray(q2[:nh])
+    P = len(g.pids)
+
+    def head(threads, frac):
+        m = max(1, int(nh * frac))
+        oracle.xfxq2(og, g.pids, xs_[:m], qs_[:m], n_threads=threads)
+        alphas(qk, a, qs_[:m], threads)
+    out["headline"] = leg("headline", head, nh * P,
+                          "first %d of the %d headline points (one core: a tenth of them), all %d flavours "
+                          "+ alpha_s" % (nh, args.n, P), 0.1)
+    out["value"] = out["headline"]["evals_per_s_all_cores"]
+    out["sample"] = out["headline"]["sample"]
+    # small workload (one sub-grid, 11 flavours, 1e5 points) + alpha_s
+    g1 = synth.config1_grid()
+    og1 = oracle.Grid(g1.xknots, g1.q2knots, g1.values, g1.pids)
+    x1, q1 = synth.config1_queries()
+    qk1, a1 = synth.config1_alphas()
+
+    def small(threads, frac):
+        m = max(1, int(len(x1) * frac))
+        oracle.xfxq2(og1, g1.pids, x1[:m], q1[:m], n_threads=threads)
+        alphas(qk1, a1, q1[:m], threads)
+    out["small"] = leg("small", small, len(x1) * len(g1.pids),
+                       "all 1e5 points, 11 flavours + alpha_s (one core: a quarter)", 0.25)
+    # batched workload: 101 members, 200 requests; the first 2000 points of every request
+    members = synth.config3_members()
+    ogm = [oracle.Grid(mg.xknots, mg.q2knots, mg.values, mg.pids) for mg in members]
+    reqs = synth.config3_requests()
+    sub = [(r["member"], r["pids"], np.ascontiguousarray(r["x"][:2000]), np.ascontiguousarray(r["q2"][:2000]))
+           for r in reqs]
+    nev = sum(len(s_[2]) * len(s_[1]) for s_ in sub)
+
+    def batched(threads, frac):
+        for mi, pids, xr, qr in sub[:max(1, int(len(sub) * frac))]:
+            oracle.xfxq2(ogm[mi], pids, xr, qr, n_threads=threads)
+    out["batched"] = leg("batched", batched, nev,
+                         "first <= 2000 points of each of the 200 requests (one core: the first 50 requests)", 0.25)
+    # Monte-Carlo load: two lookups of 13 flavours at a shared scale + alpha_s + the luminosity sum
+    cx1, cx2, cq = synth.config5_chunk(0)
+    nm = 200_000
+    cx1, cx2, cq = cx1[:nm], cx2[:nm], cq[:nm]
+
+    def mc(threads, frac):
+        m = max(1, int(nm * frac))
+        f1 = oracle.xfxq2(og1, synth.PIDS_13, cx1[:m], cq[:m], n_threads=threads)
+        f2 = oracle.xfxq2(og1, synth.PIDS_13, cx2[:m], cq[:m], n_threads=threads)
+        al = alphas(qk1, a1, cq[:m], threads)
+        math.fsum(al * np.sum(f1 * f2, axis=1))
+    out["mc"] = leg("mc", mc, nm * 26,
+                    "first %d points of chunk 0 (26 evaluations + alpha_s each; one core: a tenth)" % nm, 0.1)
+    pool.shutdown()
+    return out
 
 
 if __name__ == "__main__":
