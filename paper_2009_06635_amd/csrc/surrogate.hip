@@ -306,7 +306,12 @@ __global__ void k_gather_samples(const float* __restrict__ in_all, const float* 
 // LDS rows of 64 BF16 values (the activation tiles, the lo weight halves)
 // hold their eight 16-byte chunks in the order chunk ^ (row & 7), so the 16
 // rows an operand read touches spread over the banks.
-constexpr int kSurWaves = 4;
+// Launch shapes: with the hi weight fragments in registers (kWeightsInLds =
+// false) a wave needs ~200 VGPRs (2 waves per SIMD, blocks of 4 waves); with
+// both halves of the weights in LDS it fits 128 VGPRs and blocks of 16 waves
+// fill the CU's LDS (4 waves per SIMD).
+constexpr bool kWeightsInLds = true;
+constexpr int kSurWaves = kWeightsInLds ? 16 : 4;
 constexpr int kSurRec = 8;   // floats per point record: u, v, h00, h10 D, h01, h11 D, cell, fallback
 
 __device__ __forceinline__ int swz(int row, int col) {  // element offset of (row, col) in a swizzled [.][64] tile
@@ -326,15 +331,24 @@ struct FbRec {
 // 4 KB area (activation pair tile, then the output tile, then the fallback
 // records) and the point records.
 constexpr size_t kSurWaveArea = 2 * 16 * kH * 2;  // 4096 bytes
+constexpr size_t kSurWTile = (size_t)2 * (2 * kH * kH + kO * kH);  // one half of W2, W3, W4 (BF16)
 __host__ __device__ static inline size_t sur_head_bytes(int nx) {
-  const size_t b = (size_t)8 * nx + (size_t)4 * (2 * nx * kO + 2 * kH + 3 * kH + kO) + (size_t)2 * (2 * kH * kH + kO * kH);
+  const size_t b = (kWeightsInLds ? 2 : 1) * kSurWTile + (size_t)8 * nx + (size_t)4 * (2 * nx * kO + 2 * kH + 3 * kH + kO);
   return (b + 15) & ~(size_t)15;
 }
-size_t sur_infer_shared_bytes(int nx) {
-  return sur_head_bytes(nx) + (size_t)kSurWaves * (kSurWaveArea + 64 * kSurRec * 4);
+constexpr size_t kSurWaveBytes = kSurWaveArea + 64 * kSurRec * 4;
+// Waves per block: kSurWaves, fewer when the per-block tables (which grow
+// with the number of x knots) leave less LDS.
+int sur_infer_waves(int nx) {
+  const size_t head = sur_head_bytes(nx);
+  const size_t lds = 160 * 1024;
+  const int w = head >= lds ? 0 : (int)((lds - head) / kSurWaveBytes);
+  return w < kSurWaves ? w : kSurWaves;
 }
+size_t sur_infer_shared_bytes(int nx, int waves) { return sur_head_bytes(nx) + (size_t)waves * kSurWaveBytes; }
 
-__global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
+__global__ __launch_bounds__(64 * kSurWaves) __attribute__((amdgpu_waves_per_eu(kWeightsInLds ? 4 : 1)))
+void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
                                                              const unsigned short* __restrict__ Pb,
                                                              const float* __restrict__ Pf,
                                                              const double* __restrict__ X,
@@ -342,11 +356,14 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
                                                              float* __restrict__ out, double invL01,
                                                              unsigned long long* __restrict__ nerr) {
   extern __shared__ __align__(16) unsigned char sraw[];
-  constexpr int BS = 64 * kSurWaves;
+  const int BS = blockDim.x, nwav = BS >> 6;
   unsigned short* sw2l = reinterpret_cast<unsigned short*>(sraw);  // [kH][kH] swizzled (16-byte chunks)
   unsigned short* sw3l = sw2l + kH * kH;
   unsigned short* sw4l = sw3l + kH * kH;                   // [kO][kH] swizzled
-  double* slxk = reinterpret_cast<double*>(sw4l + kO * kH);  // [nx]
+  unsigned short* sw2h = sw4l + kO * kH;                   // hi halves, same layout (kWeightsInLds)
+  unsigned short* sw3h = sw2h + kH * kH;
+  unsigned short* sw4h = sw3h + kH * kH;
+  double* slxk = reinterpret_cast<double*>(kWeightsInLds ? sw4h + kO * kH : sw2h);  // [nx]
   float* senv = reinterpret_cast<float*>(slxk + S.nx);     // [nx][kO]
   float* senvd = senv + S.nx * kO;                         // [nx][kO]
   float* sw1 = senvd + S.nx * kO;                          // [kH][2]
@@ -361,7 +378,7 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
   unsigned short* hs_lo = hs_hi + 16 * kH;
   float* so = reinterpret_cast<float*>(area);                         // [16][kO] output tile
   FbRec* fbr = reinterpret_cast<FbRec*>(area);                        // [64] fallback records
-  float* rec = reinterpret_cast<float*>(waves + (size_t)kSurWaves * kSurWaveArea) + wv * 64 * kSurRec;
+  float* rec = reinterpret_cast<float*>(waves + (size_t)nwav * kSurWaveArea) + wv * 64 * kSurRec;
 
   for (int i = threadIdx.x; i < S.nx; i += BS) slxk[i] = S.lxk[i];
   for (int i = threadIdx.x; i < S.nx * kO; i += BS) {
@@ -380,12 +397,20 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
     const int row = i / kH, col = i % kH;
     sw2l[swz(row, col)] = Pl[kOffW2 + i];
     sw3l[swz(row, col)] = Pl[kOffW3 + i];
+    if (kWeightsInLds) {
+      sw2h[swz(row, col)] = Pb[kOffW2 + i];
+      sw3h[swz(row, col)] = Pb[kOffW3 + i];
+    }
   }
-  for (int i = threadIdx.x; i < kO * kH; i += BS) sw4l[swz(i / kH, i % kH)] = Pl[kOffW4 + i];
+  for (int i = threadIdx.x; i < kO * kH; i += BS) {
+    sw4l[swz(i / kH, i % kH)] = Pl[kOffW4 + i];
+    if (kWeightsInLds) sw4h[swz(i / kH, i % kH)] = Pb[kOffW4 + i];
+  }
   __syncthreads();
 
   // hi weight fragments: B operand of layer L, N-tile t, K-step s: lane holds W[n = 16t + r][k = 32s + 8g + i]
   bf16x8 w2[4][2], w3[4][2], w4[2];
+  if (!kWeightsInLds) {
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -400,6 +425,7 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int i = 0; i < 8; ++i) w4[s][i] = __builtin_bit_cast(__bf16, Pb[kOffW4 + r * kH + 32 * s + 8 * g + i]);
+  }
   // an 8-value chunk (16 bytes) of a swizzled LDS row, as an operand fragment
   auto frag = [&](const unsigned short* tile, int row, int col0) -> bf16x8 {
     return *reinterpret_cast<const bf16x8*>(tile + swz(row, col0));
@@ -409,7 +435,7 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
   const int R = rc.n;
 
   const int64_t ntiles = (n + 63) / 64;
-  for (int64_t tile = (int64_t)blockIdx.x * kSurWaves + wv; tile < ntiles; tile += (int64_t)gridDim.x * kSurWaves) {
+  for (int64_t tile = (int64_t)blockIdx.x * nwav + wv; tile < ntiles; tile += (int64_t)gridDim.x * nwav) {
     const int64_t p0 = tile * 64;
     const int np = (int)min((int64_t)64, n - p0);
     // one lane per point: inputs, fallback flag, envelope weights
@@ -462,7 +488,8 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
           f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
-            const bf16x8 wh = layer == 0 ? w2[t][s] : w3[t][s];
+            const bf16x8 wh = kWeightsInLds ? frag(layer == 0 ? sw2h : sw3h, 16 * t + r, 32 * s + 8 * g)
+                                            : (layer == 0 ? w2[t][s] : w3[t][s]);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], wh, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], wh, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], frag(wl, 16 * t + r, 32 * s + 8 * g), acc, 0, 0, 0);
@@ -490,8 +517,9 @@ __global__ __launch_bounds__(64 * kSurWaves) void k_sur_infer(SurDev S, MemberDe
       f32x4 y = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], w4[s], y, 0, 0, 0);
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], w4[s], y, 0, 0, 0);
+        const bf16x8 wh = kWeightsInLds ? frag(sw4h, r, 32 * s + 8 * g) : w4[s];
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], wh, y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], wh, y, 0, 0, 0);
         y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], frag(sw4l, r, 32 * s + 8 * g), y, 0, 0, 0);
       }
       const float b4 = sb4[r];
@@ -747,14 +775,16 @@ hipError_t sur_infer(const SurDev& S, const MemberDev& m, const ReqCols& rc, con
                      const double* q2, int64_t n, float* out, double invL01, unsigned long long* nerr, int n_cu,
                      hipStream_t s) {
   const int64_t tiles = (n + 63) / 64;
-  const size_t shm = sur_infer_shared_bytes(S.nx);
+  const int waves = sur_infer_waves(S.nx);
+  if (waves < 1) return hipErrorInvalidValue;  // envelope tables beyond LDS (the create call bounds nx)
+  const size_t shm = sur_infer_shared_bytes(S.nx, waves);
   const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)shm);
-  const int64_t blocks = min((tiles + kSurWaves - 1) / kSurWaves, (int64_t)n_cu * per_cu);
+  const int64_t blocks = min((tiles + waves - 1) / waves, (int64_t)n_cu * per_cu);
   if (blocks > 0) {
     hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_sur_infer), shm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sur_infer, dim3((unsigned)blocks), dim3(64 * kSurWaves), shm, s, S, m, rc, b.Pb, b.P, x, q2,
-                       n, out, invL01, nerr);
+    hipLaunchKernelGGL(k_sur_infer, dim3((unsigned)blocks), dim3(64 * waves), shm, s, S, m, rc, b.Pb, b.P, x, q2, n,
+                       out, invL01, nerr);
   }
   return hipGetLastError();
 }
