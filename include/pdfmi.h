@@ -268,12 +268,16 @@ typedef struct {
     float lr_final;       /* learning rate from global step total_steps on */
     int32_t total_steps;  /* length of the cosine schedule (>= 1) */
     float* loss_out;      /* NULL, or DEVICE [steps]: each step's batch loss before its update */
+    int32_t use_graph;    /* 1: the steps replay one recorded HIP graph of a training step (fewer launch
+                             costs); 0: the same launches queued one by one.  Results are identical. */
 } pdf_train_opts;
 /* opts->steps Adam steps (beta 0.9 / 0.999, eps 1e-8); learning rate on a
  * cosine schedule from lr to lr_final over total_steps, indexed by the
  * surrogate's global step (as is the batch slice), so a run split across
  * calls (or across a save/load) is identical to one call.  Asynchronous on
- * stream.  PDF_ERR_STATE without a training set of at least one batch. */
+ * stream; the recorded step graph is kept with the surrogate and rebuilt
+ * when the batch size or the training set changes.  PDF_ERR_STATE without a
+ * training set of at least one batch. */
 int pdf_surrogate_train(int32_t sid, const pdf_train_opts* opts, pdf_stream_t stream);
 /* One forward + backward pass on DEVICE inputs in[batch][2] (normalised) and
  * targets[batch][16]: writes the flat FP32 gradient (param_count floats) and

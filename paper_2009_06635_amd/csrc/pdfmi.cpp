@@ -40,7 +40,10 @@ constexpr int kAlphasMaxHints = 2048;  // alpha_s search hints staged in LDS
 int sur_out_width();
 int sur_hidden();
 hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, float* loss_out,
-                                hipStream_t s);
+                                const SurStep* st, hipStream_t s);
+hipError_t sur_train_begin(const SurBufs& b, int64_t step, int64_t nbatches, int total, float lr0, float lrf,
+                           float* loss_out, hipStream_t s);
+hipError_t sur_train_step(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s);
 hipError_t sur_adam(const SurBufs& b, float lr, int step, hipStream_t s);
 hipError_t sur_refresh_bf16(const SurBufs& b, hipStream_t s);
 hipError_t sur_prep(const SurDev& S, const MemberDev& m, const double* x, const double* q2, const double* xf,
@@ -1067,6 +1070,13 @@ struct Surrogate {
   int64_t n_train = 0;
   int64_t step = 0;          // Adam steps taken
   uint64_t seed = 0;
+  // one training step recorded as a graph (replayed per step), valid for g_batch and g_in
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int g_batch = 0;
+  const float* g_in = nullptr;
+  const void* g_bmem = nullptr;
 };
 
 std::vector<Surrogate> g_surs;
@@ -1082,7 +1092,19 @@ Member* sur_member(const Surrogate& S) {
   return M && M->gen == S.member_gen ? M : nullptr;
 }
 
+void sur_free_graph(Surrogate& S) {
+  if (S.exec) (void)hipGraphExecDestroy(S.exec);
+  if (S.graph) (void)hipGraphDestroy(S.graph);
+  S.exec = nullptr;
+  S.graph = nullptr;
+  S.g_batch = 0;
+  S.g_in = nullptr;
+  S.g_bmem = nullptr;
+}
+
 void sur_release(Surrogate& S) {
+  sur_free_graph(S);
+  if (S.cap) (void)hipStreamDestroy(S.cap);
   if (S.pmem) (void)hipFree(S.pmem);
   if (S.bmem) (void)hipFree(S.bmem);
   if (S.d_in) (void)hipFree(S.d_in);
@@ -1245,7 +1267,7 @@ extern "C" int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_
   }
   const size_t bp = align_up((size_t)NP * 4, 256), bpb = align_up((size_t)NP * 4, 256);  // Pb: hi and lo halves
   const size_t be = align_up(env.size() * 4, 256), bl = align_up(lxk.size() * 8, 256);
-  hipError_t e = hipMalloc(&S.pmem, 4 * bp + bpb + 2 * be + bl + 2048);
+  hipError_t e = hipMalloc(&S.pmem, 4 * bp + bpb + 2 * be + bl + 2048 + align_up(sizeof(SurStep), 256));
   if (e != hipSuccess) return fail_hip(e, "hipMalloc(surrogate)");
   unsigned char* b = static_cast<unsigned char*>(S.pmem);
   S.b.P = reinterpret_cast<float*>(b);
@@ -1258,6 +1280,7 @@ extern "C" int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_
   double* lxkd = reinterpret_cast<double*>(b + 4 * bp + bpb + 2 * be);
   S.b.loss = reinterpret_cast<float*>(b + 4 * bp + bpb + 2 * be + bl);
   S.b.partial = S.b.loss + 64;
+  S.b.st = reinterpret_cast<SurStep*>(b + 4 * bp + bpb + 2 * be + bl + 2048);
   S.sd.env = envdev;
   S.sd.envd = envddev;
   S.sd.lxk = lxkd;
@@ -1303,6 +1326,7 @@ extern "C" int pdf_surrogate_set_data(int32_t sid, const double* x, const double
   hipStream_t s = (hipStream_t)stream;
   const int O = sur_out_width(), P = (int)M->pids.size();
   // the old set is released first; until the new one is complete, training finds no data
+  sur_free_graph(*S);
   if (S->d_in) (void)hipFree(S->d_in);
   S->d_in = nullptr;
   S->d_t = nullptr;
@@ -1368,20 +1392,39 @@ extern "C" int pdf_surrogate_train(int32_t sid, const pdf_train_opts* opts, pdf_
   int rc = sur_ensure_batch(*S, batch);
   if (rc != PDF_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
-  const int O = sur_out_width();
   const int64_t nb = S->n_train / batch;
-  for (int i = 0; i < steps; ++i) {
-    const int64_t t = S->step;  // global step: batch slice and learning rate depend only on it
-    const int64_t off = (t % nb) * batch;
-    const double frac = std::min(1.0, (double)t / (double)opts->total_steps);
-    const float lr_t = (float)(opts->lr_final + 0.5 * ((double)opts->lr - opts->lr_final) *
-                                                    (1.0 + std::cos(3.141592653589793 * frac)));
-    hipError_t e = sur_forward_backward(S->b, S->d_in + 2 * off, S->d_t + O * off, batch,
-                                        opts->loss_out ? opts->loss_out + i : nullptr, s);
-    if (e == hipSuccess) e = sur_adam(S->b, lr_t, (int)(t + 1), s);
-    if (e != hipSuccess) return fail_hip(e, "surrogate training step");
-    ++S->step;
+  if (steps == 0) return PDF_OK;
+  hipError_t e = sur_train_begin(S->b, S->step, nb, opts->total_steps, opts->lr, opts->lr_final, opts->loss_out, s);
+  if (e != hipSuccess) return fail_hip(e, "surrogate training start");
+  if (opts->use_graph) {
+    if (!S->exec || S->g_batch != batch || S->g_in != S->d_in || S->g_bmem != S->bmem) {
+      sur_free_graph(*S);
+      if (!S->cap && (e = hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking)) != hipSuccess)
+        return fail_hip(e, "hipStreamCreate(capture)");
+      if ((e = hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return fail_hip(e, "hipStreamBeginCapture");
+      const hipError_t e1 = sur_train_step(S->b, S->d_in, S->d_t, batch, S->cap);
+      e = hipStreamEndCapture(S->cap, &S->graph);
+      if (e1 != hipSuccess || e != hipSuccess) {
+        sur_free_graph(*S);
+        return fail_hip(e1 != hipSuccess ? e1 : e, "capture of a training step");
+      }
+      if ((e = hipGraphInstantiate(&S->exec, S->graph, nullptr, nullptr, 0)) != hipSuccess) {
+        sur_free_graph(*S);
+        return fail_hip(e, "hipGraphInstantiate(training step)");
+      }
+      S->g_batch = batch;
+      S->g_in = S->d_in;
+      S->g_bmem = S->bmem;
+    }
+    for (int i = 0; i < steps; ++i)
+      if ((e = hipGraphLaunch(S->exec, s)) != hipSuccess) return fail_hip(e, "hipGraphLaunch(training step)");
+  } else {
+    for (int i = 0; i < steps; ++i)
+      if ((e = sur_train_step(S->b, S->d_in, S->d_t, batch, s)) != hipSuccess)
+        return fail_hip(e, "surrogate training step");
   }
+  S->step += steps;
   return PDF_OK;
 }
 
@@ -1395,7 +1438,7 @@ extern "C" int pdf_surrogate_grad(int32_t sid, const float* in, const float* tar
   int rc = sur_ensure_batch(*S, batch);
   if (rc != PDF_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = sur_forward_backward(S->b, in, target, batch, loss_out, s);
+  hipError_t e = sur_forward_backward(S->b, in, target, batch, loss_out, nullptr, s);
   if (e == hipSuccess) e = hipMemcpyAsync(grad_out, S->b.G, (size_t)sur_nparams() * 4, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return fail_hip(e, "surrogate gradient");
   return PDF_OK;

@@ -167,6 +167,18 @@ struct SurDev {
   double txlo[kMaxSub], txhi[kMaxSub], tqlo[kMaxSub], tqhi[kMaxSub];
 };
 
+// Device-side state of a surrogate's training call.  The training kernels
+// read the global step (which batch slice, which learning rate) from here,
+// so every step is the same launch sequence and can be replayed as a graph.
+struct SurStep {
+  int64_t step;      // global step: batch (step % nb), learning rate, Adam update number step + 1
+  int64_t call;      // step index within the current train call (index into loss_out)
+  int64_t nb;        // batches in the training set
+  int total;         // cosine schedule length
+  float lr0, lrf;    // schedule end points
+  float* loss_out;   // the call's per-step losses, or null
+};
+
 // Surrogate device buffers (parameters, Adam moments, gradients, batch activations).
 // Matrix operands are BF16 pairs (hi, lo) with value = hi + lo.
 struct SurBufs {
@@ -178,6 +190,7 @@ struct SurBufs {
   float* loss;              // [1]
   float* partial;           // [256]
   float* wpart;             // split-reduction partial sums, 64 slices x 64 x 64
+  SurStep* st;              // training-call state
 };
 
 // hipFuncSetAttribute(MaxDynamicSharedMemorySize) only when a launch needs

@@ -125,10 +125,18 @@ __global__ __launch_bounds__(64) void k_gemm_bf16(const unsigned short* __restri
 
 // Layer 1 (K = 2, FP32 on the vector ALUs): h1 = tanh(W1 in + b1), FP32 and
 // its BF16 pair.
-__global__ void k_layer1(const float* __restrict__ in, const float* __restrict__ P, int B, float* __restrict__ h,
-                         unsigned short* __restrict__ hb, unsigned short* __restrict__ hl) {
+// Batch slice of a training step: rows (step % nb) * B of the training set
+// when st is given (in and T are then the set's first rows), else as passed.
+__device__ __forceinline__ int64_t batch_row(const SurStep* st, int B) {
+  return st ? (st->step % st->nb) * (int64_t)B : 0;
+}
+
+__global__ void k_layer1(const float* __restrict__ in, const SurStep* __restrict__ st, const float* __restrict__ P,
+                         int B, float* __restrict__ h, unsigned short* __restrict__ hb,
+                         unsigned short* __restrict__ hl) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= (int64_t)B * kH) return;
+  in += 2 * batch_row(st, B);
   const int b = (int)(i / kH), j = (int)(i % kH);
   const float z = fmaf(P[kOffW1 + 2 * j], in[2 * b], fmaf(P[kOffW1 + 2 * j + 1], in[2 * b + 1], P[kOffB1 + j]));
   const float t = tanh_f(z);
@@ -137,10 +145,11 @@ __global__ void k_layer1(const float* __restrict__ in, const float* __restrict__
 }
 
 // Loss (mean squared error over B x kO) and its gradient dY = 2 (Y - T) / (B kO).
-__global__ void k_loss_grad(const float* __restrict__ Y, const float* __restrict__ T, int B, float* __restrict__ dY,
-                            unsigned short* __restrict__ dYb, float* __restrict__ sq) {
+__global__ void k_loss_grad(const float* __restrict__ Y, const float* __restrict__ T, const SurStep* __restrict__ st,
+                            int B, float* __restrict__ dY, unsigned short* __restrict__ dYb, float* __restrict__ sq) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= (int64_t)B * kO) return;
+  T += kO * batch_row(st, B);
   const float d = Y[i] - T[i];
   const float gr = 2.0f * d / (float)((int64_t)B * kO);
   dY[i] = gr;
@@ -173,10 +182,11 @@ __global__ void k_col_sum(const float* __restrict__ X, int B, int ncols, int kch
 
 // dW1[j][t] = sum_b dZ1[b][j] in[b][t] (FP32, in b order within a slice of
 // kchunk rows per blockIdx.y; slices added in order).
-__global__ void k_dw1(const float* __restrict__ dZ, const float* __restrict__ in, int B, int kchunk,
-                      float* __restrict__ dW1) {
+__global__ void k_dw1(const float* __restrict__ dZ, const float* __restrict__ in, const SurStep* __restrict__ st,
+                      int B, int kchunk, float* __restrict__ dW1) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= kH * 2) return;
+  in += 2 * batch_row(st, B);
   const int j = o / 2, t = o % 2;
   const int b0 = blockIdx.y * kchunk, b1 = min(B, b0 + kchunk);
   float s = 0.0f;
@@ -186,12 +196,21 @@ __global__ void k_dw1(const float* __restrict__ dZ, const float* __restrict__ in
 }
 
 // Adam step on the FP32 masters (Kingma & Ba, bias-corrected moments; c1 =
-// 1 - b1^t, c2 = 1 - b2^t), then their BF16 pairs.
+// 1 - b1^t, c2 = 1 - b2^t for update number t), then their BF16 pairs.  With
+// st the update number is st->step + 1 and the learning rate follows the
+// cosine schedule lrf + (lr0 - lrf)(1 + cos(pi min(1, step / total))) / 2.
 __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ Mm,
                        float* __restrict__ Vm, unsigned short* __restrict__ Pb, int n, float lr, float b1, float b2,
-                       float eps, float c1, float c2) {
+                       float eps, float c1, float c2, const SurStep* __restrict__ st) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (st) {
+    const double t = (double)st->step;
+    const double frac = fmin(1.0, t / (double)st->total);
+    lr = (float)(st->lrf + 0.5 * ((double)st->lr0 - st->lrf) * (1.0 + cos(3.141592653589793 * frac)));
+    c1 = (float)(1.0 - pow(0.9, t + 1.0));  // the betas in FP64, as the host computes them
+    c2 = (float)(1.0 - pow(0.999, t + 1.0));
+  }
   const float g = G[i];
   const float m = b1 * Mm[i] + (1.0f - b1) * g;
   const float v = b2 * Vm[i] + (1.0f - b2) * g * g;
@@ -200,6 +219,24 @@ __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float
   const float p = P[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
   P[i] = p;
   split_bits(p, Pb[i], Pb[n + i]);
+}
+
+// Start of a training call: the global step, the call's step index, the schedule and the loss output.
+__global__ void k_train_begin(SurStep* st, int64_t step, int64_t nb, int total, float lr0, float lrf,
+                              float* loss_out) {
+  st->step = step;
+  st->call = 0;
+  st->nb = nb;
+  st->total = total;
+  st->lr0 = lr0;
+  st->lrf = lrf;
+  st->loss_out = loss_out;
+}
+
+// End of a training step.
+__global__ void k_train_advance(SurStep* st) {
+  st->step += 1;
+  st->call += 1;
 }
 
 __global__ void k_to_bf16(const float* __restrict__ P, unsigned short* __restrict__ Pb, int n) {
@@ -669,12 +706,13 @@ __global__ void k_sum_partial(const float* __restrict__ x, int64_t n, float* __r
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 __global__ void k_sum_final(const float* __restrict__ partial, float scale, float* __restrict__ out,
-                            float* __restrict__ out2) {
+                            float* __restrict__ out2, const SurStep* __restrict__ st) {
   __shared__ float red[256];
   const float s = block_tree_sum(partial[threadIdx.x], red);
   if (threadIdx.x == 0) {
     *out = s * scale;
     if (out2) *out2 = s * scale;
+    if (st && st->loss_out) st->loss_out[st->call] = s * scale;
   }
 }
 
@@ -690,21 +728,22 @@ static void col_sum(const float* X, int B, int ncols, float* out, float* ws, hip
   hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, ws, S, ncols, out);
 }
 
-static void dw1(const float* dZ, const float* in, int B, float* out, float* ws, hipStream_t s) {
+static void dw1(const float* dZ, const float* in, const SurStep* st, int B, float* out, float* ws, hipStream_t s) {
   const int S = min(kMaxSlices, (B + kColRows - 1) / kColRows);
   const int kchunk = (B + S - 1) / S;
-  hipLaunchKernelGGL(k_dw1, dim3(1, (unsigned)S), dim3(128), 0, s, dZ, in, B, kchunk, ws);
+  hipLaunchKernelGGL(k_dw1, dim3(1, (unsigned)S), dim3(128), 0, s, dZ, in, st, B, kchunk, ws);
   hipLaunchKernelGGL(k_sum_slices, dim3(1), dim3(256), 0, s, ws, S, kH * 2, out);
 }
 
-// One forward + backward pass on a batch (inputs in[B][2], targets T[B][kO]):
-// gradients into buf.G, loss (mean squared error) into buf.loss and, if not
-// null, *loss_out.
+// One forward + backward pass on a batch (inputs in[B][2], targets T[B][kO];
+// with st, the step's slice of the training set starting at in, T): gradients
+// into buf.G, loss (mean squared error) into buf.loss and, if not null,
+// *loss_out (and the call's loss_out entry of st).
 hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, float* loss_out,
-                                hipStream_t s) {
+                                const SurStep* st, hipStream_t s) {
   const unsigned short* Wh = b.Pb;              // hi halves
   const unsigned short* Wl = b.Pb + kNParams;   // lo halves
-  hipLaunchKernelGGL(k_layer1, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, in, b.P, B, b.h1, b.h1b, b.h1l);
+  hipLaunchKernelGGL(k_layer1, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, in, st, b.P, B, b.h1, b.h1b, b.h1l);
   // z = h W^T + b: A(m=b,k) = h[b][k]; B(k,n) = W[n][k]; split operands
   gemm(b.h1b, b.h1l, kH, 1, Wh + kOffW2, Wl + kOffW2, 1, kH, b.h2, kH, b.h2b, b.h2l, B, kH, kH, b.P + kOffB2, 1,
        b.wpart, s);
@@ -712,10 +751,11 @@ hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* 
        b.wpart, s);
   gemm(b.h3b, b.h3l, kH, 1, Wh + kOffW4, Wl + kOffW4, 1, kH, b.y, kO, nullptr, nullptr, B, kO, kH, b.P + kOffB4, 0,
        b.wpart, s);
-  hipLaunchKernelGGL(k_loss_grad, dim3(nb((int64_t)B * kO, 256)), dim3(256), 0, s, b.y, T, B, b.dy, b.dyb, b.sq);
+  hipLaunchKernelGGL(k_loss_grad, dim3(nb((int64_t)B * kO, 256)), dim3(256), 0, s, b.y, T, st, B, b.dy, b.dyb,
+                     b.sq);
   hipLaunchKernelGGL(k_sum_partial, dim3(256), dim3(256), 0, s, b.sq, (int64_t)B * kO, b.partial);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, b.partial, 1.0f / (float)((int64_t)B * kO), b.loss,
-                     loss_out);
+                     loss_out, st);
   // backward on the hi halves: layer 4: dW4[o][i] = sum_b dy[b][o] h3[b][i]; db4; dh3 = dy W4
   gemm(b.dyb, nullptr, 1, kO, b.h3b, nullptr, kH, 1, b.G + kOffW4, kH, nullptr, nullptr, kO, kH, B, nullptr, 0,
        b.wpart, s);
@@ -739,7 +779,7 @@ hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* 
   // layer 1 (FP32)
   hipLaunchKernelGGL(k_tanh_back, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, b.dh, b.h1, (int64_t)B * kH, b.dz,
                      b.dzb);
-  dw1(b.dz, in, B, b.G + kOffW1, b.wpart, s);
+  dw1(b.dz, in, st, B, b.G + kOffW1, b.wpart, s);
   col_sum(b.dz, B, kH, b.G + kOffB1, b.wpart, s);
   return hipGetLastError();
 }
@@ -748,7 +788,26 @@ hipError_t sur_adam(const SurBufs& b, float lr, int step, hipStream_t s) {
   const double b1 = 0.9, b2 = 0.999;
   const float c1 = (float)(1.0 - pow(b1, step)), c2 = (float)(1.0 - pow(b2, step));
   hipLaunchKernelGGL(k_adam, dim3(nb(kNParams, 256)), dim3(256), 0, s, b.P, b.G, b.M, b.V, b.Pb, kNParams, lr,
-                     (float)b1, (float)b2, 1e-8f, c1, c2);
+                     (float)b1, (float)b2, 1e-8f, c1, c2, (const SurStep*)nullptr);
+  return hipGetLastError();
+}
+
+// Start of a training call (the state the step kernels read).
+hipError_t sur_train_begin(const SurBufs& b, int64_t step, int64_t nbatches, int total, float lr0, float lrf,
+                           float* loss_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_train_begin, dim3(1), dim3(1), 0, s, b.st, step, nbatches, total, lr0, lrf, loss_out);
+  return hipGetLastError();
+}
+
+// One training step on the slice of the training set (in, T) that b.st
+// selects: forward + backward, Adam at the scheduled learning rate, advance.
+// The same launches at every step (recorded once as a graph by the caller).
+hipError_t sur_train_step(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s) {
+  hipError_t e = sur_forward_backward(b, in, T, B, nullptr, b.st, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adam, dim3(nb(kNParams, 256)), dim3(256), 0, s, b.P, b.G, b.M, b.V, b.Pb, kNParams, 0.0f,
+                     0.9f, 0.999f, 1e-8f, 1.0f, 1.0f, (const SurStep*)b.st);
+  hipLaunchKernelGGL(k_train_advance, dim3(1), dim3(1), 0, s, b.st);
   return hipGetLastError();
 }
 

@@ -419,7 +419,8 @@ def surrogate_param_count():
 
 class _TrainOpts(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
-                ("lr_final", ctypes.c_float), ("total_steps", ctypes.c_int32), ("loss_out", ctypes.c_void_p)]
+                ("lr_final", ctypes.c_float), ("total_steps", ctypes.c_int32), ("loss_out", ctypes.c_void_p),
+                ("use_graph", ctypes.c_int32)]
 
 
 class Surrogate:
@@ -436,14 +437,15 @@ class Surrogate:
         _dev_f64(q2, "q2")
         _check(_lib.pdf_surrogate_set_data(self.id, _P(x.data_ptr()), _P(q2.data_ptr()), x.shape[0], _stream(stream)))
 
-    def train(self, steps, batch, lr, lr_final, total_steps, loss_out=None, stream=None):
+    def train(self, steps, batch, lr, lr_final, total_steps, loss_out=None, use_graph=True, stream=None):
         """steps Adam steps; loss_out: optional float32 CUDA tensor of >= steps
-        entries receiving each step's batch loss."""
+        entries receiving each step's batch loss; use_graph: replay one recorded
+        graph per step (False: the same launches one by one)."""
         if loss_out is not None and not (isinstance(loss_out, torch.Tensor) and loss_out.is_cuda and
                                          loss_out.dtype == torch.float32 and loss_out.numel() >= steps):
             raise TypeError("loss_out must be a float32 CUDA tensor of at least `steps` entries")
         o = _TrainOpts(int(steps), int(batch), float(lr), float(lr_final), int(total_steps),
-                       loss_out.data_ptr() if loss_out is not None else None)
+                       loss_out.data_ptr() if loss_out is not None else None, 1 if use_graph else 0)
         _check(_lib.pdf_surrogate_train(self.id, ctypes.byref(o), _stream(stream)))
 
     def adam(self, grad, lr, stream=None):

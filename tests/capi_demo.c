@@ -113,7 +113,7 @@ int main(int argc, char** argv) {
   HIPCHECK(hipMalloc((void**)&dloss, kSteps * 4));
   LIBCHECK(pdf_surrogate_create(member, 1, &sid));
   LIBCHECK(pdf_surrogate_set_data(sid, dx, dq, n, NULL));
-  pdf_train_opts opts = {kSteps, 256, 3e-3f, 3e-4f, kSteps, dloss};
+  pdf_train_opts opts = {kSteps, 256, 3e-3f, 3e-4f, kSteps, dloss, 1};
   LIBCHECK(pdf_surrogate_train(sid, &opts, NULL));
   LIBCHECK(pdf_surrogate_xfxq2(sid, NULL, 0, dx, dq, n, dsur, NULL));
   LIBCHECK(pdf_surrogate_xfxq2(sid, sub_pids, kSub, dx, dq, n, dsub, NULL));

@@ -211,6 +211,33 @@ def test_training_trajectory_matches_oracle(cfg1):
         s.destroy()
 
 
+def test_graph_replays_equal_eager_steps(cfg1):
+    """Training steps replayed from the recorded graph give the parameters and
+    per-step losses of the same steps launched one by one, with other GPU work
+    and synchronisations between the calls."""
+    g, m = cfg1
+    x, q2 = synth.config1_queries(n=16384, seed=37)
+    xd, qd = dev(x), dev(q2)
+    runs = {}
+    for use_graph in (False, True):
+        s = pdfmi.Surrogate(m, seed=29)
+        try:
+            s.set_data(xd, qd)
+            losses = []
+            for c in range(4):
+                loss = torch.zeros(10, dtype=torch.float32, device=DEV)
+                s.train(10, 512, 3e-3, 3e-4, 40, loss_out=loss, use_graph=use_graph)
+                a = torch.randn(256, 256, device=DEV)
+                (a @ a).sum().item()        # eager work and a synchronisation between replays
+                losses.append(loss.cpu().numpy())
+            runs[use_graph] = (s.params(), np.concatenate(losses))
+        finally:
+            s.destroy()
+    assert np.array_equal(runs[False][0], runs[True][0])
+    assert np.array_equal(runs[False][1], runs[True][1])
+    assert runs[True][1][-1] < runs[True][1][0]
+
+
 def test_inference_matches_oracle_forward(cfg1):
     g, m = cfg1
     s = pdfmi.Surrogate(m, seed=11)
