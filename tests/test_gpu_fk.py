@@ -41,6 +41,24 @@ def test_contract_matches_oracle(nrep, ndat, K):
     check(pdf, table, out)
 
 
+@pytest.mark.parametrize("nrep", [400, 1000])
+def test_contract_full_size_sampled(nrep):
+    """The benchmarked shape (a 2415-point x grid times 13 flavours against a
+    1024-row table), in the launch configuration the library picks for it
+    (80-row member tiles at 400 members, 64-row at 1000; K split into slices):
+    sampled member rows against the oracle, every table row."""
+    ndat, K = 1024, 2415 * 13
+    print("fk full size: nrep %d ndat %d K %d" % (nrep, ndat, K), flush=True)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(nrep)
+    pdf = torch.randn((nrep, K), dtype=torch.float64, device=DEV, generator=g)
+    table = torch.randn((ndat, K), dtype=torch.float64, device=DEV, generator=g)
+    out = pdfmi.fk_contract(pdf, table).cpu().numpy()
+    rows = np.unique(np.concatenate([[0, 15, 16, 63, 64, 79, 80, nrep - 1],
+                                     np.random.default_rng(nrep).integers(0, nrep, 8)]))
+    check(pdf[rows].cpu().numpy(), table.cpu().numpy(), out[rows])
+
+
 def test_contract_deterministic_and_empty():
     rng = np.random.default_rng(7)
     p, t = dev(rng.normal(size=(77, 4000))), dev(rng.normal(size=(90, 4000)))

@@ -66,7 +66,7 @@ def test_noalloc_single_slice_and_empty():
 
 
 def test_noalloc_rejects_partials_beyond_scratch():
-    # 640 x 12800 outputs in 10 x 100 tiles of 64 x 128: two K slices of 65.5 MB of partial sums
+    # 640 x 12800 outputs in 8 x 100 tiles of 80 x 128: more than one K slice of 65.5 MB of partial sums
     nrep, ndat, K = 640, 12800, 1024
     print("noalloc: oversize %d x %d x %d must be rejected" % (nrep, ndat, K), flush=True)
     pdf = torch.ones((nrep, K), dtype=torch.float64, device=DEV)
