@@ -39,8 +39,11 @@ constexpr int kSurMaxEnvKnots = 512;   // the inference kernel stages the envelo
 constexpr int kAlphasMaxHints = 2048;  // alpha_s search hints staged in LDS
 int sur_out_width();
 int sur_hidden();
+int sur_slices(int B);
+size_t sur_workspace_floats(int B);
+hipError_t sur_train_prepare();
 hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, float* loss_out,
-                                const SurStep* st, hipStream_t s);
+                                hipStream_t s);
 hipError_t sur_train_begin(const SurBufs& b, int64_t step, int64_t nbatches, int total, float lr0, float lrf,
                            float* loss_out, hipStream_t s);
 hipError_t sur_train_step(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s);
@@ -1063,7 +1066,7 @@ struct Surrogate {
   SurDev sd{};
   SurBufs b{};
   void* pmem = nullptr;      // parameters, moments, gradients, envelope tables
-  void* bmem = nullptr;      // batch activations (sized for bcap)
+  void* bmem = nullptr;      // training workspace (sized for batches of up to bcap rows)
   int bcap = 0;
   float* d_in = nullptr;     // training inputs [n][2]
   float* d_t = nullptr;      // training targets [n][kO]
@@ -1142,32 +1145,10 @@ int sur_ensure_batch(Surrogate& S, int B) {
   if (B <= S.bcap) return PDF_OK;
   if (S.bmem) (void)hipFree(S.bmem);
   S.bmem = nullptr;
-  const int H = sur_hidden(), O = sur_out_width();
-  // floats: h1,h2,h3,dh,dz (B*H each) + y,dy,sq (B*O each);
-  // shorts: h1b,h2b,h3b,h1l,h2l,h3l,dzb (B*H), dyb (B*O)
-  const size_t nw = (size_t)64 * H * H;  // split-reduction partials
-  const size_t nf = (size_t)B * (5 * H + 3 * O) + nw, ns = (size_t)B * (7 * H + O);
-  hipError_t e = hipMalloc(&S.bmem, nf * 4 + ns * 2 + 256);
+  // the fused training step's per-slice partial gradients and losses
+  hipError_t e = hipMalloc(&S.bmem, sur_workspace_floats(B) * 4);
   if (e != hipSuccess) return fail_hip(e, "hipMalloc(surrogate batch)");
-  float* f = static_cast<float*>(S.bmem);
-  S.b.wpart = f; f += nw;
-  S.b.h1 = f; f += (size_t)B * H;
-  S.b.h2 = f; f += (size_t)B * H;
-  S.b.h3 = f; f += (size_t)B * H;
-  S.b.dh = f; f += (size_t)B * H;
-  S.b.dz = f; f += (size_t)B * H;
-  S.b.y = f; f += (size_t)B * O;
-  S.b.dy = f; f += (size_t)B * O;
-  S.b.sq = f; f += (size_t)B * O;
-  unsigned short* h = reinterpret_cast<unsigned short*>(f);
-  S.b.h1b = h; h += (size_t)B * H;
-  S.b.h2b = h; h += (size_t)B * H;
-  S.b.h3b = h; h += (size_t)B * H;
-  S.b.h1l = h; h += (size_t)B * H;
-  S.b.h2l = h; h += (size_t)B * H;
-  S.b.h3l = h; h += (size_t)B * H;
-  S.b.dzb = h; h += (size_t)B * H;
-  S.b.dyb = h;
+  S.b.wpart = static_cast<float*>(S.bmem);
   S.bcap = B;
   return PDF_OK;
 }
@@ -1279,7 +1260,6 @@ extern "C" int pdf_surrogate_create(int32_t member, uint64_t seed, int32_t* sid_
   float* envddev = reinterpret_cast<float*>(b + 4 * bp + bpb + be);
   double* lxkd = reinterpret_cast<double*>(b + 4 * bp + bpb + 2 * be);
   S.b.loss = reinterpret_cast<float*>(b + 4 * bp + bpb + 2 * be + bl);
-  S.b.partial = S.b.loss + 64;
   S.b.st = reinterpret_cast<SurStep*>(b + 4 * bp + bpb + 2 * be + bl + 2048);
   S.sd.env = envdev;
   S.sd.envd = envddev;
@@ -1394,7 +1374,9 @@ extern "C" int pdf_surrogate_train(int32_t sid, const pdf_train_opts* opts, pdf_
   hipStream_t s = (hipStream_t)stream;
   const int64_t nb = S->n_train / batch;
   if (steps == 0) return PDF_OK;
-  hipError_t e = sur_train_begin(S->b, S->step, nb, opts->total_steps, opts->lr, opts->lr_final, opts->loss_out, s);
+  hipError_t e = sur_train_prepare();
+  if (e != hipSuccess) return fail_hip(e, "surrogate training set-up");
+  e = sur_train_begin(S->b, S->step, nb, opts->total_steps, opts->lr, opts->lr_final, opts->loss_out, s);
   if (e != hipSuccess) return fail_hip(e, "surrogate training start");
   if (opts->use_graph) {
     if (!S->exec || S->g_batch != batch || S->g_in != S->d_in || S->g_bmem != S->bmem) {
@@ -1438,7 +1420,7 @@ extern "C" int pdf_surrogate_grad(int32_t sid, const float* in, const float* tar
   int rc = sur_ensure_batch(*S, batch);
   if (rc != PDF_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = sur_forward_backward(S->b, in, target, batch, loss_out, nullptr, s);
+  hipError_t e = sur_forward_backward(S->b, in, target, batch, loss_out, s);
   if (e == hipSuccess) e = hipMemcpyAsync(grad_out, S->b.G, (size_t)sur_nparams() * 4, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return fail_hip(e, "surrogate gradient");
   return PDF_OK;

@@ -177,19 +177,17 @@ struct SurStep {
   int total;         // cosine schedule length
   float lr0, lrf;    // schedule end points
   float* loss_out;   // the call's per-step losses, or null
+  unsigned done;     // workgroups of the step's update kernel that have finished (the last one advances the step)
 };
 
-// Surrogate device buffers (parameters, Adam moments, gradients, batch activations).
+// Surrogate device buffers (parameters, Adam moments, gradient, training workspace).
 // Matrix operands are BF16 pairs (hi, lo) with value = hi + lo.
 struct SurBufs {
   float* P;                 // FP32 master parameters
   unsigned short* Pb;       // BF16 halves of the parameters: [0, n) hi, [n, 2n) lo
-  float *M, *V, *G;         // Adam moments, gradients
-  float *h1, *h2, *h3, *y, *dy, *dh, *dz, *sq;
-  unsigned short *h1b, *h2b, *h3b, *h1l, *h2l, *h3l, *dyb, *dzb;
+  float *M, *V, *G;         // Adam moments, gradient
   float* loss;              // [1]
-  float* partial;           // [256]
-  float* wpart;             // split-reduction partial sums, 64 slices x 64 x 64
+  float* wpart;             // per-slice partial gradients and losses of a training step
   SurStep* st;              // training-call state
 };
 

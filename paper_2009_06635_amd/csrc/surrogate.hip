@@ -19,10 +19,9 @@
 // the grid and in the first/last x or Q^2 cell of a sub-grid (which includes
 // the cells next to flavour thresholds).
 //
-// Training is deterministic: every reduction has a fixed order (one wave per
-// 16x16 output tile loops over the whole batch; bias sums are sequential per
-// column), so a checkpointed and resumed run reproduces a straight run bit for
-// bit.
+// Training is deterministic: every reduction has a fixed order (within a
+// 64-row slice of the batch, then the slices in order), so a checkpointed and
+// resumed run reproduces a straight run bit for bit.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -69,149 +68,347 @@ __device__ __forceinline__ float tanh_scaled(float zs) {
 __device__ __forceinline__ float tanh_f(float z) { return tanh_scaled(kTwoLog2e * z); }
 
 // ---------------------------------------------------------------------------------------
-// Generic BF16 GEMM tile: C[m][n] = sum_k A(m,k) B(k,n) (+ bias[n]) (then tanh)
-// A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (BF16 bit patterns);
-// with A2 / B2 (the lo halves of split operands, same strides) the products
-// are A B + A2 B + A B2.  M, N multiples of 16; K any (zero padded to 32).
-// One wave per 16x16 tile, K walked in order (fixed summation order).
-// Writes FP32 C (ldc) and, if Cb != null, its BF16 hi half (and the lo half
-// to Cl if not null).
-// With gridDim.y > 1 workgroup y covers k in [y kchunk, (y + 1) kchunk) and
-// writes its partial tile to C + y M ldc (the slices are added in order by
-// k_sum_slices); bias and activation then belong to the unsplit form only.
-__global__ __launch_bounds__(64) void k_gemm_bf16(const unsigned short* __restrict__ A,
-                                                  const unsigned short* __restrict__ A2, int sam, int sak,
-                                                  const unsigned short* __restrict__ B,
-                                                  const unsigned short* __restrict__ B2, int sbk, int sbn,
-                                                  float* __restrict__ C, int ldc, unsigned short* __restrict__ Cb,
-                                                  unsigned short* __restrict__ Cl, int M, int N, int K,
-                                                  const float* __restrict__ bias, int act, int kchunk) {
-  const int tn = N / 16;
-  const int m0 = (blockIdx.x / tn) * 16, n0 = (blockIdx.x % tn) * 16;
-  const int l = threadIdx.x, r = l & 15, g = l >> 4;
-  const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
-  C += (int64_t)blockIdx.y * M * ldc;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kb; k0 < ke; k0 += 32) {
-    bf16x8 a, b, a2, b2;
+// Training step, fused into two launches.  k_train_fb: one workgroup of four
+// waves per 64-row slice of the batch runs the forward and backward passes
+// of its rows (wave w owns rows 16 w .. 16 w + 15; hidden activations stay in
+// registers and LDS) and writes the slice's gradient and its sum of squared
+// errors to the workspace.  k_train_update (k_grad_reduce without the
+// update) adds the slices in slice order and applies Adam.
+//
+// Matrix products on v_mfma_f32_16x16x32_bf16: lane l = 16 g + r holds
+// A(row r, k = 8 g .. 8 g + 7) and B(k = 8 g .. 8 g + 7, column r) of a
+// 32-deep step and receives C(rows 4 g .. 4 g + 3, column r).  The forward
+// products take the three split terms per k step (hi*hi, lo*hi, hi*lo) and
+// walk k in order; the backward products multiply BF16 (hi) signals with the
+// hi halves.  Weight gradients sum over the slice's 64 rows in two k steps,
+// bias gradients (and the FP32 first-layer weight gradient) over each lane's
+// four rows, then lanes g = 0..3 of waves 0..3 in that order.
+//
+// LDS tiles of BF16 with 64 columns are rows of 128 bytes whose 16-byte
+// chunks are rotated by (row & 7), so that the 16-byte operand reads of eight
+// lanes on consecutive rows hit eight different chunk positions; tiles of 16
+// columns (32-byte rows) swap their two chunks on rows 4..7 of every eight.
+constexpr int kTRows = 64, kTWaves = 4, kTThreads = 64 * kTWaves;
+constexpr int kNPad = (kNParams + 1 + 63) / 64 * 64;  // workspace stride per slice: gradient, then the loss sum
+
+__device__ __forceinline__ int swz64(int row, int col) {
+  return row * 128 + ((((col >> 3) ^ row) & 7) << 4) + ((col & 7) << 1);
+}
+__device__ __forceinline__ int swz16(int row, int col) {
+  return row * 32 + ((((col >> 3) ^ (row >> 2)) & 1) << 4) + ((col & 7) << 1);
+}
+__device__ __forceinline__ bf16x8 ld8(const unsigned char* base, int off) {
+  return *reinterpret_cast<const bf16x8*>(base + off);
+}
+__device__ __forceinline__ void st_bf16(unsigned char* base, int off, unsigned short v) {
+  *reinterpret_cast<unsigned short*>(base + off) = v;
+}
+// four consecutive columns c .. c + 3 (c a multiple of 4) of one row
+__device__ __forceinline__ void st4_bf16(unsigned char* base, int off, const unsigned short v[4]) {
+  *reinterpret_cast<uint2*>(base + off) =
+      make_uint2((unsigned)v[0] | ((unsigned)v[1] << 16), (unsigned)v[2] | ((unsigned)v[3] << 16));
+}
+
+// Byte offsets of the LDS regions of k_train_fb.
+constexpr int kT64 = 64 * 64 * 2, kT16 = 64 * 16 * 2;
+constexpr int kLW2h = 0, kLW2l = kLW2h + kT64, kLW3h = kLW2l + kT64, kLW3l = kLW3h + kT64;  // W[n][k]
+constexpr int kLW2t = kLW3l + kT64, kLW3t = kLW2t + kT64;                                   // W^T[k][n], hi
+constexpr int kLW4h = kLW3t + kT64, kLW4l = kLW4h + kT16, kLW4t = kLW4l + kT16;           // W4[o][k]; W4^T[k][o]
+constexpr int kLAh0 = kLW4t + kT16, kLAl0 = kLAh0 + kT64, kLAh1 = kLAl0 + kT64, kLAl1 = kLAh1 + kT64;  // layer inputs
+constexpr int kLH1t = kLAl1 + kT64, kLH2t = kLH1t + kT64, kLH3t = kLH2t + kT64;  // activations^T [unit][row], hi
+constexpr int kLDz = kLH3t + kT64, kLDzt = kLDz + kT64;                          // dz [row][unit], dz^T, hi
+constexpr int kLDy = kLDzt + kT64, kLDyt = kLDy + kT16;                          // dy [row][o], dy^T [o][row]
+constexpr int kLIn = kLDyt + kT16;                                               // in [row][2], FP32
+constexpr int kLRed = kLIn + kTRows * 2 * 4;                                     // [3][waves][4][64] FP32
+constexpr int kLLoss = kLRed + 3 * kTWaves * 4 * 64 * 4;                         // [threads] FP32
+constexpr int kTrainLds = kLLoss + kTThreads * 4;
+
+// The three split products of one 32-deep k step, in the order hi*hi, lo*hi, hi*lo.
+__device__ __forceinline__ f32x4 mfma3(bf16x8 a, bf16x8 al, bf16x8 b, bf16x8 bl, f32x4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, c, 0, 0, 0);
+}
+
+// Stores a hidden layer's outputs h (this lane's rows 4 g + i, columns 16 t + r)
+// as the next layer's split A operand and as hi^T for the weight gradient.
+__device__ __forceinline__ void store_hidden(unsigned char* L, int ah, int al, int ht, int R0, int g, int r,
+                                             const float h[4][4]) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = k0 + 8 * g + i;
-      const int64_t ia = (int64_t)(m0 + r) * sam + (int64_t)k * sak, ib = (int64_t)k * sbk + (int64_t)(n0 + r) * sbn;
-      a[i] = __builtin_bit_cast(__bf16, k < ke ? A[ia] : (unsigned short)0);
-      b[i] = __builtin_bit_cast(__bf16, k < ke ? B[ib] : (unsigned short)0);
-      a2[i] = __builtin_bit_cast(__bf16, (A2 && k < ke) ? A2[ia] : (unsigned short)0);
-      b2[i] = __builtin_bit_cast(__bf16, (B2 && k < ke) ? B2[ib] : (unsigned short)0);
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-    if (A2) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b, acc, 0, 0, 0);
-    if (B2) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b2, acc, 0, 0, 0);
-  }
+  for (int t = 0; t < 4; ++t) {
+    unsigned short hi[4], lo[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = m0 + 4 * g + i, n = n0 + r;
-    float v = acc[i];
-    if (bias) v += bias[n];
-    if (act) v = tanh_f(v);
-    C[(int64_t)m * ldc + n] = v;
-    if (Cb) {
-      unsigned short hi, lo;
-      split_bits(v, hi, lo);
-      Cb[(int64_t)m * ldc + n] = hi;
-      if (Cl) Cl[(int64_t)m * ldc + n] = lo;
+    for (int i = 0; i < 4; ++i) {
+      split_bits(h[t][i], hi[i], lo[i]);
+      st_bf16(L + ah, swz64(R0 + 4 * g + i, 16 * t + r), hi[i]);
+      st_bf16(L + al, swz64(R0 + 4 * g + i, 16 * t + r), lo[i]);
     }
+    st4_bf16(L + ht, swz64(16 * t + r, R0 + 4 * g), hi);
   }
 }
 
-// Layer 1 (K = 2, FP32 on the vector ALUs): h1 = tanh(W1 in + b1), FP32 and
-// its BF16 pair.
+// Hidden layer 2 or 3 forward: h = tanh(A W^T + b) for this wave's rows.
+__device__ __forceinline__ void hidden_fwd(const unsigned char* L, int ah, int al, int wh, int wl,
+                                           const float* __restrict__ bias, int R0, int g, int r, float h[4][4]) {
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k0 = 0; k0 < kH; k0 += 32) {
+    const bf16x8 a = ld8(L + ah, swz64(R0 + r, k0 + 8 * g)), a2 = ld8(L + al, swz64(R0 + r, k0 + 8 * g));
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      acc[t] = mfma3(a, a2, ld8(L + wh, swz64(16 * t + r, k0 + 8 * g)), ld8(L + wl, swz64(16 * t + r, k0 + 8 * g)),
+                     acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const float bv = bias[16 * t + r];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h[t][i] = tanh_f(acc[t][i] + bv);
+  }
+}
+
+// Weight gradient of a 64-unit layer for output units 16 w .. 16 w + 15:
+// dW[j][i] = sum over the slice's rows of dz[b][j] h[b][i] (hi operands).
+__device__ __forceinline__ void weight_grad(const unsigned char* L, int dzt, int ht, int w, int g, int r,
+                                            float* __restrict__ out) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < kTRows; k0 += 32)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(L + dzt, swz64(16 * w + r, k0 + 8 * g)),
+                                                    ld8(L + ht, swz64(16 * t + r, k0 + 8 * g)), acc, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[(16 * w + 4 * g + i) * kH + 16 * t + r] = acc[i];
+  }
+}
+
+// dh = dz W for this wave's rows (K = the 64 output units, W^T staged).
+__device__ __forceinline__ void input_grad(const unsigned char* L, int dz, int wt, int R0, int g, int r,
+                                           float dh[4][4]) {
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k0 = 0; k0 < kH; k0 += 32) {
+    const bf16x8 a = ld8(L + dz, swz64(R0 + r, k0 + 8 * g));
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ld8(L + wt, swz64(16 * t + r, k0 + 8 * g)), acc[t], 0, 0,
+                                                       0);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dh[t][i] = acc[t][i];
+}
+
+// dz = dh (1 - h^2) (tanh derivative) into dh; its hi halves to the dz and
+// dz^T tiles; this lane's sum over its four rows of each column to red[w][g].
+__device__ __forceinline__ void tanh_back(unsigned char* L, float* red, const float h[4][4], float dh[4][4],
+                                          int R0, int w, int g, int r) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    unsigned short hi[4];
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dh[t][i] = dh[t][i] * (1.0f - h[t][i] * h[t][i]);
+      hi[i] = bf16_bits(dh[t][i]);
+      st_bf16(L + kLDz, swz64(R0 + 4 * g + i, 16 * t + r), hi[i]);
+      s += dh[t][i];
+    }
+    st4_bf16(L + kLDzt, swz64(16 * t + r, R0 + 4 * g), hi);
+    red[(w * 4 + g) * 64 + 16 * t + r] = s;
+  }
+}
+
+// Column c's sum of red[w][g][c] over w = 0..3, g = 0..3 in that order.
+__device__ __forceinline__ float red_sum(const float* red, int c) {
+  float s = red[c];
+#pragma unroll
+  for (int q = 1; q < kTWaves * 4; ++q) s += red[q * 64 + c];
+  return s;
+}
+
 // Batch slice of a training step: rows (step % nb) * B of the training set
 // when st is given (in and T are then the set's first rows), else as passed.
 __device__ __forceinline__ int64_t batch_row(const SurStep* st, int B) {
   return st ? (st->step % st->nb) * (int64_t)B : 0;
 }
 
-__global__ void k_layer1(const float* __restrict__ in, const SurStep* __restrict__ st, const float* __restrict__ P,
-                         int B, float* __restrict__ h, unsigned short* __restrict__ hb,
-                         unsigned short* __restrict__ hl) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)B * kH) return;
-  in += 2 * batch_row(st, B);
-  const int b = (int)(i / kH), j = (int)(i % kH);
-  const float z = fmaf(P[kOffW1 + 2 * j], in[2 * b], fmaf(P[kOffW1 + 2 * j + 1], in[2 * b + 1], P[kOffB1 + j]));
-  const float t = tanh_f(z);
-  h[i] = t;
-  split_bits(t, hb[i], hl[i]);
-}
+__global__ __launch_bounds__(kTThreads) void k_train_fb(const float* __restrict__ in, const float* __restrict__ T,
+                                                        const SurStep* __restrict__ st, const float* __restrict__ P,
+                                                        const unsigned short* __restrict__ Pb, int B,
+                                                        float* __restrict__ ws) {
+  extern __shared__ __align__(16) unsigned char L[];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, g = lane >> 4;
+  const int R0 = 16 * w;
+  const int64_t row0 = batch_row(st, B) + (int64_t)blockIdx.x * kTRows;
+  const int nrow = min(kTRows, B - (int)blockIdx.x * kTRows);  // valid rows of this slice
+  float* out = ws + (int64_t)blockIdx.x * kNPad;
+  float* red = reinterpret_cast<float*>(L + kLRed);
 
-// Loss (mean squared error over B x kO) and its gradient dY = 2 (Y - T) / (B kO).
-__global__ void k_loss_grad(const float* __restrict__ Y, const float* __restrict__ T, const SurStep* __restrict__ st,
-                            int B, float* __restrict__ dY, unsigned short* __restrict__ dYb, float* __restrict__ sq) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)B * kO) return;
-  T += kO * batch_row(st, B);
-  const float d = Y[i] - T[i];
-  const float gr = 2.0f * d / (float)((int64_t)B * kO);
-  dY[i] = gr;
-  dYb[i] = bf16_bits(gr);
-  sq[i] = d * d;
-}
-
-// dZ = dH * (1 - H^2) (tanh derivative), FP32 and BF16.
-__global__ void k_tanh_back(const float* __restrict__ dH, const float* __restrict__ H, int64_t n,
-                            float* __restrict__ dZ, unsigned short* __restrict__ dZb) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float h = H[i];
-  const float v = dH[i] * (1.0f - h * h);
-  dZ[i] = v;
-  dZb[i] = bf16_bits(v);
-}
-
-// out[y][c] = sum over b in slice y of X[b][c] (sequential in b), for c < ncols;
-// slices of kchunk rows, one per blockIdx.y (added in order afterwards).
-__global__ void k_col_sum(const float* __restrict__ X, int B, int ncols, int kchunk, float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
-  const int b0 = blockIdx.y * kchunk, b1 = min(B, b0 + kchunk);
-  float s = 0.0f;
-#pragma unroll 16
-  for (int b = b0; b < b1; ++b) s += X[(int64_t)b * ncols + c];
-  out[(int64_t)blockIdx.y * ncols + c] = s;
-}
-
-// dW1[j][t] = sum_b dZ1[b][j] in[b][t] (FP32, in b order within a slice of
-// kchunk rows per blockIdx.y; slices added in order).
-__global__ void k_dw1(const float* __restrict__ dZ, const float* __restrict__ in, const SurStep* __restrict__ st,
-                      int B, int kchunk, float* __restrict__ dW1) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= kH * 2) return;
-  in += 2 * batch_row(st, B);
-  const int j = o / 2, t = o % 2;
-  const int b0 = blockIdx.y * kchunk, b1 = min(B, b0 + kchunk);
-  float s = 0.0f;
-#pragma unroll 16
-  for (int b = b0; b < b1; ++b) s = fmaf(dZ[(int64_t)b * kH + j], in[2 * b + t], s);
-  dW1[(int64_t)blockIdx.y * kH * 2 + o] = s;
-}
-
-// Adam step on the FP32 masters (Kingma & Ba, bias-corrected moments; c1 =
-// 1 - b1^t, c2 = 1 - b2^t for update number t), then their BF16 pairs.  With
-// st the update number is st->step + 1 and the learning rate follows the
-// cosine schedule lrf + (lr0 - lrf)(1 + cos(pi min(1, step / total))) / 2.
-__global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ Mm,
-                       float* __restrict__ Vm, unsigned short* __restrict__ Pb, int n, float lr, float b1, float b2,
-                       float eps, float c1, float c2, const SurStep* __restrict__ st) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (st) {
-    const double t = (double)st->step;
-    const double frac = fmin(1.0, t / (double)st->total);
-    lr = (float)(st->lrf + 0.5 * ((double)st->lr0 - st->lrf) * (1.0 + cos(3.141592653589793 * frac)));
-    c1 = (float)(1.0 - pow(0.9, t + 1.0));  // the betas in FP64, as the host computes them
-    c2 = (float)(1.0 - pow(0.999, t + 1.0));
+  // stage the weights: split W2, W3, W4 row-major; hi of W2^T, W3^T, W4^T
+  {
+    const unsigned short* Wh = Pb;
+    const unsigned short* Wl = Pb + kNParams;
+    for (int c = tid; c < 64 * 8; c += kTThreads) {  // 16-byte chunks of the 64 x 64 matrices
+      const int n = c >> 3, k = (c & 7) * 8;
+      const uint4 w2h = *reinterpret_cast<const uint4*>(Wh + kOffW2 + n * kH + k);
+      const uint4 w3h = *reinterpret_cast<const uint4*>(Wh + kOffW3 + n * kH + k);
+      *reinterpret_cast<uint4*>(L + kLW2h + swz64(n, k)) = w2h;
+      *reinterpret_cast<uint4*>(L + kLW2l + swz64(n, k)) = *reinterpret_cast<const uint4*>(Wl + kOffW2 + n * kH + k);
+      *reinterpret_cast<uint4*>(L + kLW3h + swz64(n, k)) = w3h;
+      *reinterpret_cast<uint4*>(L + kLW3l + swz64(n, k)) = *reinterpret_cast<const uint4*>(Wl + kOffW3 + n * kH + k);
+      const unsigned short* e2 = reinterpret_cast<const unsigned short*>(&w2h);
+      const unsigned short* e3 = reinterpret_cast<const unsigned short*>(&w3h);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        st_bf16(L + kLW2t, swz64(k + q, n), e2[q]);
+        st_bf16(L + kLW3t, swz64(k + q, n), e3[q]);
+      }
+    }
+    for (int c = tid; c < kO * 8; c += kTThreads) {  // W4: 16 rows of 8 chunks
+      const int o = c >> 3, k = (c & 7) * 8;
+      const uint4 w4h = *reinterpret_cast<const uint4*>(Wh + kOffW4 + o * kH + k);
+      *reinterpret_cast<uint4*>(L + kLW4h + swz64(o, k)) = w4h;
+      *reinterpret_cast<uint4*>(L + kLW4l + swz64(o, k)) = *reinterpret_cast<const uint4*>(Wl + kOffW4 + o * kH + k);
+      const unsigned short* e4 = reinterpret_cast<const unsigned short*>(&w4h);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) st_bf16(L + kLW4t, swz16(k + q, o), e4[q]);
+    }
+    float* sin = reinterpret_cast<float*>(L + kLIn);
+    if (tid < 2 * kTRows) sin[tid] = tid < 2 * nrow ? in[2 * row0 + tid] : 0.0f;
   }
-  const float g = G[i];
+  __syncthreads();
+  const float* sin = reinterpret_cast<const float*>(L + kLIn);
+
+  // layer 1 (FP32): h1[b][j] = tanh(W1[j][0] in[b][0] + W1[j][1] in[b][1] + b1[j])
+  float h1[4][4], h2[4][4], h3[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = 16 * t + r;
+    const float w0 = P[kOffW1 + 2 * j], w1 = P[kOffW1 + 2 * j + 1], bj = P[kOffB1 + j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = R0 + 4 * g + i;
+      h1[t][i] = tanh_f(fmaf(w0, sin[2 * b], fmaf(w1, sin[2 * b + 1], bj)));
+    }
+  }
+  store_hidden(L, kLAh0, kLAl0, kLH1t, R0, g, r, h1);
+  __syncthreads();
+  hidden_fwd(L, kLAh0, kLAl0, kLW2h, kLW2l, P + kOffB2, R0, g, r, h2);
+  store_hidden(L, kLAh1, kLAl1, kLH2t, R0, g, r, h2);
+  __syncthreads();
+  hidden_fwd(L, kLAh1, kLAl1, kLW3h, kLW3l, P + kOffB3, R0, g, r, h3);
+  store_hidden(L, kLAh0, kLAl0, kLH3t, R0, g, r, h3);
+  __syncthreads();
+
+  // layer 4 and the loss: y = h3 W4^T + b4; d = y - T; dy = 2 d / (B kO)
+  {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < kH; k0 += 32)
+      acc = mfma3(ld8(L + kLAh0, swz64(R0 + r, k0 + 8 * g)), ld8(L + kLAl0, swz64(R0 + r, k0 + 8 * g)),
+                  ld8(L + kLW4h, swz64(r, k0 + 8 * g)), ld8(L + kLW4l, swz64(r, k0 + 8 * g)), acc);
+    const float bo = P[kOffB4 + r];
+    const float scale = (float)((int64_t)B * kO);
+    unsigned short hi[4];
+    float sq = 0.0f, s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = R0 + 4 * g + i;
+      const float d = b < nrow ? (acc[i] + bo) - T[(row0 + b) * kO + r] : 0.0f;
+      const float gr = 2.0f * d / scale;
+      hi[i] = bf16_bits(gr);
+      st_bf16(L + kLDy, swz16(b, r), hi[i]);
+      sq += d * d;
+      s += gr;
+    }
+    st4_bf16(L + kLDyt, swz64(r, R0 + 4 * g), hi);
+    red[(w * 4 + g) * 64 + r] = s;
+    reinterpret_cast<float*>(L + kLLoss)[tid] = sq;
+  }
+  __syncthreads();
+
+  // layer 4 backward: dW4 (wave w: input units 16 w ..), db4, dh3 = dy W4
+  {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < kTRows; k0 += 32)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(L + kLDyt, swz64(r, k0 + 8 * g)),
+                                                    ld8(L + kLH3t, swz64(R0 + r, k0 + 8 * g)), acc, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[kOffW4 + (4 * g + i) * kH + R0 + r] = acc[i];
+  }
+  if (tid < kO) out[kOffB4 + tid] = red_sum(red, tid);
+  if (tid == 0) {
+    const float* ls = reinterpret_cast<const float*>(L + kLLoss);
+    float s = ls[0];
+    for (int q = 1; q < kTThreads; ++q) s += ls[q];
+    out[kNParams] = s;
+  }
+  float dh[4][4];
+  {
+    const bf16x8 zero = {};
+    const bf16x8 a = g < 2 ? ld8(L + kLDy, swz16(R0 + r, 8 * g)) : zero;  // K = 16 of 32
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bf16x8 bw = g < 2 ? ld8(L + kLW4t, swz16(16 * t + r, 8 * g)) : zero;
+      const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dh[t][i] = acc[i];
+    }
+  }
+  __syncthreads();  // red and the loss sums consumed
+
+  // layer 3 backward
+  tanh_back(L, red, h3, dh, R0, w, g, r);
+  __syncthreads();
+  weight_grad(L, kLDzt, kLH2t, w, g, r, out + kOffW3);
+  if (tid < kH) out[kOffB3 + tid] = red_sum(red, tid);
+  input_grad(L, kLDz, kLW3t, R0, g, r, dh);
+  __syncthreads();
+  // layer 2 backward
+  tanh_back(L, red, h2, dh, R0, w, g, r);
+  __syncthreads();
+  weight_grad(L, kLDzt, kLH1t, w, g, r, out + kOffW2);
+  if (tid < kH) out[kOffB2 + tid] = red_sum(red, tid);
+  input_grad(L, kLDz, kLW2t, R0, g, r, dh);
+  __syncthreads();
+  // layer 1 backward (FP32): dW1[j][t] = sum_b dz[b][j] in[b][t], db1
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    float s0 = 0.0f, s1 = 0.0f, sb = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = R0 + 4 * g + i;
+      const float dz = dh[t][i] * (1.0f - h1[t][i] * h1[t][i]);
+      s0 = fmaf(dz, sin[2 * b], s0);
+      s1 = fmaf(dz, sin[2 * b + 1], s1);
+      sb += dz;
+    }
+    const int q = (w * 4 + g) * 64 + 16 * t + r;
+    red[q] = s0;
+    red[kTWaves * 4 * 64 + q] = s1;
+    red[2 * kTWaves * 4 * 64 + q] = sb;
+  }
+  __syncthreads();
+  if (tid < kH) {
+    out[kOffW1 + 2 * tid] = red_sum(red, tid);
+    out[kOffW1 + 2 * tid + 1] = red_sum(red + kTWaves * 4 * 64, tid);
+    out[kOffB1 + tid] = red_sum(red + 2 * kTWaves * 4 * 64, tid);
+  }
+}
+
+// Adam step of parameter i (Kingma & Ba, bias-corrected moments; c1 = 1 -
+// b1^t, c2 = 1 - b2^t for update number t), then its BF16 pair.
+__device__ __forceinline__ void adam_update(int i, int n, float g, float lr, float b1, float b2, float eps, float c1,
+                                            float c2, float* __restrict__ P, float* __restrict__ Mm,
+                                            float* __restrict__ Vm, unsigned short* __restrict__ Pb) {
   const float m = b1 * Mm[i] + (1.0f - b1) * g;
   const float v = b2 * Vm[i] + (1.0f - b2) * g * g;
   Mm[i] = m;
@@ -219,6 +416,77 @@ __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float
   const float p = P[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
   P[i] = p;
   split_bits(p, Pb[i], Pb[n + i]);
+}
+
+// Learning rate and bias corrections of update number st->step + 1: cosine
+// schedule lrf + (lr0 - lrf)(1 + cos(pi min(1, step / total))) / 2; the
+// betas' powers in FP64, as the host computes them.
+__device__ __forceinline__ void schedule(const SurStep* st, float& lr, float& c1, float& c2) {
+  const double t = (double)st->step;
+  const double frac = fmin(1.0, t / (double)st->total);
+  lr = (float)(st->lrf + 0.5 * ((double)st->lr0 - st->lrf) * (1.0 + cos(3.141592653589793 * frac)));
+  c1 = (float)(1.0 - pow(0.9, t + 1.0));
+  c2 = (float)(1.0 - pow(0.999, t + 1.0));
+}
+
+// Adam with a given gradient G (pdf_surrogate_adam).
+__global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ Mm,
+                       float* __restrict__ Vm, unsigned short* __restrict__ Pb, int n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) adam_update(i, n, G[i], lr, b1, b2, eps, c1, c2, P, Mm, Vm, Pb);
+}
+
+// Gradient i = sum over the S slices of the workspace, in slice order.
+__device__ __forceinline__ float slice_sum(const float* __restrict__ ws, int S, int i) {
+  float g = ws[i];
+  for (int q = 1; q < S; ++q) g += ws[(int64_t)q * kNPad + i];
+  return g;
+}
+
+// The gradient and loss of k_train_fb's slices (no update).
+__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ ws, int S, float* __restrict__ G,
+                                                     float inv_n, float* __restrict__ loss,
+                                                     float* __restrict__ loss_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kNParams) G[i] = slice_sum(ws, S, i);
+  if (i == 0) {
+    const float l = slice_sum(ws, S, kNParams) * inv_n;
+    *loss = l;
+    if (loss_out) *loss_out = l;
+  }
+}
+
+// Gradient of the slices, Adam at the scheduled rate, and -- in the last
+// workgroup to finish -- the step's loss and the advance of the step state.
+__global__ __launch_bounds__(256) void k_train_update(const float* __restrict__ ws, int S, float* __restrict__ P,
+                                                      float* __restrict__ G, float* __restrict__ Mm,
+                                                      float* __restrict__ Vm, unsigned short* __restrict__ Pb,
+                                                      float inv_n, float* __restrict__ loss, SurStep* st) {
+  __shared__ int last;
+  float lr, c1, c2;
+  schedule(st, lr, c1, c2);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kNParams) {
+    const float g = slice_sum(ws, S, i);
+    G[i] = g;
+    adam_update(i, kNParams, g, lr, 0.9f, 0.999f, 1e-8f, c1, c2, P, Mm, Vm, Pb);
+  }
+  __syncthreads();  // every thread of this workgroup has read the step state
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(&st->done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    const float l = slice_sum(ws, S, kNParams) * inv_n;
+    *loss = l;
+    if (st->loss_out) st->loss_out[st->call] = l;
+    st->step += 1;
+    st->call += 1;
+    st->done = 0;
+  }
 }
 
 // Start of a training call: the global step, the call's step index, the schedule and the loss output.
@@ -231,12 +499,7 @@ __global__ void k_train_begin(SurStep* st, int64_t step, int64_t nb, int total, 
   st->lr0 = lr0;
   st->lrf = lrf;
   st->loss_out = loss_out;
-}
-
-// End of a training step.
-__global__ void k_train_advance(SurStep* st) {
-  st->step += 1;
-  st->call += 1;
+  st->done = 0;
 }
 
 __global__ void k_to_bf16(const float* __restrict__ P, unsigned short* __restrict__ Pb, int n) {
@@ -649,138 +912,28 @@ int sur_hidden() { return kH; }
 
 static unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// out[i] = sum over slices s = 0..S-1 (in order) of P[s n + i].
-__global__ void k_sum_slices(const float* __restrict__ P, int S, int n, float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float acc = P[i];
-  for (int q = 1; q < S; ++q) acc += P[(int64_t)q * n + i];
-  out[i] = acc;
+// Slices of a batch of B rows in the fused training step, and the workspace
+// (floats) their partial gradients and losses take.
+int sur_slices(int B) { return (B + kTRows - 1) / kTRows; }
+size_t sur_workspace_floats(int B) { return (size_t)sur_slices(B) * kNPad; }
+
+// LDS limit of the fused step; called before a step is first launched or recorded.
+hipError_t sur_train_prepare() {
+  return allow_dynamic_lds(reinterpret_cast<const void*>(&k_train_fb), kTrainLds);
 }
 
-// Long reductions (the weight gradients, K = batch) are split into slices of
-// kSplitK rows so that the few 16x16 output tiles keep many waves busy.
-constexpr int kSplitK = 256;
-constexpr int kMaxSlices = 64;
-
-// C = A B (A2, B2: lo halves of split operands, or null), see k_gemm_bf16.
-static void gemm(const unsigned short* A, const unsigned short* A2, int sam, int sak, const unsigned short* B,
-                 const unsigned short* B2, int sbk, int sbn, float* C, int ldc, unsigned short* Cb,
-                 unsigned short* Cl, int M, int N, int K, const float* bias, int act, float* ws, hipStream_t s) {
-  const unsigned tiles = (unsigned)((M / 16) * (N / 16));
-  int S = (K + kSplitK - 1) / kSplitK;
-  if (S > kMaxSlices) S = kMaxSlices;
-  if (S > 1 && !bias && !act && !Cb && ws && ldc == N) {
-    const int kchunk = ((K + S - 1) / S + 31) / 32 * 32;
-    S = (K + kchunk - 1) / kchunk;
-    hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles, (unsigned)S), dim3(64), 0, s, A, A2, sam, sak, B, B2, sbk, sbn, ws,
-                       ldc, nullptr, nullptr, M, N, K, nullptr, 0, kchunk);
-    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, s, ws, S, M * N, C);
-    return;
-  }
-  hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles), dim3(64), 0, s, A, A2, sam, sak, B, B2, sbk, sbn, C, ldc, Cb, Cl, M, N,
-                     K, bias, act, K);
-}
-
-// Sum of 256 per-thread values of a 256-thread block by a fixed pairwise tree
-// (the same order on every call); the result is valid in thread 0.
-__device__ float block_tree_sum(float v, float* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  return red[0];
-}
-
-// 256 blocks of 256 threads: block j sums its contiguous share of x, its
-// threads striding through it (coalesced), into partial[j].
-__global__ void k_sum_partial(const float* __restrict__ x, int64_t n, float* __restrict__ partial) {
-  __shared__ float red[256];
-  const int64_t per = (n + 255) / 256;
-  const int64_t b = blockIdx.x * per, e = min(b + per, n);
-  float s = 0.0f;
-  for (int64_t i = b + threadIdx.x; i < e; i += 256) s += x[i];
-  s = block_tree_sum(s, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-__global__ void k_sum_final(const float* __restrict__ partial, float scale, float* __restrict__ out,
-                            float* __restrict__ out2, const SurStep* __restrict__ st) {
-  __shared__ float red[256];
-  const float s = block_tree_sum(partial[threadIdx.x], red);
-  if (threadIdx.x == 0) {
-    *out = s * scale;
-    if (out2) *out2 = s * scale;
-    if (st && st->loss_out) st->loss_out[st->call] = s * scale;
-  }
-}
-
-// Column sums and the first-layer weight gradient over the batch, in row
-// slices of at least kColRows rows added in order (a thread per column and
-// slice: short slices give the few columns enough waves to hide latency).
-constexpr int kColRows = 64;
-static void col_sum(const float* X, int B, int ncols, float* out, float* ws, hipStream_t s) {
-  const int S = min(kMaxSlices, (B + kColRows - 1) / kColRows);
-  const int kchunk = (B + S - 1) / S;
-  hipLaunchKernelGGL(k_col_sum, dim3((unsigned)((ncols + 63) / 64), (unsigned)S), dim3(64), 0, s, X, B, ncols, kchunk,
-                     ws);
-  hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, ws, S, ncols, out);
-}
-
-static void dw1(const float* dZ, const float* in, const SurStep* st, int B, float* out, float* ws, hipStream_t s) {
-  const int S = min(kMaxSlices, (B + kColRows - 1) / kColRows);
-  const int kchunk = (B + S - 1) / S;
-  hipLaunchKernelGGL(k_dw1, dim3(1, (unsigned)S), dim3(128), 0, s, dZ, in, st, B, kchunk, ws);
-  hipLaunchKernelGGL(k_sum_slices, dim3(1), dim3(256), 0, s, ws, S, kH * 2, out);
-}
-
-// One forward + backward pass on a batch (inputs in[B][2], targets T[B][kO];
-// with st, the step's slice of the training set starting at in, T): gradients
-// into buf.G, loss (mean squared error) into buf.loss and, if not null,
-// *loss_out (and the call's loss_out entry of st).
+// One forward + backward pass on a batch (inputs in[B][2], targets T[B][kO])
+// with no update: gradient into buf.G, loss (mean squared error) into
+// buf.loss and, if not null, *loss_out.
 hipError_t sur_forward_backward(const SurBufs& b, const float* in, const float* T, int B, float* loss_out,
-                                const SurStep* st, hipStream_t s) {
-  const unsigned short* Wh = b.Pb;              // hi halves
-  const unsigned short* Wl = b.Pb + kNParams;   // lo halves
-  hipLaunchKernelGGL(k_layer1, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, in, st, b.P, B, b.h1, b.h1b, b.h1l);
-  // z = h W^T + b: A(m=b,k) = h[b][k]; B(k,n) = W[n][k]; split operands
-  gemm(b.h1b, b.h1l, kH, 1, Wh + kOffW2, Wl + kOffW2, 1, kH, b.h2, kH, b.h2b, b.h2l, B, kH, kH, b.P + kOffB2, 1,
-       b.wpart, s);
-  gemm(b.h2b, b.h2l, kH, 1, Wh + kOffW3, Wl + kOffW3, 1, kH, b.h3, kH, b.h3b, b.h3l, B, kH, kH, b.P + kOffB3, 1,
-       b.wpart, s);
-  gemm(b.h3b, b.h3l, kH, 1, Wh + kOffW4, Wl + kOffW4, 1, kH, b.y, kO, nullptr, nullptr, B, kO, kH, b.P + kOffB4, 0,
-       b.wpart, s);
-  hipLaunchKernelGGL(k_loss_grad, dim3(nb((int64_t)B * kO, 256)), dim3(256), 0, s, b.y, T, st, B, b.dy, b.dyb,
-                     b.sq);
-  hipLaunchKernelGGL(k_sum_partial, dim3(256), dim3(256), 0, s, b.sq, (int64_t)B * kO, b.partial);
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, b.partial, 1.0f / (float)((int64_t)B * kO), b.loss,
-                     loss_out, st);
-  // backward on the hi halves: layer 4: dW4[o][i] = sum_b dy[b][o] h3[b][i]; db4; dh3 = dy W4
-  gemm(b.dyb, nullptr, 1, kO, b.h3b, nullptr, kH, 1, b.G + kOffW4, kH, nullptr, nullptr, kO, kH, B, nullptr, 0,
-       b.wpart, s);
-  col_sum(b.dy, B, kO, b.G + kOffB4, b.wpart, s);
-  gemm(b.dyb, nullptr, kO, 1, Wh + kOffW4, nullptr, kH, 1, b.dh, kH, nullptr, nullptr, B, kH, kO, nullptr, 0, b.wpart,
-       s);
-  // layers 3 and 2
-  const float* Hs[3] = {b.h1, b.h2, b.h3};
-  const unsigned short* Hbs[3] = {b.h1b, b.h2b, b.h3b};
-  const int offW[2] = {kOffW2, kOffW3}, offB[2] = {kOffB2, kOffB3};
-  for (int L = 1; L >= 0; --L) {  // L = 1: layer 3 (input h2, output h3); L = 0: layer 2 (h1 -> h2)
-    hipLaunchKernelGGL(k_tanh_back, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, b.dh, Hs[L + 1],
-                       (int64_t)B * kH, b.dz, b.dzb);
-    gemm(b.dzb, nullptr, 1, kH, Hbs[L], nullptr, kH, 1, b.G + offW[L], kH, nullptr, nullptr, kH, kH, B, nullptr, 0,
-         b.wpart, s);
-    col_sum(b.dz, B, kH, b.G + offB[L], b.wpart, s);
-    // dh_in = dz W: A(m=b, k=j) = dz[b][j]; B(k=j, n=i) = W[j][i]
-    gemm(b.dzb, nullptr, kH, 1, Wh + offW[L], nullptr, kH, 1, b.dh, kH, nullptr, nullptr, B, kH, kH, nullptr, 0,
-         b.wpart, s);
-  }
-  // layer 1 (FP32)
-  hipLaunchKernelGGL(k_tanh_back, dim3(nb((int64_t)B * kH, 256)), dim3(256), 0, s, b.dh, b.h1, (int64_t)B * kH, b.dz,
-                     b.dzb);
-  dw1(b.dz, in, st, B, b.G + kOffW1, b.wpart, s);
-  col_sum(b.dz, B, kH, b.G + kOffB1, b.wpart, s);
+                                hipStream_t s) {
+  hipError_t e = sur_train_prepare();
+  if (e != hipSuccess) return e;
+  const int S = sur_slices(B);
+  hipLaunchKernelGGL(k_train_fb, dim3((unsigned)S), dim3(kTThreads), kTrainLds, s, in, T, (const SurStep*)nullptr,
+                     b.P, b.Pb, B, b.wpart);
+  hipLaunchKernelGGL(k_grad_reduce, dim3(nb(kNParams, 256)), dim3(256), 0, s, b.wpart, S, b.G,
+                     1.0f / (float)((int64_t)B * kO), b.loss, loss_out);
   return hipGetLastError();
 }
 
@@ -788,7 +941,7 @@ hipError_t sur_adam(const SurBufs& b, float lr, int step, hipStream_t s) {
   const double b1 = 0.9, b2 = 0.999;
   const float c1 = (float)(1.0 - pow(b1, step)), c2 = (float)(1.0 - pow(b2, step));
   hipLaunchKernelGGL(k_adam, dim3(nb(kNParams, 256)), dim3(256), 0, s, b.P, b.G, b.M, b.V, b.Pb, kNParams, lr,
-                     (float)b1, (float)b2, 1e-8f, c1, c2, (const SurStep*)nullptr);
+                     (float)b1, (float)b2, 1e-8f, c1, c2);
   return hipGetLastError();
 }
 
@@ -800,14 +953,16 @@ hipError_t sur_train_begin(const SurBufs& b, int64_t step, int64_t nbatches, int
 }
 
 // One training step on the slice of the training set (in, T) that b.st
-// selects: forward + backward, Adam at the scheduled learning rate, advance.
-// The same launches at every step (recorded once as a graph by the caller).
+// selects: the fused forward + backward pass, then the slice sums, Adam at
+// the scheduled learning rate and the step advance.  The same two launches
+// at every step (recorded once as a graph by the caller); sur_train_prepare
+// must have run.
 hipError_t sur_train_step(const SurBufs& b, const float* in, const float* T, int B, hipStream_t s) {
-  hipError_t e = sur_forward_backward(b, in, T, B, nullptr, b.st, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adam, dim3(nb(kNParams, 256)), dim3(256), 0, s, b.P, b.G, b.M, b.V, b.Pb, kNParams, 0.0f,
-                     0.9f, 0.999f, 1e-8f, 1.0f, 1.0f, (const SurStep*)b.st);
-  hipLaunchKernelGGL(k_train_advance, dim3(1), dim3(1), 0, s, b.st);
+  const int S = sur_slices(B);
+  hipLaunchKernelGGL(k_train_fb, dim3((unsigned)S), dim3(kTThreads), kTrainLds, s, in, T, (const SurStep*)b.st, b.P,
+                     b.Pb, B, b.wpart);
+  hipLaunchKernelGGL(k_train_update, dim3(nb(kNParams, 256)), dim3(256), 0, s, b.wpart, S, b.P, b.G, b.M, b.V, b.Pb,
+                     1.0f / (float)((int64_t)B * kO), b.loss, b.st);
   return hipGetLastError();
 }
 
