@@ -46,6 +46,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # L2 read bandwidth of the chip: 8 XCDs x 16 channels x 128 B per clock at 2.4 GHz
 L2_PEAK_GBS = 8 * 16 * 128 * 2.4
+# vector L1 (texture) path: 256 compute units x 64 B per clock at 2.4 GHz
+L1_PEAK_GBS = 256 * 64 * 2.4
 
 
 def kernel_source_sha():
@@ -86,6 +88,9 @@ def main():
                     help="run a 1 GiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--sur-steps", type=int, default=20000)
     ap.add_argument("--mc-chunks", type=int, default=100)
+    ap.add_argument("--locality", action="store_true",
+                    help="also measure the headline kernel on cell-sorted points, with the sort and the "
+                         "scatter back to point order (what a cell-binned variant would cost)")
     ap.add_argument("--settle-ms", type=float, default=300.0,
                     help="untimed run of each timed step before its warm-up steps, so that the GPU "
                          "clocks have ramped up whatever --warmup is")
@@ -226,19 +231,25 @@ def main():
                      "frac": ach64 / HBM_PEAK_GBS, "traffic": measured_traffic("xfxq2_f64"),
                      "kernel": "k_xfxq2<double> with alpha_s output (pdf_xfxq2_alphas)", "kernel_ms": k64,
                      "algorithmic_bytes_per_launch": bytes64,
-                     # the ceiling that binds: every point gathers its 4 x 4 stencil, 16 grid rows of
-                     # 16 FP64 columns = 16 x 128-byte L2 lines, from the L2-resident grid
+                     # the gather behind the HBM figure: every point reads its 4 x 4 stencil, 16 grid
+                     # rows of 13 FP64 columns, as 16 x 128-byte lines from the L2-resident grid and as
+                     # 16 rows x 7 lanes x 16 bytes through each compute unit's vector-memory (L1) path
                      "l2_gather": {"achieved": 16 * 128 * args.n / (k64 * 1e-3) / 1e9, "peak": L2_PEAK_GBS,
                                    "unit": "GB/s", "frac": 16 * 128 * args.n / (k64 * 1e-3) / 1e9 / L2_PEAK_GBS,
-                                   "bytes_per_point": 16 * 128}},
+                                   "bytes_per_point": 16 * 128},
+                     "l1_gather": {"achieved": 16 * 7 * 16 * args.n / (k64 * 1e-3) / 1e9, "peak": L1_PEAK_GBS,
+                                   "unit": "GB/s", "frac": 16 * 7 * 16 * args.n / (k64 * 1e-3) / 1e9 / L1_PEAK_GBS,
+                                   "bytes_per_point": 16 * 7 * 16}},
         "variants": {
             "f64_kernel_evals_per_s": evals / (k64 * 1e-3),
             "f32": {"value": evals / wall32, "ms_per_step": wall32 * 1e3, "kernel_ms": k32,
                     "kernel_evals_per_s": evals / (k32 * 1e-3), "achieved_GBs": ach32,
                     "frac": ach32 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes32,
                     "speedup_vs_f64_kernel": k64 / k32,
-                    # FP32 rows of 16 columns: the 4 rows of one x knot's Q^2 window span 2-3 lines
-                    "l2_gather_frac": 4 * 2.5 * 128 * args.n / (k32 * 1e-3) / 1e9 / L2_PEAK_GBS},
+                    # FP32 rows of 16 columns: the 4 rows of one x knot's Q^2 window span 2-3 lines;
+                    # through the L1 path 16 rows x 4 lanes x 16 bytes
+                    "l2_gather_frac": 4 * 2.5 * 128 * args.n / (k32 * 1e-3) / 1e9 / L2_PEAK_GBS,
+                    "l1_gather_frac": 16 * 4 * 16 * args.n / (k32 * 1e-3) / 1e9 / L1_PEAK_GBS},
         },
     }
     V = res["variants"]
@@ -274,6 +285,38 @@ def main():
         "f64": parity(out64[sidx_t].cpu().numpy(), 1e-12, None, 4 * eps64, True, 0.0),
         "f32": parity(out32[sidx_t].cpu().numpy(), 1e-5, None, 4 * eps32, False, 1e-8)}
     del out32
+
+    if args.locality:
+        # What binning the points by grid cell could gain: the same kernel on the points sorted by
+        # stencil cell (neighbouring lanes and waves then share grid lines, which the L1 cache
+        # serves instead of L2), and what binning costs on top -- the sort of the cell keys and the
+        # scatter of the output rows back to the caller's point order.
+        log("locality: the headline points sorted by stencil cell")
+        qall = np.concatenate(g.q2knots)
+        key = np.searchsorted(qall, q2).astype(np.int64) * (len(g.xknots[0]) + 1) + np.searchsorted(g.xknots[0], x)
+        perm = np.argsort(key, kind="stable")
+        xs_d, qs_d = torch.from_numpy(x[perm]).to(dev), torch.from_numpy(q2[perm]).to(dev)
+        perm_d, key_d = torch.from_numpy(perm).to(dev), torch.from_numpy(key).to(dev)
+        outs, as_s = torch.empty_like(out64), torch.empty_like(aout)
+
+        def step_sorted(e):
+            if e:
+                e[0].record()
+            pdfmi.xfxq2_alphas(member, g.pids, xs_d, qs_d, out=outs, alphas_out=as_s)
+            if e:
+                e[1].record()
+        wall_s, k_s = timed(step_sorted, args.steps, args.warmup)
+        ref = out64.clone()
+        t_scatter = dtime(lambda: (out64.index_copy_(0, perm_d, outs), aout.index_copy_(0, perm_d, as_s)), reps=5)
+        t_sort = dtime(lambda: torch.sort(key_d, stable=True), reps=5)
+        same = bool(torch.equal(out64.view(torch.int64), ref.view(torch.int64)))
+        del ref, outs, as_s
+        V["locality"] = {
+            "sorted_kernel_ms": k_s, "unsorted_kernel_ms": k64, "scatter_to_point_order_ms": t_scatter,
+            "key_sort_ms": t_sort, "binned_total_ms": k_s + t_scatter + t_sort,
+            "scattered_output_equals_unsorted": same,
+            "note": "sorted kernel + scatter back + key sort against the unsorted kernel; a counting sort "
+                    "in a kernel of its own would replace torch's sort"}
 
     if not args.only_headline:
         import oracle
