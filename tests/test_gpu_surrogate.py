@@ -127,7 +127,7 @@ def forward_bound(p, inp, y):
     return 2.0 ** -17 * sensitivity(p, inp) + 1e-5 * (np.abs(y) + 0.05)
 
 
-@pytest.mark.parametrize("B", [16, 48, 256, 4096])
+@pytest.mark.parametrize("B", [16, 48, 80, 208, 256, 4096])
 def test_gradients_match_oracle(cfg1, B):
     g, m = cfg1
     s = pdfmi.Surrogate(m, seed=7)
@@ -211,7 +211,8 @@ def test_training_trajectory_matches_oracle(cfg1):
         s.destroy()
 
 
-def test_graph_replays_equal_eager_steps(cfg1):
+@pytest.mark.parametrize("B", [208, 512])
+def test_graph_replays_equal_eager_steps(cfg1, B):
     """Training steps replayed from the recorded graph give the parameters and
     per-step losses of the same steps launched one by one, with other GPU work
     and synchronisations between the calls."""
@@ -226,7 +227,7 @@ def test_graph_replays_equal_eager_steps(cfg1):
             losses = []
             for c in range(4):
                 loss = torch.zeros(10, dtype=torch.float32, device=DEV)
-                s.train(10, 512, 3e-3, 3e-4, 40, loss_out=loss, use_graph=use_graph)
+                s.train(10, B, 3e-3, 3e-4, 40, loss_out=loss, use_graph=use_graph)
                 a = torch.randn(256, 256, device=DEV)
                 (a @ a).sum().item()        # eager work and a synchronisation between replays
                 losses.append(loss.cpu().numpy())
