@@ -162,6 +162,8 @@ int pdf_validate_alphas(int32_t n_knots, const double* q2_knots, const double* a
  * each workgroup's LDS (160 KB per CU on gfx950) when it fits.
  *   0 = automatic (stage when it fits and the call has enough points to pay
  *       for one grid copy per workgroup), 1 = never, 2 = whenever it fits.
+ * A batch plan takes the policy in force when it is created: 1 reads the
+ * grids from global memory, 0 and 2 stage them whenever the largest fits.
  * Results are identical under every policy.
  */
 int pdf_set_lds_policy(int32_t policy);

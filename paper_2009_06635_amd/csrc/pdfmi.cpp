@@ -885,8 +885,9 @@ extern "C" int pdf_batch_create(const pdf_request* reqs, int32_t n_req, int32_t 
     b.n = q.n;
     P.reqs.push_back(b);
   }
-  P.lds = batch_shared_bytes(P.max_tbl, !P.out_f64, true) + (size_t)P.max_elems * (P.out_f64 ? 8 : 4) <=
-          kLdsBytes - 1024;
+  P.lds = g_lds_policy != 1 &&
+          batch_shared_bytes(P.max_tbl, !P.out_f64, true) + (size_t)P.max_elems * (P.out_f64 ? 8 : 4) <=
+              kLdsBytes - 1024;
   P.blocks_per_cu = 1;
   const size_t br = align_up(sizeof(BatchReq) * std::max<size_t>(1, P.reqs.size()), 256);
   const size_t bc = align_up(sizeof(int) * std::max<size_t>(1, P.cols.size()), 256);

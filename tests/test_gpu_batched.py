@@ -82,6 +82,30 @@ def test_batched_equals_per_request_and_oracle(members, out_f64):
         plan.destroy()
 
 
+@pytest.mark.parametrize("out_f64", [False, True])
+def test_plan_without_lds_grid_is_identical(members, out_f64):
+    """A plan created under the never-stage policy reads the member grids from
+    global memory; its outputs equal those of a plan that stages them in LDS."""
+    grids, ids = members
+    outs = {}
+    for policy in (2, 1):
+        pdfmi.set_lds_policy(policy)
+        try:
+            reqs, _ = make_requests(grids, ids, out_f64, seed=5)
+            plan = pdfmi.BatchPlan(reqs, out_f64=out_f64)
+        finally:
+            pdfmi.set_lds_policy(0)
+        try:
+            plan.configure(tile_points=1024, vector_cols=1)
+            plan.run()
+            torch.cuda.synchronize()
+            outs[policy] = [torch.nan_to_num(r[4], nan=123.0).clone() for r in reqs]
+        finally:
+            plan.destroy()
+    for a, b in zip(outs[2], outs[1]):
+        assert torch.equal(a, b)
+
+
 def test_graph_replay_matches_eager(members):
     grids, ids = members
     reqs, host = make_requests(grids, ids, False, seed=2)
