@@ -231,8 +231,12 @@ int pdf_batch_run(int32_t plan, pdf_stream_t stream);
  */
 int pdf_batch_autotune(int32_t plan, int32_t reps, pdf_stream_t stream, int32_t* tile_out, int32_t* vector_out);
 int pdf_batch_destroy(int32_t plan);
-/* One-shot: create, run, synchronise stream, destroy. */
-int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, int32_t out_f64, pdf_stream_t stream);
+/* One-shot: create a plan with FP32 outputs (the FP32 bulk path of many
+ * members), run it on stream, synchronise stream, destroy it.  Errors as
+ * pdf_batch_create / pdf_batch_run; nothing is written when creation fails. */
+int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, pdf_stream_t stream);
+/* The same with FP64 outputs (every out pointer a double[n][n_pids]). */
+int pdf_xfxq2_batched_f64(const pdf_request* reqs, int32_t n_req, pdf_stream_t stream);
 
 /*
  * MLP surrogate of one member's PDFs (an alternative evaluator grown on top

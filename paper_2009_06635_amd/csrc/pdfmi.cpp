@@ -1042,7 +1042,8 @@ extern "C" int pdf_batch_destroy(int32_t plan) {
   return PDF_OK;
 }
 
-extern "C" int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, int32_t out_f64, pdf_stream_t stream) {
+namespace {
+int batched_one_shot(const pdf_request* reqs, int32_t n_req, int32_t out_f64, pdf_stream_t stream) {
   int32_t plan = -1;
   int rc = pdf_batch_create(reqs, n_req, out_f64, &plan);
   if (rc != PDF_OK) return rc;
@@ -1053,6 +1054,15 @@ extern "C" int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, int32_t
   }
   pdf_batch_destroy(plan);
   return rc;
+}
+}  // namespace
+
+extern "C" int pdf_xfxq2_batched(const pdf_request* reqs, int32_t n_req, pdf_stream_t stream) {
+  return batched_one_shot(reqs, n_req, 0, stream);
+}
+
+extern "C" int pdf_xfxq2_batched_f64(const pdf_request* reqs, int32_t n_req, pdf_stream_t stream) {
+  return batched_one_shot(reqs, n_req, 1, stream);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -43,7 +43,8 @@ _SIGS = {
     "pdf_batch_run": [_i32, _P],
     "pdf_batch_autotune": [_i32, _i32, _P, _P, _P],
     "pdf_batch_destroy": [_i32],
-    "pdf_xfxq2_batched": [_P, _i32, _i32, _P],
+    "pdf_xfxq2_batched": [_P, _i32, _P],
+    "pdf_xfxq2_batched_f64": [_P, _i32, _P],
     "pdf_surrogate_param_count": [_P],
     "pdf_surrogate_create": [_i32, ctypes.c_uint64, _P],
     "pdf_surrogate_destroy": [_i32],
@@ -360,25 +361,32 @@ class _Request(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("q2", ctypes.c_void_p), ("n", ctypes.c_int64), ("out", ctypes.c_void_p)]
 
 
+def _request_array(requests, out_f64, keep):
+    """ctypes array of pdf_request for [(member, pids, x, q2, out), ...]; the
+    objects it points into are appended to keep."""
+    arr = (_Request * max(1, len(requests)))()
+    for i, (member, pids, x, q2, out) in enumerate(requests):
+        _dev_f64(x, "x")
+        _dev_f64(q2, "q2")
+        want = torch.float64 if out_f64 else torch.float32
+        if not (out.is_cuda and out.dtype == want and out.is_contiguous()):
+            raise TypeError("out must be a contiguous %s CUDA tensor" % want)
+        pa, npid = _pid_arg(pids)
+        if pa is not None:
+            keep.append(pa)
+        keep.append((x, q2, out))
+        arr[i] = _Request(int(member), npid, _ptr(pa) if pa is not None else None, x.data_ptr(),
+                          q2.data_ptr(), x.shape[0], out.data_ptr())
+    return arr
+
+
 class BatchPlan:
     """A batched plan over requests [(member, pids, x, q2, out), ...] with
     device tensors x, q2 (float64) and out (float32, or float64 if out_f64)."""
 
     def __init__(self, requests, out_f64=False):
         self._keep = []
-        arr = (_Request * max(1, len(requests)))()
-        for i, (member, pids, x, q2, out) in enumerate(requests):
-            _dev_f64(x, "x")
-            _dev_f64(q2, "q2")
-            want = torch.float64 if out_f64 else torch.float32
-            if not (out.is_cuda and out.dtype == want and out.is_contiguous()):
-                raise TypeError("out must be a contiguous %s CUDA tensor" % want)
-            pa, npid = _pid_arg(pids)
-            if pa is not None:
-                self._keep.append(pa)
-            self._keep.append((x, q2, out))
-            arr[i] = _Request(int(member), npid, _ptr(pa) if pa is not None else None, x.data_ptr(),
-                              q2.data_ptr(), x.shape[0], out.data_ptr())
+        arr = _request_array(requests, out_f64, self._keep)
         self._reqs = arr
         pid = ctypes.c_int32(-1)
         _check(_lib.pdf_batch_create(ctypes.cast(arr, _P), len(requests), 1 if out_f64 else 0, ctypes.byref(pid)))
@@ -402,13 +410,12 @@ class BatchPlan:
 
 
 def xfxq2_batched(requests, out_f64=False, stream=None):
-    """One-shot batched evaluation (synchronises the stream)."""
-    plan = BatchPlan(requests, out_f64)
-    try:
-        plan.run(stream)
-        (torch.cuda.current_stream() if stream is None else stream).synchronize()
-    finally:
-        plan.destroy()
+    """One-shot batched evaluation (pdf_xfxq2_batched / pdf_xfxq2_batched_f64;
+    synchronises the stream)."""
+    keep = []
+    arr = _request_array(requests, out_f64, keep)
+    fn = _lib.pdf_xfxq2_batched_f64 if out_f64 else _lib.pdf_xfxq2_batched
+    _check(fn(ctypes.cast(arr, _P), len(requests), _stream(stream)))
 
 
 def surrogate_param_count():

@@ -146,6 +146,21 @@ def test_autotune_keeps_results(members):
         plan.destroy()
 
 
+@pytest.mark.parametrize("out_f64", [False, True])
+def test_one_shot_equals_per_request(members, out_f64):
+    """pdf_xfxq2_batched (FP32 outputs) and pdf_xfxq2_batched_f64 against the
+    per-request calls, bit for bit."""
+    grids, ids = members
+    reqs, host = make_requests(grids, ids, out_f64, seed=6, sizes=(100, 5, 3000, 0))
+    pdfmi.xfxq2_batched(reqs, out_f64=out_f64)
+    for (m, pids, x, q2, out), (mi, _, _, _) in zip(reqs, host):
+        if x.shape[0] == 0:
+            continue
+        fn = pdfmi.xfxq2 if out_f64 else pdfmi.xfxq2_f32
+        ref = fn(m, pids, x, q2, n_cols=len(grids[mi].pids))
+        assert torch.equal(torch.nan_to_num(out, nan=123.0), torch.nan_to_num(ref, nan=123.0))
+
+
 def test_one_shot_and_errors(members):
     grids, ids = members
     reqs, _ = make_requests(grids, ids, False, seed=4, sizes=(100, 5))
