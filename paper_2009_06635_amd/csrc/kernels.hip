@@ -793,10 +793,14 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
         x2 = X2[i];
         q2 = Q2[i];
       }
-      T w1[4], v1[4], w2[4], v2[4];
+      // Q^2 weights: the shared location's.  locate_x copies them for a valid
+      // point (and zeros them for an invalid one, whose value is NaN before
+      // any weight is read), so both lookups read them from Qs.
+      T w1[4], w2[4], vx[4];
       const QLoc<T> Qs = locate_q<T>(m, tb, q2);  // shared Q^2: located once for both lookups
-      const PointLoc L1 = locate_x<T>(m, tb, Qs, x1, w1, v1);
-      const PointLoc L2 = locate_x<T>(m, tb, Qs, x2, w2, v2);
+      const PointLoc L1 = locate_x<T>(m, tb, Qs, x1, w1, vx);
+      const PointLoc L2 = locate_x<T>(m, tb, Qs, x2, w2, vx);
+      const T* v = Qs.v;
       const double as = alphas_point(A, ask, asv, asc, ash, q2);
       const bool bad1 = live && (L1.mode & kInvalid), bad2 = live && (L2.mode & kInvalid);
       const bool bada = live && !(q2 > 0.0 && q2 < INFINITY);
@@ -806,11 +810,38 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
       mc_origin(tb, soff, L1, P, b1, sa1);
       mc_origin(tb, soff, L2, P, b2, sa2);
       double lum = 0.0;
-      if (!((L1.mode | L2.mode) & (kLowX | kLowQ | kHighQ))) {
+      if (kLdsGrid && !((L1.mode | L2.mode) & (kLowX | kLowQ | kHighQ))) {
+        // both lookups inside the LDS-staged grid: the values mc_value gives,
+        // with both stencils' reads issued together and no branch per point
+        // (an invalid point reads the in-bounds stencil at offset 0 and takes
+        // NaN); from global memory the 32 loads in flight would spill
+        const bool inv1 = L1.mode & kInvalid, inv2 = L2.mode & kInvalid;
+        for (int j = 0; j < R; ++j) {
+          const int col = __builtin_amdgcn_readfirstlane(scol[j]);
+          T f1 = (T)0, f2 = (T)0;
+          if (col >= 0) {
+            T F1[4][4], F2[4][4];
+            const T* g1 = grid + b1 + col;
+            const T* g2 = grid + b2 + col;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                F1[a][b] = g1[a * sa1 + b * P];
+                F2[a][b] = g2[a * sa2 + b * P];
+              }
+            f1 = interp_stencil<T>(F1, w1, v);
+            f2 = interp_stencil<T>(F2, w2, v);
+          }
+          f1 = inv1 ? (T)NAN : f1;
+          f2 = inv2 ? (T)NAN : f2;
+          lum = fma((double)f1, (double)f2, lum);
+        }
+      } else if (!((L1.mode | L2.mode) & (kLowX | kLowQ | kHighQ))) {
         for (int j = 0; j < R; ++j) {
           const int col = scol[j];
-          const T f1 = mc_value<T, false>(grid + b1 + col, L1, w1, v1, sa1, P, col, invL01);
-          const T f2 = mc_value<T, false>(grid + b2 + col, L2, w2, v2, sa2, P, col, invL01);
+          const T f1 = mc_value<T, false>(grid + b1 + col, L1, w1, v, sa1, P, col, invL01);
+          const T f2 = mc_value<T, false>(grid + b2 + col, L2, w2, v, sa2, P, col, invL01);
           lum = fma((double)f1, (double)f2, lum);
         }
       } else {
@@ -818,8 +849,8 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
         // extrapolation formulas
         for (int j = 0; j < R; ++j) {
           const int col = scol[j];
-          const T f1 = mc_value<T, true>(grid + b1 + col, L1, w1, v1, sa1, P, col, invL01);
-          const T f2 = mc_value<T, true>(grid + b2 + col, L2, w2, v2, sa2, P, col, invL01);
+          const T f1 = mc_value<T, true>(grid + b1 + col, L1, w1, v, sa1, P, col, invL01);
+          const T f2 = mc_value<T, true>(grid + b2 + col, L2, w2, v, sa2, P, col, invL01);
           lum = fma((double)f1, (double)f2, lum);
         }
       }
