@@ -294,19 +294,25 @@ __device__ __forceinline__ PointLoc locate_x(const MemberDev& m, const Tables& t
   return L;
 }
 
+// a^b for a > 0 as exp(b ln a): the bases here are positive ratios, and a
+// few ulps of exp and log stay far inside the FP64 parity bound, at a
+// fraction of the general pow's cost (the extrapolated points of a tile run
+// these formulas on a few of the wave's lanes).
+__device__ __forceinline__ double pos_pow(double a, double b) { return exp(b * log(a)); }
 // Two-anchor continuation (log-linear when both anchors exceed 1e-3).
 __device__ __forceinline__ double cont_low(double f0, double f1, double s) {
-  return (f0 > 1e-3 && f1 > 1e-3) ? f0 * pow(f1 / f0, s) : f0 + s * (f1 - f0);
+  return (f0 > 1e-3 && f1 > 1e-3) ? f0 * pos_pow(f1 / f0, s) : f0 + s * (f1 - f0);
 }
 __device__ __forceinline__ double cont_high(double f0, double f1, double s) {
-  return (f0 > 1e-3 && f1 > 1e-3) ? f1 * pow(f1 / f0, s) : f1 + s * (f1 - f0);
+  return (f0 > 1e-3 && f1 > 1e-3) ? f1 * pos_pow(f1 / f0, s) : f1 + s * (f1 - f0);
 }
 // Below Q^2_min: f0 * r^(gamma r + 1 - r), gamma from the first two Q^2 knots.
 __device__ __forceinline__ double low_q(double f0, double f1, double r, double invL01, bool xhigh) {
   const bool use_gamma = f0 > 1e-5 && f1 > 1e-5 && !xhigh;
   if (!use_gamma) return f0 * r;
+  const double lr = log(r);
   const double gamma = log(f1 / f0) * invL01;
-  return f0 * pow(r, gamma * r + 1.0 - r);
+  return f0 * exp((gamma * r + 1.0 - r) * lr);
 }
 
 // Extrapolated value from anchor values (rare path, FP64 combination):
