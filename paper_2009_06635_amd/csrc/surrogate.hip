@@ -633,7 +633,8 @@ struct FbRec {
 constexpr size_t kSurWaveArea = 2 * 16 * kH * 2;  // 4096 bytes
 constexpr size_t kSurWTile = (size_t)2 * (2 * kH * kH + kO * kH);  // one half of W2, W3, W4 (BF16)
 __host__ __device__ static inline size_t sur_head_bytes(int nx) {
-  const size_t b = (kWeightsInLds ? 2 : 1) * kSurWTile + (size_t)8 * nx + (size_t)4 * (2 * nx * kO + 2 * kH + 3 * kH + kO);
+  const size_t b = (kWeightsInLds ? 2 : 1) * kSurWTile + (size_t)8 * nx +
+                   (size_t)4 * (2 * nx * kO + 2 * kH + 3 * kH + kO + kMaxReq);
   return (b + 15) & ~(size_t)15;
 }
 constexpr size_t kSurWaveBytes = kSurWaveArea + 64 * kSurRec * 4;
@@ -671,6 +672,7 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
   float* sb2 = sb1 + kH;
   float* sb3 = sb2 + kH;
   float* sb4 = sb3 + kH;                                   // [kO]
+  int* scol = reinterpret_cast<int*>(sb4 + kO);            // [kMaxReq] stored column of each requested flavour
   unsigned char* waves = sraw + sur_head_bytes(S.nx);
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
   unsigned char* area = waves + (size_t)wv * kSurWaveArea;
@@ -692,6 +694,7 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
     sb3[i] = kTwoLog2e * Pf[kOffB3 + i];
   }
   for (int i = threadIdx.x; i < kO; i += BS) sb4[i] = Pf[kOffB4 + i];
+  for (int i = threadIdx.x; i < rc.n; i += BS) scol[i] = rc.col[i];
   const unsigned short* Pl = Pb + kNParams;  // lo halves
   for (int i = threadIdx.x; i < kH * kH; i += BS) {
     const int row = i / kH, col = i % kH;
@@ -834,12 +837,13 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // requested columns of the network's points, point-major
       const int nq = min(16, np - q0);
-      for (int e = l; e < nq * R; e += 64) {
-        const int pt = e / R, j = e - pt * R;
-        if (rec[(q0 + pt) * kSurRec + 7] == 0.0f) {
-          const int c = rc.col[j];
-          out[(p0 + q0 + pt) * R + j] = c >= 0 ? so[pt * kO + c] : 0.0f;
-        }
+      // lane (point l / 16 + 4 k, requested flavour j0 + l % 16), flavours in chunks of 16: no division
+      for (int j0 = 0; j0 < R; j0 += 16) {
+        const int j = j0 + (l & 15);
+        const int c = j < R ? scol[j] : -1;
+        for (int pt = l >> 4; pt < nq; pt += 4)
+          if (j < R && rec[(q0 + pt) * kSurRec + 7] == 0.0f)
+            out[(p0 + q0 + pt) * R + j] = c >= 0 ? so[pt * kO + c] : 0.0f;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -868,7 +872,7 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
       for (int e = l; e < nfb * R; e += 64) {
         const int k = e / R, j = e - k * R;
         const FbRec& fr = fbr[k];
-        const int c = rc.col[j];
+        const int c = scol[j];
         float val;
         if (fr.mode & kInvalid) {
           val = NAN;
