@@ -91,6 +91,49 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int voff, co
   }
 }
 
+// Workgroup copy of `bytes` (a multiple of 4; both pointers 16-byte
+// aligned) from global memory to LDS.  Each thread issues eight 16-byte loads
+// before it stores them: a loop of dependent load-store pairs waits out the
+// memory latency once per element (a 72 KB grid: 18 round trips per thread).
+template <int BS>
+__device__ __forceinline__ void stage_copy(void* dst, const void* src, int64_t bytes) {
+  const u32x4* s = static_cast<const u32x4*>(src);
+  u32x4* d = static_cast<u32x4*>(dst);
+  const int64_t nv = bytes >> 4;
+  for (int64_t i0 = threadIdx.x; i0 < nv; i0 += 8 * BS) {
+    u32x4 r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = s[min(i0 + k * BS, nv - 1)];  // clamped: every load in bounds
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (i0 + k * BS < nv) d[i0 + k * BS] = r[k];
+  }
+  const int tail = (int)((bytes & 15) >> 2);  // trailing 4-byte words
+  if ((int)threadIdx.x < tail)
+    reinterpret_cast<unsigned*>(d + nv)[threadIdx.x] = reinterpret_cast<const unsigned*>(s + nv)[threadIdx.x];
+}
+
+// Workgroup copy of rows x P elements from rows of stride Ps (global) into
+// rows of stride P (LDS), eight loads in flight per thread.
+template <int BS, typename T>
+__device__ __forceinline__ void stage_rows(T* dst, const T* src, int rows, int P, int Ps) {
+  const int ne = rows * P;
+  for (int e0 = threadIdx.x; e0 < ne; e0 += 8 * BS) {
+    T r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = min(e0 + k * BS, ne - 1);  // clamped: every load in bounds
+      const int row = e / P;
+      r[k] = src[(int64_t)row * Ps + (e - row * P)];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = e0 + k * BS;
+      if (e < ne) dst[e] = r[k];
+    }
+  }
+}
+
 // x*f for a set of flavours; see file header.  out is point-major [n][R].
 // Each wave works on its own 64-point tiles with no workgroup barrier after
 // the initial staging, so the knot searches and log transforms of some waves
@@ -321,16 +364,11 @@ void k_xfxq2(MemberDev m, ReqCols rc, const double* __restrict__ X, const double
     for (int i = threadIdx.x; i < A.nhints; i += BS) h[i] = A.hints[i];
   }
 
-  if constexpr (kLdsTables) {
-    const uint4* src = reinterpret_cast<const uint4*>(m.tables);
-    for (int i = threadIdx.x; i < m.tbl_bytes / 16; i += BS) reinterpret_cast<uint4*>(stbl)[i] = src[i];
-  }
+  if constexpr (kLdsTables) stage_copy<BS>(stbl, m.tables, m.tbl_bytes);
   for (int i = threadIdx.x; i < rc.n; i += BS) scol[i] = rc.col[i];
   const T* __restrict__ gvals = member_values<T>(m);
   const uint32_t gbytes = (uint32_t)((sizeof(T) == 8 ? m.elems64 : m.elems32) * (int64_t)sizeof(T));
-  if constexpr (kLdsGrid) {
-    for (int i = threadIdx.x; i < lds_grid_elems; i += BS) sgrid[i] = gvals[i];
-  }
+  if constexpr (kLdsGrid) stage_copy<BS>(sgrid, gvals, (int64_t)lds_grid_elems * (int64_t)sizeof(T));
   __syncthreads();
   const Tables tb = kLdsTables ? tables_at(stbl, m) : Tables{m.knots, m.cells, m.hints, m.subs};
 
@@ -739,10 +777,7 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
   int* soff = scol + kMaxReq;                             // [kMaxSub] staged sub-grid offsets
   T* sgrid = reinterpret_cast<T*>(soff + kMaxSub);        // 16-byte aligned: kMaxReq + kMaxSub ints
 
-  {
-    const uint4* src = reinterpret_cast<const uint4*>(m.tables);
-    for (int i = threadIdx.x; i < m.tbl_bytes / 16; i += kMcFusedBS) reinterpret_cast<uint4*>(stbl)[i] = src[i];
-  }
+  stage_copy<kMcFusedBS>(stbl, m.tables, m.tbl_bytes);
   for (int i = threadIdx.x; i < A.n; i += kMcFusedBS) {
     ask[i] = A.knots[i];
     asv[i] = A.vals[i];
@@ -765,11 +800,7 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
     for (int k = 0; k < m.K; ++k) {
       const SubDesc& S = m.sub[k];
       const int rows = S.nxp * S.nqp;
-      const T* src = gvals + (sizeof(T) == 8 ? S.val_off64 : S.val_off32);
-      for (int e = threadIdx.x; e < rows * m.P; e += kMcFusedBS) {
-        const int r = e / m.P, c = e - r * m.P;
-        sgrid[off + e] = src[(int64_t)r * Pp + c];
-      }
+      stage_rows<kMcFusedBS>(sgrid + off, gvals + (sizeof(T) == 8 ? S.val_off64 : S.val_off32), rows, m.P, Pp);
       off += rows * m.P;
     }
   }
@@ -965,14 +996,8 @@ __global__ __launch_bounds__(kBatchBS) void k_batched(const BatchReq* __restrict
     const T* __restrict__ gvals = member_values<T>(m);
     const uint32_t gbytes = (uint32_t)((sizeof(T) == 8 ? m.elems64 : m.elems32) * (int64_t)sizeof(T));
     if (rq.member != s_member) {
-      if constexpr (kLdsTables) {
-        const uint4* src = reinterpret_cast<const uint4*>(m.tables);
-        for (int i = threadIdx.x; i < m.tbl_bytes / 16; i += kBatchBS) reinterpret_cast<uint4*>(stbl)[i] = src[i];
-      }
-      if constexpr (kLdsGrid) {
-        const int64_t ne = sizeof(T) == 8 ? m.elems64 : m.elems32;
-        for (int64_t i = threadIdx.x; i < ne; i += kBatchBS) sgrid[i] = gvals[i];
-      }
+      if constexpr (kLdsTables) stage_copy<kBatchBS>(stbl, m.tables, m.tbl_bytes);
+      if constexpr (kLdsGrid) stage_copy<kBatchBS>(sgrid, gvals, (int64_t)gbytes);
     }
     for (int i = threadIdx.x; i < rq.R; i += kBatchBS) scol[i] = cols[rq.col_off + i];
     __syncthreads();
