@@ -591,31 +591,36 @@ __global__ void k_gather_samples(const float* __restrict__ in_all, const float* 
 // ---------------------------------------------------------------------------------------
 // Fused inference.  Each wave takes 64 consecutive points: their inputs,
 // fallback flags and envelope weights are prepared one lane per point, then
-// the network runs on four 16-point sub-tiles: layer 1 on the VALUs straight
-// into the A-operand layout of layer 2 (as BF16 pairs); layers 2-4 on the
-// matrix cores, three products per operand pair, with the hi halves of the
-// weight fragments held in registers and the lo halves read from LDS; hidden
-// activations re-laid out from the accumulator layout to the A-operand layout
-// through LDS.  The outputs times the envelope go to a 16 x 16 LDS tile from
-// which the requested columns are stored point-major, consecutive lanes on
-// consecutive values.  Points in the fallback domain are then evaluated by
-// the FP32 interpolator: each is located once (one lane per point: sub-grid,
-// cells, weights), after which one lane per (point, requested column)
-// gathers its 4x4 stencil.
+// the network runs on four 16-point sub-tiles with the activations kept in
+// registers from layer to layer.  Each layer is formed transposed on the
+// matrix cores, h' = tanh(W h + b) with the weights as the A operand and the
+// 16 points' activations as the B operand, three products per operand pair:
+// lane (r, g) then receives units 16 t + 4 g + i (t, i = 0..3) of point r,
+// which are the 16 values it supplies to the next layer's B operand when
+// that layer's 64-deep k index k' = 32 s + 8 g + i stands for unit
+// kunit(k') = 16 (2 s + i / 4) + 4 g + i % 4.  The weight columns are staged
+// in LDS in that order (once per workgroup), so no activation passes through
+// LDS.  Layer 1 (two inputs) runs on the VALUs straight into that layout.
+// The outputs times the envelope go to a 16 x 16 LDS tile from which the
+// requested columns are stored point-major, consecutive lanes on consecutive
+// values.  Points in the fallback domain are then evaluated by the FP32
+// interpolator: each is located once (one lane per point: sub-grid, cells,
+// weights), after which one lane per (point, requested column) gathers its
+// 4x4 stencil.
 //
-// LDS rows of 64 BF16 values (the activation tiles, the lo weight halves)
-// hold their eight 16-byte chunks in the order chunk ^ (row & 7), so the 16
-// rows an operand read touches spread over the banks.
-// Launch shapes: with the hi weight fragments in registers (kWeightsInLds =
-// false) a wave needs ~200 VGPRs (2 waves per SIMD, blocks of 4 waves); with
-// both halves of the weights in LDS it fits 128 VGPRs and blocks of 16 waves
-// fill the CU's LDS (4 waves per SIMD).
-constexpr bool kWeightsInLds = true;
-constexpr int kSurWaves = kWeightsInLds ? 16 : 4;
+// LDS rows of 64 BF16 values (the weight halves) hold their eight 16-byte
+// chunks in the order chunk ^ (row & 7), so the 16 rows an operand read
+// touches spread over the banks.  Blocks of 16 waves fill the CU's LDS
+// (4 waves per SIMD, at most 128 VGPRs).
+constexpr int kSurWaves = 16;
 constexpr int kSurRec = 8;   // floats per point record: u, v, h00, h10 D, h01, h11 D, cell, fallback
 
 __device__ __forceinline__ int swz(int row, int col) {  // element offset of (row, col) in a swizzled [.][64] tile
   return row * kH + ((((col >> 3) ^ row) & 7) << 3) + (col & 7);
+}
+// Hidden unit that the k index k' of a layer's B operand stands for (see above).
+__device__ __forceinline__ int kunit(int kp) {
+  return ((kp >> 5) << 5) + (((kp >> 2) & 1) << 4) + (((kp >> 3) & 3) << 2) + (kp & 3);
 }
 
 // Location of one fallback point (what interp_point derives before its gathers).
@@ -625,15 +630,15 @@ struct FbRec {
   double p0, p1;           // extrapolation parameters
 };
 
-// LDS of k_sur_infer: the lo halves of W2, W3 (64 x 64) and W4 (16 x 64),
-// [nx] ln x knots (double), [nx][16] envelope values and slopes, W1 and b1-b3
-// times 2 log2(e) (the argument scale of tanh_scaled), b4; then per wave a
-// 4 KB area (activation pair tile, then the output tile, then the fallback
-// records) and the point records.
+// LDS of k_sur_infer: the lo and hi halves of W2, W3 (64 x 64) and W4
+// (16 x 64) with their columns in kunit order, [nx] ln x knots (double),
+// [nx][16] envelope values and slopes, W1 and b1-b3 times 2 log2(e) (the
+// argument scale of tanh_scaled), b4; then per wave a 4 KB area (the output
+// tile, then the fallback records) and the point records.
 constexpr size_t kSurWaveArea = 2 * 16 * kH * 2;  // 4096 bytes
 constexpr size_t kSurWTile = (size_t)2 * (2 * kH * kH + kO * kH);  // one half of W2, W3, W4 (BF16)
 __host__ __device__ static inline size_t sur_head_bytes(int nx) {
-  const size_t b = (kWeightsInLds ? 2 : 1) * kSurWTile + (size_t)8 * nx +
+  const size_t b = 2 * kSurWTile + (size_t)8 * nx +
                    (size_t)4 * (2 * nx * kO + 2 * kH + 3 * kH + kO + kMaxReq);
   return (b + 15) & ~(size_t)15;
 }
@@ -648,7 +653,7 @@ int sur_infer_waves(int nx) {
 }
 size_t sur_infer_shared_bytes(int nx, int waves) { return sur_head_bytes(nx) + (size_t)waves * kSurWaveBytes; }
 
-__global__ __launch_bounds__(64 * kSurWaves) __attribute__((amdgpu_waves_per_eu(kWeightsInLds ? 4 : 1)))
+__global__ __launch_bounds__(64 * kSurWaves) __attribute__((amdgpu_waves_per_eu(4)))
 void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
                                                              const unsigned short* __restrict__ Pb,
                                                              const float* __restrict__ Pf,
@@ -661,10 +666,10 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
   unsigned short* sw2l = reinterpret_cast<unsigned short*>(sraw);  // [kH][kH] swizzled (16-byte chunks)
   unsigned short* sw3l = sw2l + kH * kH;
   unsigned short* sw4l = sw3l + kH * kH;                   // [kO][kH] swizzled
-  unsigned short* sw2h = sw4l + kO * kH;                   // hi halves, same layout (kWeightsInLds)
+  unsigned short* sw2h = sw4l + kO * kH;                   // hi halves, same layout
   unsigned short* sw3h = sw2h + kH * kH;
   unsigned short* sw4h = sw3h + kH * kH;
-  double* slxk = reinterpret_cast<double*>(kWeightsInLds ? sw4h + kO * kH : sw2h);  // [nx]
+  double* slxk = reinterpret_cast<double*>(sw4h + kO * kH);  // [nx]
   float* senv = reinterpret_cast<float*>(slxk + S.nx);     // [nx][kO]
   float* senvd = senv + S.nx * kO;                         // [nx][kO]
   float* sw1 = senvd + S.nx * kO;                          // [kH][2]
@@ -676,8 +681,6 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
   unsigned char* waves = sraw + sur_head_bytes(S.nx);
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, r = l & 15, g = l >> 4;
   unsigned char* area = waves + (size_t)wv * kSurWaveArea;
-  unsigned short* hs_hi = reinterpret_cast<unsigned short*>(area);   // [16][kH] swizzled
-  unsigned short* hs_lo = hs_hi + 16 * kH;
   float* so = reinterpret_cast<float*>(area);                         // [16][kO] output tile
   FbRec* fbr = reinterpret_cast<FbRec*>(area);                        // [64] fallback records
   float* rec = reinterpret_cast<float*>(waves + (size_t)nwav * kSurWaveArea) + wv * 64 * kSurRec;
@@ -696,39 +699,20 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
   for (int i = threadIdx.x; i < kO; i += BS) sb4[i] = Pf[kOffB4 + i];
   for (int i = threadIdx.x; i < rc.n; i += BS) scol[i] = rc.col[i];
   const unsigned short* Pl = Pb + kNParams;  // lo halves
-  for (int i = threadIdx.x; i < kH * kH; i += BS) {
-    const int row = i / kH, col = i % kH;
-    sw2l[swz(row, col)] = Pl[kOffW2 + i];
-    sw3l[swz(row, col)] = Pl[kOffW3 + i];
-    if (kWeightsInLds) {
-      sw2h[swz(row, col)] = Pb[kOffW2 + i];
-      sw3h[swz(row, col)] = Pb[kOffW3 + i];
-    }
+  for (int i = threadIdx.x; i < kH * kH; i += BS) {  // stored column kp of row n holds W[n][kunit(kp)]
+    const int row = i / kH, kp = i % kH, src = row * kH + kunit(kp);
+    sw2l[swz(row, kp)] = Pl[kOffW2 + src];
+    sw3l[swz(row, kp)] = Pl[kOffW3 + src];
+    sw2h[swz(row, kp)] = Pb[kOffW2 + src];
+    sw3h[swz(row, kp)] = Pb[kOffW3 + src];
   }
   for (int i = threadIdx.x; i < kO * kH; i += BS) {
-    sw4l[swz(i / kH, i % kH)] = Pl[kOffW4 + i];
-    if (kWeightsInLds) sw4h[swz(i / kH, i % kH)] = Pb[kOffW4 + i];
+    const int row = i / kH, kp = i % kH, src = row * kH + kunit(kp);
+    sw4l[swz(row, kp)] = Pl[kOffW4 + src];
+    sw4h[swz(row, kp)] = Pb[kOffW4 + src];
   }
   __syncthreads();
 
-  // hi weight fragments: B operand of layer L, N-tile t, K-step s: lane holds W[n = 16t + r][k = 32s + 8g + i]
-  bf16x8 w2[4][2], w3[4][2], w4[2];
-  if (!kWeightsInLds) {
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int nn = 16 * t + r, kk = 32 * s + 8 * g + i;
-        w2[t][s][i] = __builtin_bit_cast(__bf16, Pb[kOffW2 + nn * kH + kk]);
-        w3[t][s][i] = __builtin_bit_cast(__bf16, Pb[kOffW3 + nn * kH + kk]);
-      }
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) w4[s][i] = __builtin_bit_cast(__bf16, Pb[kOffW4 + r * kH + 32 * s + 8 * g + i]);
-  }
   // an 8-value chunk (16 bytes) of a swizzled LDS row, as an operand fragment
   auto frag = [&](const unsigned short* tile, int row, int col0) -> bf16x8 {
     return *reinterpret_cast<const bf16x8*>(tile + swz(row, col0));
@@ -768,69 +752,69 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int q0 = 0; q0 < np; q0 += 16) {
-      // layer 1 straight into the A layout: lane (r, g) holds h1[point q0 + r][32 s + 8 g + i]
+      // layer 1 straight into the B layout: lane (r, g) holds unit kunit(32 s + 8 g + i) of point q0 + r
       const float u = rec[(q0 + r) * kSurRec], v = rec[(q0 + r) * kSurRec + 1];
-      bf16x8 ah[2], al[2];
+      bf16x8 bh[2], bl[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const int j = 32 * s + 8 * g + i;
+          const int j = kunit(32 * s + 8 * g + i);
           unsigned short hb, lb;
           split_bits(tanh_scaled(fmaf(sw1[2 * j], u, fmaf(sw1[2 * j + 1], v, sb1[j]))), hb, lb);
-          ah[s][i] = __builtin_bit_cast(__bf16, hb);
-          al[s][i] = __builtin_bit_cast(__bf16, lb);
+          bh[s][i] = __builtin_bit_cast(__bf16, hb);
+          bl[s][i] = __builtin_bit_cast(__bf16, lb);
         }
-      // layers 2 and 3
+      // layers 2 and 3: lane (r, g) receives units 16 t + 4 g + i of point q0 + r
 #pragma unroll
       for (int layer = 0; layer < 2; ++layer) {
-        const float* bl = layer == 0 ? sb2 : sb3;
+        const float* bias = layer == 0 ? sb2 : sb3;
+        const unsigned short* wh = layer == 0 ? sw2h : sw3h;
         const unsigned short* wl = layer == 0 ? sw2l : sw3l;
+        float h[4][4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
-            const bf16x8 wh = kWeightsInLds ? frag(layer == 0 ? sw2h : sw3h, 16 * t + r, 32 * s + 8 * g)
-                                            : (layer == 0 ? w2[t][s] : w3[t][s]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], wh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], wh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], frag(wl, 16 * t + r, 32 * s + 8 * g), acc, 0, 0, 0);
+            const bf16x8 ah = frag(wh, 16 * t + r, 32 * s + 8 * g);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[s], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[s], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(wl, 16 * t + r, 32 * s + 8 * g), bh[s], acc, 0, 0, 0);
           }
-          const float bn = bl[16 * t + r];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int o = swz(4 * g + i, 16 * t + r);
-            split_bits(tanh_scaled(fmaf(acc[i], kTwoLog2e, bn)), hs_hi[o], hs_lo[o]);
+          for (int i = 0; i < 4; ++i) h[t][i] = tanh_scaled(fmaf(acc[i], kTwoLog2e, bias[16 * t + 4 * g + i]));
+        }
+        // the next layer's B operand: k' = 32 s + 8 g + i is unit 16 (2 s + i / 4) + 4 g + i % 4
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            unsigned short hb, lb;
+            split_bits(h[2 * s + (i >> 2)][i & 3], hb, lb);
+            bh[s][i] = __builtin_bit_cast(__bf16, hb);
+            bl[s][i] = __builtin_bit_cast(__bf16, lb);
           }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          ah[s] = frag(hs_hi, r, 32 * s + 8 * g);
-          al[s] = frag(hs_lo, r, 32 * s + 8 * g);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      // layer 4: lane (r, g) gets y[point q0 + 4 g + i][output r]; times the envelope into the output tile
+      // layer 4: lane (r, g) gets y[output 4 g + i][point q0 + r]; times the envelope into the output tile
       f32x4 y = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const bf16x8 wh = kWeightsInLds ? frag(sw4h, r, 32 * s + 8 * g) : w4[s];
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], wh, y, 0, 0, 0);
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], wh, y, 0, 0, 0);
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], frag(sw4l, r, 32 * s + 8 * g), y, 0, 0, 0);
+        const bf16x8 ah = frag(sw4h, r, 32 * s + 8 * g);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[s], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[s], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(sw4l, r, 32 * s + 8 * g), bh[s], y, 0, 0, 0);
       }
-      const float b4 = sb4[r];
+      {
+        const float* pq = rec + (q0 + r) * kSurRec;
+        const int ei = __float_as_int(pq[6]);
+        float yo[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float* pq = rec + (q0 + 4 * g + i) * kSurRec;
-        const float e = env_at(senv, senvd, __float_as_int(pq[6]), pq[2], pq[3], pq[4], pq[5], r);
-        so[(4 * g + i) * kO + r] = (y[i] + b4) * e;
+        for (int i = 0; i < 4; ++i) {
+          const int c = 4 * g + i;
+          yo[i] = (y[i] + sb4[c]) * env_at(senv, senvd, ei, pq[2], pq[3], pq[4], pq[5], c);
+        }
+        *reinterpret_cast<float4*>(so + r * kO + 4 * g) = make_float4(yo[0], yo[1], yo[2], yo[3]);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
