@@ -633,9 +633,10 @@ struct FbRec {
 // LDS of k_sur_infer: the lo and hi halves of W2, W3 (64 x 64) and W4
 // (16 x 64) with their columns in kunit order, [nx] ln x knots (double),
 // [nx][16] envelope values and slopes, W1 and b1-b3 times 2 log2(e) (the
-// argument scale of tanh_scaled), b4; then per wave a 4 KB area (the output
-// tile, then the fallback records) and the point records.
-constexpr size_t kSurWaveArea = 2 * 16 * kH * 2;  // 4096 bytes
+// argument scale of tanh_scaled), b4; then per wave a 5 KB area (4 KB for
+// the output tile, later the fallback records; 1 KB for the fallback queue)
+// and the point records.
+constexpr size_t kSurWaveArea = 4096 + 128 * 8;  // output tile or fallback records, then the fallback queue
 constexpr size_t kSurWTile = (size_t)2 * (2 * kH * kH + kO * kH);  // one half of W2, W3, W4 (BF16)
 __host__ __device__ static inline size_t sur_head_bytes(int nx) {
   const size_t b = 2 * kSurWTile + (size_t)8 * nx +
@@ -683,6 +684,8 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
   unsigned char* area = waves + (size_t)wv * kSurWaveArea;
   float* so = reinterpret_cast<float*>(area);                         // [16][kO] output tile
   FbRec* fbr = reinterpret_cast<FbRec*>(area);                        // [64] fallback records
+  int64_t* fq = reinterpret_cast<int64_t*>(area + 4096);              // [128] queued fallback points
+  static_assert(64 * sizeof(FbRec) <= 4096, "fallback records fit the wave area");
   float* rec = reinterpret_cast<float*>(waves + (size_t)nwav * kSurWaveArea) + wv * 64 * kSurRec;
 
   for (int i = threadIdx.x; i < S.nx; i += BS) slxk[i] = S.lxk[i];
@@ -722,6 +725,7 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
   const int R = rc.n;
 
   const int64_t ntiles = (n + 63) / 64;
+  int qn = 0;  // queued fallback points of this wave (fewer than 64 between tiles)
   for (int64_t tile = (int64_t)blockIdx.x * nwav + wv; tile < ntiles; tile += (int64_t)gridDim.x * nwav) {
     const int64_t p0 = tile * 64;
     const int np = (int)min((int64_t)64, n - p0);
@@ -833,13 +837,23 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // fallback points: located once each, then one lane per (point, requested column)
-    if (fbmask) {
-      const int nfb = __popcll(fbmask);
+    // fallback points: queued, and evaluated 64 at a time (one lane per point
+    // locates it, then one lane per (point, requested column) gathers), so the
+    // location runs on full waves rather than on the few fallback lanes of
+    // every tile
+    if (fb) fq[qn + __popcll(fbmask & ((1ull << l) - 1))] = p0 + l;
+    qn += __popcll(fbmask);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool last = tile + (int64_t)gridDim.x * nwav >= ntiles;
+    while (qn >= 64 || (last && qn > 0)) {
+      const int nfb = min(qn, 64);
       bool bad = false;
-      if (fb) {
-        FbRec& fr = fbr[__popcll(fbmask & ((1ull << l) - 1))];
-        const PointLoc L = locate_point<float>(m, gtb, xr, qr, fr.w, fr.v);
+      if (l < nfb) {
+        FbRec& fr = fbr[l];
+        const int64_t pi = fq[l];
+        const PointLoc L = locate_point<float>(m, gtb, X[pi], Q2[pi], fr.w, fr.v);
         fr.base = L.base;
         fr.sa = L.sa;
         fr.mode = L.mode;
@@ -877,8 +891,16 @@ void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
             val = (float)extrap_entry<float>(f, fr.sa, m.P32, fr.mode, wt, fr.p0, fr.p1, invL01);
           }
         }
-        out[(p0 + fr.pt) * R + j] = val;
+        out[fq[fr.pt] * R + j] = val;
       }
+      // the rest of the queue (fewer than 64) to its front: the two ranges do not overlap
+      const int rest = qn - nfb;
+      const int64_t mv = l < rest ? fq[nfb + l] : 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (l < rest) fq[l] = mv;
+      qn = rest;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
