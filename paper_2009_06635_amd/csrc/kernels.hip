@@ -180,7 +180,7 @@ __host__ __device__ constexpr size_t wave_record_bytes() {
 // column gets the same value twice).  Reading it from LDS, groups start at
 // G*j (16-byte aligned LDS reads; rows are zero-padded to a multiple of G)
 // and the last group stores only the columns below R.
-template <typename T, bool kLdsGrid, int G, bool kAlphas = false, bool kOverlap = !kLdsGrid>
+template <typename T, bool kLdsGrid, int G, bool kAlphas = false, bool kOverlap = !kLdsGrid, int kRowB = 0>
 __device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, const int* scol, int R,
                                           const T* sgrid, const T* __restrict__ gvals, uint32_t gbytes,
                                           double xv, double qv, int tp, T* __restrict__ obase,
@@ -189,7 +189,9 @@ __device__ __forceinline__ void wave_tile(const MemberDev& m, const Tables& tb, 
   PointRec<T>* srec = reinterpret_cast<PointRec<T>*>(rec);        // [64]
   double* sp = reinterpret_cast<double*>(srec + kWave);           // [64][2] extrapolation parameters
   const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
-  const int rowb = Pp * (int)sizeof(T);  // bytes between consecutive Q^2 knots
+  // bytes between consecutive Q^2 knots; a compile-time kRowB (the caller has
+  // checked it) lets the four Q^2 rows of an LDS gather use immediate offsets
+  const int rowb = kRowB ? kRowB : Pp * (int)sizeof(T);
   constexpr int kSlow = kLowX | kLowQ | kHighQ;
   // lane -> (point, flavour) or (point, column group) walk of the tile's outputs
   const int NE = G == 1 ? R : (R + G - 1) / G;
@@ -1014,6 +1016,10 @@ __global__ __launch_bounds__(kBatchBS) void k_batched(const BatchReq* __restrict
       if (vector_cols && rq.all_cols && rq.R >= G)
         wave_tile<T, kLdsGrid, G>(m, tb, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp, out + pbeg * rq.R, nerr,
                                   invL01, rec, lane, kNoAlphas, AsView{});
+      else if (kLdsGrid && sizeof(T) == 4 && m.P32 == 12)  // 9-12 stored flavours in FP32: 48-byte rows
+        wave_tile<T, kLdsGrid, 1, false, !kLdsGrid, 48>(m, tb, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp,
+                                                        out + pbeg * rq.R, nerr, invL01, rec, lane, kNoAlphas,
+                                                        AsView{});
       else
         wave_tile<T, kLdsGrid, 1>(m, tb, scol, rq.R, sgrid, gvals, gbytes, xv, qv, tp, out + pbeg * rq.R, nerr,
                                   invL01, rec, lane, kNoAlphas, AsView{});
