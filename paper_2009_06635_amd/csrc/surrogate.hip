@@ -603,10 +603,10 @@ __global__ void k_gather_samples(const float* __restrict__ in_all, const float* 
 // LDS.  Layer 1 (two inputs) runs on the VALUs straight into that layout.
 // The outputs times the envelope go to a 16 x 16 LDS tile from which the
 // requested columns are stored point-major, consecutive lanes on consecutive
-// values.  Points in the fallback domain are then evaluated by the FP32
-// interpolator: each is located once (one lane per point: sub-grid, cells,
-// weights), after which one lane per (point, requested column) gathers its
-// 4x4 stencil.
+// values.  Points in the fallback domain are queued per wave and evaluated
+// 64 at a time by the FP32 interpolator: each is located once (one lane per
+// point: sub-grid, cells, weights), after which one lane per (point,
+// requested column) gathers its 4x4 stencil.
 //
 // LDS rows of 64 BF16 values (the weight halves) hold their eight 16-byte
 // chunks in the order chunk ^ (row & 7), so the 16 rows an operand read
@@ -626,7 +626,7 @@ __device__ __forceinline__ int kunit(int kp) {
 // Location of one fallback point (what interp_point derives before its gathers).
 struct FbRec {
   float w[4], v[4];
-  int base, sa, mode, pt;  // grid offset and x stride (elements), region bits, point within the 64
+  int base, sa, mode, pt;  // grid offset and x stride (elements), region bits, slot in the wave's queue
   double p0, p1;           // extrapolation parameters
 };
 
@@ -655,13 +655,9 @@ int sur_infer_waves(int nx) {
 size_t sur_infer_shared_bytes(int nx, int waves) { return sur_head_bytes(nx) + (size_t)waves * kSurWaveBytes; }
 
 __global__ __launch_bounds__(64 * kSurWaves) __attribute__((amdgpu_waves_per_eu(4)))
-void k_sur_infer(SurDev S, MemberDev m, ReqCols rc,
-                                                             const unsigned short* __restrict__ Pb,
-                                                             const float* __restrict__ Pf,
-                                                             const double* __restrict__ X,
-                                                             const double* __restrict__ Q2, int64_t n,
-                                                             float* __restrict__ out, double invL01,
-                                                             unsigned long long* __restrict__ nerr) {
+void k_sur_infer(SurDev S, MemberDev m, ReqCols rc, const unsigned short* __restrict__ Pb,
+                 const float* __restrict__ Pf, const double* __restrict__ X, const double* __restrict__ Q2,
+                 int64_t n, float* __restrict__ out, double invL01, unsigned long long* __restrict__ nerr) {
   extern __shared__ __align__(16) unsigned char sraw[];
   const int BS = blockDim.x, nwav = BS >> 6;
   unsigned short* sw2l = reinterpret_cast<unsigned short*>(sraw);  // [kH][kH] swizzled (16-byte chunks)
