@@ -83,6 +83,61 @@ def test_batched_equals_per_request_and_oracle(members, out_f64):
 
 
 @pytest.mark.parametrize("out_f64", [False, True])
+def test_lds_grids_of_other_row_widths(out_f64):
+    """Grids staged in LDS with 13, 7 and 12 stored flavours (16-, 8- and
+    12-float FP32 rows; the FP32 kernel has a separate code path for 12-float
+    rows) beside an 11-flavour member, with full and partial flavour lists:
+    every request equal to its per-request call, and within tolerance of the
+    oracle."""
+    rng = np.random.default_rng(5)
+    grids = [synth.config3_members(n_members=1)[0],
+             synth.tiny_grid(rng, K=1, nx=40, nq=25, npid=13, loguniform_knots=True),
+             synth.tiny_grid(rng, K=2, nx=30, nq=[12, 14], npid=7, loguniform_knots=True),
+             synth.tiny_grid(rng, K=1, nx=36, nq=20, npid=12, loguniform_knots=True)]
+    ids = [pdfmi.load_synth(g) for g in grids]
+    try:
+        reqs, host = [], []
+        for i, n in enumerate((5000, 777, 4097, 3000, 64, 20000, 1500, 999)):
+            gi = i % len(grids)
+            g = grids[gi]
+            pids = None if i < 4 else [int(p) for p in rng.permutation(g.pids)[: max(1, len(g.pids) // 2)]]
+            P = len(g.pids) if pids is None else len(pids)
+            x = np.exp(rng.uniform(np.log(g.xknots[0][0]), 0.0, n))
+            q2 = np.exp(rng.uniform(np.log(g.q2knots[0][0]), np.log(g.q2knots[-1][-1]), n))
+            out = torch.full((n, P), -7.0, dtype=torch.float64 if out_f64 else torch.float32, device=DEV)
+            reqs.append((ids[gi], pids, dev(x), dev(q2), out))
+            host.append((g, pids, x, q2))
+        pdfmi.set_lds_policy(2)   # stage every member grid in LDS
+        try:
+            plan = pdfmi.BatchPlan(reqs, out_f64=out_f64)
+        finally:
+            pdfmi.set_lds_policy(0)
+        try:
+            for tile in (64, 2048):
+                plan.configure(tile_points=tile, vector_cols=0)
+                for r in reqs:
+                    r[4].fill_(-7.0)
+                plan.run()
+                torch.cuda.synchronize()
+                fn = pdfmi.xfxq2 if out_f64 else pdfmi.xfxq2_f32
+                for (m, pids, x, q2, out), (g, _, _, _) in zip(reqs, host):
+                    ref = fn(m, pids, x, q2, n_cols=len(g.pids))
+                    assert torch.equal(out, ref), (tile, len(g.pids))
+            for (m, pids, x, q2, out), (g, p2, xh, qh) in zip(reqs, host):
+                req = g.pids if p2 is None else p2
+                ora, sc = oracle.xfxq2(oracle.Grid(g.xknots, g.q2knots, g.values, g.pids), req, xh, qh,
+                                       with_scale=True)
+                o = out.cpu().numpy()
+                ok = check_f64(o, ora, sc, grid_L(g))[0] if out_f64 else check_f32(o, ora, sc)[0]
+                assert ok.all(), len(g.pids)
+        finally:
+            plan.destroy()
+    finally:
+        for m in ids:
+            pdfmi.unload(m)
+
+
+@pytest.mark.parametrize("out_f64", [False, True])
 def test_plan_without_lds_grid_is_identical(members, out_f64):
     """A plan created under the never-stage policy reads the member grids from
     global memory; its outputs equal those of a plan that stages them in LDS."""
