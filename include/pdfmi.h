@@ -230,6 +230,21 @@ int pdf_batch_run(int32_t plan, pdf_stream_t stream);
  * Synchronises stream.  tile_out / vector_out (nullable) receive the choice.
  */
 int pdf_batch_autotune(int32_t plan, int32_t reps, pdf_stream_t stream, int32_t* tile_out, int32_t* vector_out);
+/*
+ * Autotune choices kept on disk, for later processes with the same workload:
+ * reads path (a text file of "key tile_points vector_cols" lines; a missing
+ * file holds none, lines that do not parse are skipped) into the choices
+ * pdf_batch_autotune remembers, and from then on appends every choice a
+ * sweep makes.  Keys are the request signature (request count, point and
+ * evaluation totals, output precision, grid staging) and the device
+ * (architecture name, compute units), so a file can serve several GPUs and
+ * workloads; a later line for a key replaces an earlier one on reading.
+ * path NULL or "" stops the appending (choices already read stay).  Host
+ * only: no device work.  Errors: PDF_ERR_ARG when path exists but cannot be
+ * read.  A file that cannot be appended to is ignored (the choice is then
+ * remembered in this process only).
+ */
+int pdf_batch_tune_cache(const char* path);
 int pdf_batch_destroy(int32_t plan);
 /* One-shot: create a plan with FP32 outputs (the FP32 bulk path of many
  * members), run it on stream, synchronise stream, destroy it.  Errors as

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cerrno>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -114,6 +115,7 @@ std::vector<Member> g_members;
 uint64_t g_load_gen = 0;
 bool g_init = false;
 int g_ncu = 0;
+std::string g_arch;  // device architecture name (autotune cache keys)
 unsigned long long* g_nerr = nullptr;
 bool g_has_alphas = false;
 AlphasDev g_alphas{};
@@ -136,6 +138,12 @@ int ensure_device() {
   if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
   e = hipDeviceGetAttribute(&g_ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDeviceProperties");
+  g_arch = prop.gcnArchName;
+  for (char& c : g_arch)
+    if (c == ' ' || c == '\t') c = '_';
   e = fk_scratch_setup(dev, &g_fk_scratch);
   if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(fk scratch)");
   g_dev_ready = true;
@@ -841,9 +849,42 @@ int plan_members_live(const Plan& P) {
   return PDF_OK;
 }
 
+// Autotune choices (tile points, vector columns) by request signature and
+// device, and the file they are also kept in ("" = none).
 std::map<std::string, std::pair<int, int>> g_tune_cache;
+std::string g_tune_path;
+
+bool valid_tile(int tile) { return tile >= 64 && tile <= (1 << 22) && (tile & 63) == 0; }
+
+// Reads the "key tile vector" lines of a cache file into g_tune_cache; lines
+// that do not parse or hold an invalid choice are skipped.  A missing file
+// holds no entries.
+int tune_cache_load(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return errno == ENOENT ? PDF_OK : fail(PDF_ERR_ARG, "cannot read autotune cache %s", path);
+  char line[512], key[400];
+  while (std::fgets(line, sizeof line, f)) {
+    int tile = 0, vec = -1;
+    if (std::sscanf(line, "%399s %d %d", key, &tile, &vec) == 3 && valid_tile(tile) && (vec == 0 || vec == 1))
+      g_tune_cache[key] = {tile, vec};
+  }
+  std::fclose(f);
+  return PDF_OK;
+}
 
 }  // namespace
+
+extern "C" int pdf_batch_tune_cache(const char* path) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (!path || !*path) {
+    g_tune_path.clear();
+    return PDF_OK;
+  }
+  const int rc = tune_cache_load(path);
+  if (rc != PDF_OK) return rc;
+  g_tune_path = path;
+  return PDF_OK;
+}
 
 extern "C" int pdf_batch_create(const pdf_request* reqs, int32_t n_req, int32_t out_f64, int32_t* plan_out) {
   if (!plan_out || (n_req > 0 && !reqs) || n_req < 0) return fail(PDF_ERR_ARG, "bad argument");
@@ -974,9 +1015,9 @@ extern "C" int pdf_batch_autotune(int32_t plan, int32_t reps, pdf_stream_t strea
     pts += r.n;
     evals += r.n * r.R;
   }
-  char key[160];
-  snprintf(key, sizeof key, "%zu/%lld/%lld/%d/%d", P->reqs.size(), (long long)pts, (long long)evals, P->out_f64,
-           (int)P->lds);
+  char key[400];
+  snprintf(key, sizeof key, "%s/%d/%zu/%lld/%lld/%d/%d", g_arch.c_str(), g_ncu, P->reqs.size(), (long long)pts,
+           (long long)evals, P->out_f64, (int)P->lds);
   auto it = g_tune_cache.find(key);
   int best_tile = P->tile_points, best_vec = P->vector_cols;
   if (it != g_tune_cache.end()) {
@@ -1023,6 +1064,12 @@ extern "C" int pdf_batch_autotune(int32_t plan, int32_t reps, pdf_stream_t strea
     if (e1) (void)hipEventDestroy(e1);
     if (rc != PDF_OK) return rc;
     g_tune_cache[key] = {best_tile, best_vec};
+    if (!g_tune_path.empty()) {  // best effort: a cache that cannot be written only costs a later sweep
+      if (FILE* f = std::fopen(g_tune_path.c_str(), "a")) {
+        std::fprintf(f, "%s %d %d\n", key, best_tile, best_vec);
+        std::fclose(f);
+      }
+    }
   }
   plan_free_graph(*P);
   P->tile_points = best_tile;

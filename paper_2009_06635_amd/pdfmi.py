@@ -42,6 +42,7 @@ _SIGS = {
     "pdf_batch_configure": [_i32, _i32, _i32, _i32],
     "pdf_batch_run": [_i32, _P],
     "pdf_batch_autotune": [_i32, _i32, _P, _P, _P],
+    "pdf_batch_tune_cache": [ctypes.c_char_p],
     "pdf_batch_destroy": [_i32],
     "pdf_xfxq2_batched": [_P, _i32, _P],
     "pdf_xfxq2_batched_f64": [_P, _i32, _P],
@@ -506,6 +507,11 @@ class Surrogate:
 
 def set_lds_policy(policy):
     _check(_lib.pdf_set_lds_policy(int(policy)))
+
+
+def batch_tune_cache(path):
+    """pdf_batch_tune_cache: keep autotune choices in the file at path (None stops appending)."""
+    _check(_lib.pdf_batch_tune_cache(None if path is None else os.fsencode(path)))
 
 
 TUNE_LDS_POLICY, TUNE_VECTOR_COLUMNS, TUNE_BLOCKS_PER_CU = 0, 1, 2

@@ -121,3 +121,16 @@ def test_capi_demo_is_built_against_the_library():
     assert os.access(exe, os.X_OK)
     out = subprocess.run(["ldd", exe], capture_output=True, text=True).stdout
     assert "libpdfmi.so" in out
+
+
+def test_tune_cache_file_handling(lib, tmp_path):
+    """pdf_batch_tune_cache is host-only: a missing file holds no entries, lines
+    that do not parse or hold an invalid choice are skipped, NULL stops it."""
+    f = lib.pdf_batch_tune_cache
+    f.argtypes = [ctypes.c_char_p]
+    assert f(os.fsencode(str(tmp_path / "none.txt"))) == 0
+    p = tmp_path / "tune.txt"
+    p.write_text("not a line\nkey-a 4096 1\nkey-b 100 0\nkey-c 8192 7\n\n")
+    assert f(os.fsencode(str(p))) == 0
+    assert f(None) == 0
+    assert f(b"") == 0

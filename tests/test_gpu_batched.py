@@ -201,6 +201,37 @@ def test_autotune_keeps_results(members):
         plan.destroy()
 
 
+def test_autotune_cache_file(members, tmp_path):
+    """A sweep appends its choice to the cache file; a choice read from the
+    file (here edited by hand to a tile size the sweep never picks) is taken
+    without a sweep, and the plan still gives the per-request values."""
+    grids, ids = members
+    reqs, host = make_requests(grids, ids, False, seed=11, sizes=(5, 6001, 333, 70))
+    path = tmp_path / "tune.txt"
+    pdfmi.batch_tune_cache(str(path))
+    try:
+        plan = pdfmi.BatchPlan(reqs)
+        try:
+            t1, v1 = plan.autotune(reps=1)
+            lines = [ln for ln in path.read_text().splitlines() if ln.strip()]
+            assert len(lines) == 1 and lines[0].split()[1:] == [str(t1), str(v1)]
+            path.write_text("%s 3008 1\n" % lines[0].split()[0])
+            pdfmi.batch_tune_cache(str(path))
+            assert plan.autotune(reps=1) == (3008, 1)
+            assert len(path.read_text().splitlines()) == 1   # no sweep, nothing appended
+            for r in reqs:
+                r[4].fill_(-7.0)
+            plan.run()
+            torch.cuda.synchronize()
+            for (m, pids, x, q2, out), (mi, _, _, _) in zip(reqs, host):
+                ref = pdfmi.xfxq2_f32(m, pids, x, q2, n_cols=len(grids[mi].pids))
+                assert torch.equal(torch.nan_to_num(out, nan=123.0), torch.nan_to_num(ref, nan=123.0))
+        finally:
+            plan.destroy()
+    finally:
+        pdfmi.batch_tune_cache(None)
+
+
 @pytest.mark.parametrize("out_f64", [False, True])
 def test_one_shot_equals_per_request(members, out_f64):
     """pdf_xfxq2_batched (FP32 outputs) and pdf_xfxq2_batched_f64 against the
