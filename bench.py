@@ -205,6 +205,26 @@ def main():
     log("timing FP64 / FP32")
     wall64, k64 = timed(step64, args.steps, args.warmup)
     wall32, k32 = timed(step32, args.steps, args.warmup)
+
+    def copy_gbs():
+        # a measured HBM figure beside the published peak: a 1 GiB device-to-device
+        # copy, bytes read + written per second (context only; the roofline keeps 8 TB/s)
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        gbs = 2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del a, b
+        return gbs
+
+    hbm_copy = copy_gbs()
     evals = args.n * P
     bytes64 = args.n * (16 + 8 * P + 8)
     bytes32 = args.n * (16 + 4 * P + 8)
@@ -231,6 +251,8 @@ def main():
                      "frac": ach64 / HBM_PEAK_GBS, "traffic": measured_traffic("xfxq2_f64"),
                      "kernel": "k_xfxq2<double> with alpha_s output (pdf_xfxq2_alphas)", "kernel_ms": k64,
                      "algorithmic_bytes_per_launch": bytes64,
+                     "hbm_copy_measured": {"achieved": hbm_copy, "unit": "GB/s", "frac_of_it": ach64 / hbm_copy,
+                                           "what": "1 GiB device-to-device copy, bytes read + written"},
                      # the gather behind the HBM figure: every point reads its 4 x 4 stencil, 16 grid
                      # rows of 13 FP64 columns, as 16 x 128-byte lines from the L2-resident grid and as
                      # 16 rows x 7 lanes x 16 bytes through each compute unit's vector-memory (L1) path
