@@ -1,0 +1,56 @@
+"""Property-based parity of the HIP path with the oracle: hypothesis draws
+small grids (sub-grid count, knot counts, stored flavour count, values from a
+seed, values of mixed sign or positive) and a flavour request, and for every
+draw, on points over and around the grid (every knot and its float
+neighbours, thresholds, every extrapolation region, invalid inputs):
+  * sub-grid, cell indices and region bits equal the oracle's bit for bit;
+  * FP64 values meet the FP64 criterion and FP32 values the FP32 one, with the
+    grid read from global memory and staged in LDS.
+"""
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import oracle
+from paper_2009_06635_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_2009_06635_amd import pdfmi  # noqa: E402
+from test_gpu_parity import dev, edge_queries, run_parity  # noqa: E402
+
+# (sub-grids, x knots, Q^2 knots per sub-grid, stored flavours, seed of knots and values)
+shapes = st.tuples(st.integers(1, 3), st.integers(2, 9), st.lists(st.integers(2, 7), min_size=3, max_size=3),
+                   st.integers(1, 13), st.integers(0, 2**31 - 1))
+
+
+@settings(max_examples=25, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(shapes, st.booleans(), st.integers(0, 2**31 - 1))
+def test_drawn_grids_match_oracle(shape, positive, qseed):
+    K, nx, nqs, npid, seed = shape
+    g = synth.tiny_grid(np.random.default_rng(seed), K=K, nx=nx, nq=nqs[:K], npid=npid)
+    if positive:  # positive values: the power-law extrapolation branches
+        g = g.with_values([np.abs(v) + 0.01 for v in g.values])
+    r = np.random.default_rng(qseed)
+    x, q2 = edge_queries(g, r, n_rand=400)
+    # every stored flavour, or a drawn subset with a repeat and the gluon's alias 0
+    pids = list(g.pids) if qseed % 2 else [int(p) for p in r.permutation(g.pids)[: max(1, npid // 2)]] + [0]
+    m = pdfmi.load_synth(g)
+    try:
+        og = oracle.Grid(g.xknots, g.q2knots, g.values, g.pids)
+        k, ix, iq, reg = pdfmi.locate(m, dev(x), dev(q2))
+        ok_, oix, oiq, oreg = oracle.locate(og, x, q2)
+        assert np.array_equal(k.cpu().numpy(), ok_)
+        assert np.array_equal(ix.cpu().numpy(), oix)
+        assert np.array_equal(iq.cpu().numpy(), oiq)
+        assert np.array_equal(reg.cpu().numpy(), oreg)
+        for policy in (1, 2):  # grid read from global memory, grid staged in LDS
+            pdfmi.set_lds_policy(policy)
+            for f32 in (False, True):
+                run_parity(m, g, pids, x, q2, f32=f32)
+    finally:
+        pdfmi.set_lds_policy(0)
+        pdfmi.unload(m)
