@@ -54,3 +54,29 @@ def test_drawn_grids_match_oracle(shape, positive, qseed):
     finally:
         pdfmi.set_lds_policy(0)
         pdfmi.unload(m)
+
+
+@settings(max_examples=25, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(st.lists(st.integers(2, 12), min_size=1, max_size=3), st.integers(0, 2**31 - 1))
+def test_drawn_alphas_tables_match_oracle(seg_sizes, seed):
+    """alpha_s tables of 1-3 segments (a segment starts at a repeated knot, a
+    flavour threshold): values within 1e-13 of the oracle at points over and
+    around the table, knots bit-exact, NaN for invalid Q^2."""
+    r = np.random.default_rng(seed)
+    knots, vals = [], []
+    q = float(np.exp(r.uniform(0.0, 1.0)))
+    for m in seg_sizes:
+        seg = [q] + list(q * np.exp(np.cumsum(r.uniform(0.1, 1.5, m - 1))))
+        knots += seg
+        vals += list(r.uniform(0.05, 0.4, m))
+        q = seg[-1]  # the next segment starts at this knot
+    qk, a = np.array(knots), np.array(vals)
+    pdfmi.load_alphas(qk, a)
+    q2 = np.concatenate([np.exp(r.uniform(np.log(qk[0]) - 1.0, np.log(qk[-1]) + 1.0, 2000)), qk,
+                         np.nextafter(qk, 0.0), np.nextafter(qk, np.inf), [0.0, -1.0, np.nan, np.inf]])
+    out = pdfmi.alphas_q2(dev(q2)).cpu().numpy()
+    ora = oracle.alphas_q2(qk, a, q2)
+    assert np.array_equal(np.isnan(out), np.isnan(ora))
+    f = ~np.isnan(ora)
+    assert np.max(np.abs(out[f] - ora[f]) / np.abs(ora[f])) < 1e-13
+    assert np.array_equal(out[2000:2000 + len(qk)], ora[2000:2000 + len(qk)])
