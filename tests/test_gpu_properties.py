@@ -22,6 +22,8 @@ if not torch.cuda.is_available():
 from paper_2009_06635_amd import pdfmi  # noqa: E402
 from test_gpu_parity import dev, edge_queries, run_parity  # noqa: E402
 
+DEV = "cuda:0"
+
 # (sub-grids, x knots, Q^2 knots per sub-grid, stored flavours, seed of knots and values)
 shapes = st.tuples(st.integers(1, 3), st.integers(2, 9), st.lists(st.integers(2, 7), min_size=3, max_size=3),
                    st.integers(1, 13), st.integers(0, 2**31 - 1))
@@ -110,3 +112,44 @@ def test_drawn_mc_fused_equals_unfused(shape, f32, n, qseed):
         assert s.view(np.uint64)[0] == s_ref.view(np.uint64)[0], (s, s_ref)
     finally:
         pdfmi.unload(m)
+
+
+@settings(max_examples=20, deadline=None, derandomize=True, suppress_health_check=[HealthCheck.too_slow])
+@given(st.lists(shapes, min_size=1, max_size=4), st.lists(st.integers(0, 3000), min_size=1, max_size=8),
+       st.sampled_from([64, 256, 1024, 4096]), st.booleans(), st.booleans(), st.integers(0, 2**31 - 1))
+def test_drawn_batched_plans_equal_per_request(member_shapes, sizes, tile, vec, out_f64, qseed):
+    """Batched plans over drawn members (tiny grids of any shape, staged in LDS
+    together) and drawn requests (sizes including 0, full or partial flavour
+    lists, points in every region): every output equal to its per-request
+    call, for a drawn tile size and column grouping."""
+    grids = [synth.tiny_grid(np.random.default_rng(s[4]), K=s[0], nx=s[1], nq=s[2][:s[0]], npid=s[3])
+             for s in member_shapes]
+    ids = [pdfmi.load_synth(g) for g in grids]
+    r = np.random.default_rng(qseed)
+    plan = None
+    try:
+        reqs = []
+        for i, n in enumerate(sizes):
+            gi = int(r.integers(0, len(grids)))
+            g = grids[gi]
+            pids = None if i % 2 == 0 else [int(p) for p in r.permutation(g.pids)[: int(r.integers(1, len(g.pids) + 1))]]
+            P = len(g.pids) if pids is None else len(pids)
+            x = np.exp(r.uniform(np.log(g.xknots[0][0]) - 1.0, 0.0, n))
+            q2 = np.exp(r.uniform(np.log(g.q2knots[0][0]) - 0.5, np.log(g.q2knots[-1][-1]) + 0.5, n))
+            out = torch.full((n, P), -7.0, dtype=torch.float64 if out_f64 else torch.float32, device=DEV)
+            reqs.append((ids[gi], pids, dev(x), dev(q2), out, g))
+        plan = pdfmi.BatchPlan([q[:5] for q in reqs], out_f64=out_f64)
+        plan.configure(tile_points=tile, vector_cols=int(vec))
+        plan.run()
+        torch.cuda.synchronize()
+        fn = pdfmi.xfxq2 if out_f64 else pdfmi.xfxq2_f32
+        for m, pids, x, q2, out, g in reqs:
+            if x.shape[0] == 0:
+                continue
+            ref = fn(m, pids, x, q2, n_cols=len(g.pids))
+            assert torch.equal(torch.nan_to_num(out, nan=123.0), torch.nan_to_num(ref, nan=123.0))
+    finally:
+        if plan is not None:
+            plan.destroy()
+        for m in ids:
+            pdfmi.unload(m)
