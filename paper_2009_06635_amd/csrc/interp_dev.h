@@ -341,17 +341,24 @@ __device__ __forceinline__ const float* member_values<float>(const MemberDev& m)
 
 // In-grid value of one column from its gathered 4x4 stencil: the x-direction
 // weights on each of the four Q^2 rows, then the Q^2-direction weights.
+// stencil_step adds Q^2 row b (its four x-knot values f0..f3) to the running
+// sum acc; interp_stencil is the four steps in order, and a caller that
+// gathers the stencil row by row may take the steps itself with the same
+// result.
+template <typename T>
+__device__ __forceinline__ T stencil_step(int b, T acc, T f0, T f1, T f2, T f3, const T w[4], const T v[4]) {
+  T g = w[0] * f0;
+  g = fma(w[1], f1, g);
+  g = fma(w[2], f2, g);
+  g = fma(w[3], f3, g);
+  return b == 0 ? v[0] * g : fma(v[b], g, acc);
+}
+
 template <typename T>
 __device__ __forceinline__ T interp_stencil(const T F[4][4], const T w[4], const T v[4]) {
-  T acc;
+  T acc = (T)0;
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    T g = w[0] * F[0][b];
-    g = fma(w[1], F[1][b], g);
-    g = fma(w[2], F[2][b], g);
-    g = fma(w[3], F[3][b], g);
-    acc = b == 0 ? v[0] * g : fma(v[b], g, acc);
-  }
+  for (int b = 0; b < 4; ++b) acc = stencil_step<T>(b, acc, F[0][b], F[1][b], F[2][b], F[3][b], w, v);
   return acc;
 }
 

@@ -34,6 +34,10 @@ template <>
 struct VecOf<double, 2> { using type = double2; };
 template <>
 struct VecOf<float, 4> { using type = float4; };
+template <>
+struct VecOf<double, 1> { using type = double; };
+template <>
+struct VecOf<float, 1> { using type = float; };
 
 // Buffer resource over [base, base + bytes): loads and stores through it take
 // a 32-bit per-lane byte offset plus a uniform (scalar) byte offset, so the
@@ -723,9 +727,63 @@ hipError_t launch_mc_sum(const T* xf1, const T* xf2, int P, const double* as, in
 // point locates x1 and x2, evaluates every requested flavour of both with the
 // same device functions as k_xfxq2, forms sum_j xf1_j xf2_j in flavour order
 // and accumulates alpha_s times it -- the summation order of k_mc_partial, so
-// both paths give bit-identical sums.  The grid is staged in LDS with row
-// stride P when it fits (kLdsGrid), else read from global memory.
+// both paths give bit-identical sums.  The grid is staged in LDS when it
+// fits (kLdsGrid), else read from global memory.  In FP32 the LDS rows are
+// padded with zeros to a multiple of kGW = 4 columns when that fits too, and
+// the stencils are then read four columns at a time: one 16-byte LDS read
+// brings four columns of a stencil row (a random-row gather of 16-byte reads
+// delivers 2.3x the values per clock of 4-byte reads).  The flavour loop then
+// walks a list of column-group steps built once per workgroup from the
+// request: a step reads one group and applies the terms of the next 1..kGW
+// requested flavours whose columns fall in it, in request order, so the sum
+// is still formed flavour by flavour in that order; a flavour absent from the
+// grid is a step of its own with no read.  Otherwise (and in FP64, where
+// column pairs measured slower: a pair's 16 reads per lookup do not fit in
+// flight beside the rest of the point's registers) the rows keep stride P
+// and each requested column is read on its own (kGW = 1).
 constexpr int kMcFusedBS = 4 * kMcThreads;
+constexpr int kStepAbsent = -1;   // a step whose flavour is absent from the grid
+constexpr int kStepOrdered = 1 << 19;  // the step's terms are the group's columns 0, 1, ... in order
+
+// Column-group steps of a request (see above) into st[1..], their count into st[0].
+// Step: group's first column (bits 0-15), term count (16-18), kStepOrdered,
+// and the column within the group of term t in bits 20 + 2t, 21 + 2t.
+template <int kGW>
+__device__ __forceinline__ void mc_build_steps(const ReqCols& rc, int* st) {
+  int ns = 0;
+  for (int j = 0; j < rc.n;) {
+    const int c = rc.col[j];
+    if (c < 0) {
+      st[1 + ns++] = kStepAbsent;
+      ++j;
+      continue;
+    }
+    const int g0 = c & ~(kGW - 1);
+    int nt = 1, sel = c - g0;
+    bool ordered = c == g0;
+    while (nt < kGW && j + nt < rc.n && rc.col[j + nt] >= 0 && (rc.col[j + nt] & ~(kGW - 1)) == g0) {
+      sel |= (rc.col[j + nt] - g0) << (2 * nt);
+      ordered = ordered && rc.col[j + nt] - g0 == nt;
+      ++nt;
+    }
+    st[1 + ns++] = g0 | (nt << 16) | (ordered ? kStepOrdered : 0) | (sel << 20);
+    j += nt;
+  }
+  st[0] = ns;
+}
+
+// Element e (uniform) of a kGW-array of values held in registers.
+template <typename T, int kGW>
+__device__ __forceinline__ T mc_pick(const T (&f)[kGW], int e) {
+  if constexpr (kGW == 1) {
+    return f[0];
+  } else if constexpr (kGW == 2) {
+    return e ? f[1] : f[0];
+  } else {
+    static_assert(kGW == 4, "column groups of 2 or 4");
+    return e == 0 ? f[0] : (e == 1 ? f[1] : (e == 2 ? f[2] : f[3]));
+  }
+}
 
 // One flavour of one located point, the value k_xfxq2 writes for it: NaN for
 // an invalid point, 0 for a flavour absent from the grid, the stencil sum
@@ -760,7 +818,7 @@ __device__ __forceinline__ void mc_origin(const Tables& tb, const int* soff, con
   base = soff[k] + (L.sx * nqp + L.sq) * P;
 }
 
-template <typename T, bool kLdsGrid>
+template <typename T, bool kLdsGrid, int kGW>
 __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc, AlphasDev A,
                                                          const double* __restrict__ X1,
                                                          const double* __restrict__ X2,
@@ -777,7 +835,8 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
   double* tree = reinterpret_cast<double*>(ash + ((A.nhints + 7) & ~7));  // [4][256]
   int* scol = reinterpret_cast<int*>(tree + kMcFusedBS);  // [kMaxReq]
   int* soff = scol + kMaxReq;                             // [kMaxSub] staged sub-grid offsets
-  T* sgrid = reinterpret_cast<T*>(soff + kMaxSub);        // 16-byte aligned: kMaxReq + kMaxSub ints
+  int* sstep = soff + kMaxSub;                            // [kMaxReq + 4] column-group steps (kGW > 1)
+  T* sgrid = reinterpret_cast<T*>(sstep + kMaxReq + 4);   // 16-byte aligned: 2 kMaxReq + kMaxSub + 4 ints
 
   stage_copy<kMcFusedBS>(stbl, m.tables, m.tbl_bytes);
   for (int i = threadIdx.x; i < A.n; i += kMcFusedBS) {
@@ -789,21 +848,24 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
   for (int i = threadIdx.x; i < rc.n; i += kMcFusedBS) scol[i] = rc.col[i];
   const int Pp = sizeof(T) == 8 ? m.P64 : m.P32;
   const T* __restrict__ gvals = member_values<T>(m);
-  const int P = kLdsGrid ? m.P : Pp;  // row stride of the values read below
+  // row stride of the values read below: in LDS P, or P rounded up to whole
+  // column groups (<= Pp, whose padding columns are zero in global memory)
+  const int P = kLdsGrid ? (m.P + kGW - 1) & ~(kGW - 1) : Pp;
   if (threadIdx.x == 0) {
     int off = 0;
     for (int k = 0; k < m.K; ++k) {
       soff[k] = kLdsGrid ? off : (int)(sizeof(T) == 8 ? m.sub[k].val_off64 : m.sub[k].val_off32);
-      off += m.sub[k].nxp * m.sub[k].nqp * m.P;
+      off += m.sub[k].nxp * m.sub[k].nqp * P;
     }
+    if constexpr (kGW > 1) mc_build_steps<kGW>(rc, sstep);
   }
   if constexpr (kLdsGrid) {
     int off = 0;
     for (int k = 0; k < m.K; ++k) {
       const SubDesc& S = m.sub[k];
       const int rows = S.nxp * S.nqp;
-      stage_rows<kMcFusedBS>(sgrid + off, gvals + (sizeof(T) == 8 ? S.val_off64 : S.val_off32), rows, m.P, Pp);
-      off += rows * m.P;
+      stage_rows<kMcFusedBS>(sgrid + off, gvals + (sizeof(T) == 8 ? S.val_off64 : S.val_off32), rows, P, Pp);
+      off += rows * P;
     }
   }
   __syncthreads();
@@ -843,7 +905,59 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
       mc_origin(tb, soff, L1, P, b1, sa1);
       mc_origin(tb, soff, L2, P, b2, sa2);
       double lum = 0.0;
-      if (kLdsGrid && !((L1.mode | L2.mode) & (kLowX | kLowQ | kHighQ))) {
+      if (kLdsGrid && kGW > 1 && !((L1.mode | L2.mode) & (kLowX | kLowQ | kHighQ))) {
+        // both lookups inside the LDS-staged grid, read a column group at a
+        // time: per step, the kGW values of each lookup that mc_value gives
+        // for the group's columns, then the step's terms in request order
+        using V = typename VecOf<T, kGW>::type;
+        const bool inv1 = L1.mode & kInvalid, inv2 = L2.mode & kInvalid;
+        const int ns = __builtin_amdgcn_readfirstlane(sstep[0]);
+        for (int s = 0; s < ns; ++s) {
+          const int st = __builtin_amdgcn_readfirstlane(sstep[1 + s]);
+          if (st == kStepAbsent) {
+            const T f1 = inv1 ? (T)NAN : (T)0, f2 = inv2 ? (T)NAN : (T)0;
+            lum = fma((double)f1, (double)f2, lum);
+            continue;
+          }
+          const T* g1 = grid + b1 + (st & 0xFFFF);
+          const T* g2 = grid + b2 + (st & 0xFFFF);
+          T f1[kGW], f2[kGW];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            T u1[4][kGW], u2[4][kGW];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const V q1 = *reinterpret_cast<const V*>(g1 + a * sa1 + b * P);
+              const V q2v = *reinterpret_cast<const V*>(g2 + a * sa2 + b * P);
+              __builtin_memcpy(u1[a], &q1, sizeof(V));
+              __builtin_memcpy(u2[a], &q2v, sizeof(V));
+            }
+#pragma unroll
+            for (int i = 0; i < kGW; ++i) {
+              f1[i] = stencil_step<T>(b, f1[i], u1[0][i], u1[1][i], u1[2][i], u1[3][i], w1, v);
+              f2[i] = stencil_step<T>(b, f2[i], u2[0][i], u2[1][i], u2[2][i], u2[3][i], w2, v);
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < kGW; ++i) {
+            f1[i] = inv1 ? (T)NAN : f1[i];
+            f2[i] = inv2 ? (T)NAN : f2[i];
+          }
+          const int nt = (st >> 16) & 7;
+          if (st & kStepOrdered) {
+#pragma unroll
+            for (int t = 0; t < kGW; ++t)
+              if (t < nt) lum = fma((double)f1[t], (double)f2[t], lum);
+          } else {
+#pragma unroll
+            for (int t = 0; t < kGW; ++t)
+              if (t < nt) {
+                const int e = (st >> (20 + 2 * t)) & 3;
+                lum = fma((double)mc_pick<T, kGW>(f1, e), (double)mc_pick<T, kGW>(f2, e), lum);
+              }
+          }
+        }
+      } else if (kLdsGrid && kGW == 1 && !((L1.mode | L2.mode) & (kLowX | kLowQ | kHighQ))) {
         // both lookups inside the LDS-staged grid: the values mc_value gives,
         // with both stencils' reads issued together and no branch per point
         // (an invalid point reads the in-bounds stencil at offset 0 and takes
@@ -906,7 +1020,7 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
 size_t mc_fused_shared_bytes(const MemberDev& m, const AlphasDev& A, int64_t grid_elems, bool f32) {
   const size_t an2 = (size_t)((A.n + 1) & ~1);
   return (size_t)m.tbl_bytes + an2 * (8 + 8 + sizeof(CellCoef)) + (size_t)((A.nhints + 7) & ~7) * 2 +
-         kMcFusedBS * 8 + (kMaxReq + kMaxSub) * 4 +
+         kMcFusedBS * 8 + (2 * kMaxReq + kMaxSub + 4) * 4 +
          (size_t)grid_elems * (f32 ? 4 : 8);
 }
 
@@ -916,24 +1030,32 @@ hipError_t launch_mc_fused(const MemberDev& m, const ReqCols& rc, const AlphasDe
                            unsigned long long* nerr, double invL01, int n_cu, hipStream_t s) {
   const int64_t np = mc_partials(n);
   if (np > 0) {
-    int64_t elems = 0;
-    for (int k = 0; k < m.K; ++k) elems += (int64_t)m.sub[k].nxp * m.sub[k].nqp * m.P;
+    constexpr int kGW = sizeof(T) == 4 ? 4 : 1;  // column groups in FP32 only
+    const int Pg = (m.P + kGW - 1) & ~(kGW - 1);
+    int64_t rows = 0;
+    for (int k = 0; k < m.K; ++k) rows += (int64_t)m.sub[k].nxp * m.sub[k].nqp;
     const bool f32 = sizeof(T) == 4;
-    const size_t lds_all = mc_fused_shared_bytes(m, A, elems, f32);
-    const bool lds = lds_all <= 160 * 1024;
-    const size_t shm = lds ? lds_all : mc_fused_shared_bytes(m, A, 0, f32);
-    const void* fn = lds ? reinterpret_cast<const void*>(&k_mc_fused<T, true>)
-                         : reinterpret_cast<const void*>(&k_mc_fused<T, false>);
+    // grid in LDS in column groups, else in LDS with stride P, else in global memory
+    const size_t lds_g = mc_fused_shared_bytes(m, A, rows * Pg, f32);
+    const size_t lds_1 = mc_fused_shared_bytes(m, A, rows * m.P, f32);
+    const int mode = kGW > 1 && lds_g <= 160 * 1024 ? 2 : (lds_1 <= 160 * 1024 ? 1 : 0);
+    const size_t shm = mode == 2 ? lds_g : (mode == 1 ? lds_1 : mc_fused_shared_bytes(m, A, 0, f32));
+    const void* fn = mode == 2   ? reinterpret_cast<const void*>(&k_mc_fused<T, true, kGW>)
+                     : mode == 1 ? reinterpret_cast<const void*>(&k_mc_fused<T, true, 1>)
+                                 : reinterpret_cast<const void*>(&k_mc_fused<T, false, 1>);
     hipError_t e = allow_dynamic_lds(fn, shm);
     if (e != hipSuccess) return e;
     const int per_cu = max(1, (int)(160 * 1024 / shm));
     const int64_t nb = min((np + 3) / 4, (int64_t)n_cu * per_cu);
-    if (lds)
-      hipLaunchKernelGGL((k_mc_fused<T, true>), dim3((unsigned)nb), dim3(kMcFusedBS), shm, s, m, rc, A, x1, x2, q2, n,
-                         partial, nerr, invL01);
+    if (mode == 2)
+      hipLaunchKernelGGL((k_mc_fused<T, true, kGW>), dim3((unsigned)nb), dim3(kMcFusedBS), shm, s, m, rc, A, x1, x2,
+                         q2, n, partial, nerr, invL01);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_mc_fused<T, true, 1>), dim3((unsigned)nb), dim3(kMcFusedBS), shm, s, m, rc, A, x1, x2,
+                         q2, n, partial, nerr, invL01);
     else
-      hipLaunchKernelGGL((k_mc_fused<T, false>), dim3((unsigned)nb), dim3(kMcFusedBS), shm, s, m, rc, A, x1, x2, q2,
-                         n, partial, nerr, invL01);
+      hipLaunchKernelGGL((k_mc_fused<T, false, 1>), dim3((unsigned)nb), dim3(kMcFusedBS), shm, s, m, rc, A, x1, x2,
+                         q2, n, partial, nerr, invL01);
   }
   hipLaunchKernelGGL(k_mc_final, dim3(1), dim3(kMcThreads), 0, s, partial, np, sum_out);
   return hipGetLastError();

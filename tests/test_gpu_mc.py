@@ -78,9 +78,10 @@ def test_mc_full_chunk_sampled():
         pdfmi.unload(m)
 
 
-def _mixed_chunk(n, seed):
+def _mixed_chunk(n, seed, invalid=True):
     """config-5 points with a share moved outside the grid in x and Q^2 (all
-    extrapolation regions) and a few invalid points."""
+    extrapolation regions) and, with ``invalid``, a few invalid points (whose
+    NaN values make the chunk sum NaN)."""
     x1, x2, q2 = synth.config5_chunk(1, n=n)
     x1, x2, q2 = x1.copy(), x2.copy(), q2.copy()
     rng = np.random.default_rng(seed)
@@ -92,14 +93,14 @@ def _mixed_chunk(n, seed):
     q2[c] = np.exp(rng.uniform(np.log(2e8), np.log(1e10), len(c)))    # above Q^2_max
     x2[d] = np.exp(rng.uniform(np.log(1e-8), np.log(1e-6), len(d)))   # corner with some of the above
     q2[d] = np.exp(rng.uniform(np.log(0.5), np.log(2.0), len(d)))
-    if n > 10:
+    if invalid and n > 10:
         x1[3], q2[5], x2[7] = -1.0, np.nan, 1.5
     return x1, x2, q2
 
 
 @pytest.mark.parametrize("n", [1, 4095, 4097, 16385, 200_000, 1_000_000])
 @pytest.mark.parametrize("f32", [False, True])
-@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("mixed", ["none", "extrap", "invalid"])
 @pytest.mark.parametrize("pids", ["p13", "all"])
 def test_fused_equals_unfused(n, f32, mixed, pids):
     g = synth.config1_grid()
@@ -108,7 +109,10 @@ def test_fused_equals_unfused(n, f32, mixed, pids):
     pdfmi.load_alphas(qk, a)
     plist = PIDS if pids == "p13" else list(g.pids)
     try:
-        x1, x2, q2 = _mixed_chunk(n, 9) if mixed else synth.config5_chunk(2, n=n)
+        if mixed == "none":
+            x1, x2, q2 = synth.config5_chunk(2, n=n)
+        else:
+            x1, x2, q2 = _mixed_chunk(n, 9, invalid=mixed == "invalid")
         d1, d2, dq = dev(x1), dev(x2), dev(q2)
         ev = pdfmi.xfxq2_f32 if f32 else pdfmi.xfxq2
         pdfmi.error_count(reset=True)
@@ -120,6 +124,7 @@ def test_fused_equals_unfused(n, f32, mixed, pids):
         e = pdfmi.error_count(reset=True)
         assert s.view(np.uint64)[0] == s_ref.view(np.uint64)[0], (s, s_ref)
         assert e == e_ref
+        assert np.isnan(s[0]) == (mixed == "invalid" and n > 10)
     finally:
         pdfmi.unload(m)
 
@@ -155,6 +160,78 @@ def test_fused_large_grid_reads_global():
             s_ref = pdfmi.mc_chunk_sum(ev(m, g.pids, d1, dq), ev(m, g.pids, d2, dq), pdfmi.alphas_q2(dq)).cpu().numpy()
             s = pdfmi.mc_fused(m, g.pids, d1, d2, dq, f32=f32).cpu().numpy()
             assert s.view(np.uint64)[0] == s_ref.view(np.uint64)[0], (f32, s, s_ref)
+    finally:
+        pdfmi.unload(m)
+
+
+# Requests whose stored columns fall into the 16-byte column groups of the
+# LDS-staged grid in every way: whole groups in order, groups entered at an
+# odd column, reversed order, a column repeated (0 and 21 are both the gluon),
+# absent flavours between stored ones, single flavours.
+GROUP_REQUESTS = {
+    "reversed": PIDS[::-1],
+    "odd_start": [-4, -3, -2, -1, 21, 1, 2],
+    "repeat": [21, 0, 21, 1, 1, -1],
+    "absent_between": [-5, 6, -4, -3, -6, -2, -6, -1],
+    "swapped_pairs": [-4, -5, -2, -3, 21, -1, 2, 1],
+    "single": [3],
+    "single_absent": [6],
+}
+
+
+@pytest.mark.parametrize("name", sorted(GROUP_REQUESTS))
+@pytest.mark.parametrize("f32", [False, True])
+def test_fused_column_group_requests(name, f32):
+    """The fused sum reads the staged grid a column group at a time and
+    applies the request's flavours in request order: bit-identical to the
+    unfused calls for every way a request can fall into the groups, with
+    extrapolated and invalid points mixed in."""
+    g = synth.config1_grid()
+    qk, a = synth.config1_alphas()
+    m = pdfmi.load_synth(g)
+    pdfmi.load_alphas(qk, a)
+    plist = GROUP_REQUESTS[name]
+    try:
+        ev = pdfmi.xfxq2_f32 if f32 else pdfmi.xfxq2
+        for invalid in (False, True):
+            x1, x2, q2 = _mixed_chunk(20_000, 17, invalid=invalid)
+            d1, d2, dq = dev(x1), dev(x2), dev(q2)
+            s_ref = pdfmi.mc_chunk_sum(ev(m, plist, d1, dq), ev(m, plist, d2, dq),
+                                       pdfmi.alphas_q2(dq)).cpu().numpy()
+            s = pdfmi.mc_fused(m, plist, d1, d2, dq, f32=f32).cpu().numpy()
+            assert s.view(np.uint64)[0] == s_ref.view(np.uint64)[0], (invalid, s, s_ref)
+            # an invalid point's values are NaN, also for flavours absent from the grid
+            assert np.isnan(s[0]) == invalid
+            assert invalid or name == "single_absent" or s[0] != 0.0
+    finally:
+        pdfmi.unload(m)
+
+
+def test_fused_unpadded_lds_rows():
+    """A 60 x 53-knot, 11-flavour grid: in FP32 its rows padded to 12 columns
+    (152.6 KB) and the other LDS contents exceed 160 KB, rows of 11 columns
+    (139.9 KB) do not, so the fused kernel reads one column at a time from
+    the grid staged in LDS; in FP64 the grid (280 KB) is read from global
+    memory.  Both bit-identical to the unfused calls."""
+    g = synth.tiny_grid(np.random.default_rng(60), K=1, nx=60, nq=53, npid=11)
+    qk, a = synth.config1_alphas()
+    m = pdfmi.load_synth(g)
+    pdfmi.load_alphas(qk, a)
+    try:
+        r = np.random.default_rng(5)
+        n = 30_000
+        lx0 = np.log(g.xknots[0][0])
+        x1 = np.exp(r.uniform(lx0 - 1.0, 0.0, n))
+        x2 = np.exp(r.uniform(lx0 - 1.0, 0.0, n))
+        q2 = np.exp(r.uniform(np.log(g.q2knots[0][0]) - 0.5, np.log(g.q2knots[0][-1]) + 0.5, n))
+        d1, d2, dq = dev(x1), dev(x2), dev(q2)
+        for f32 in (False, True):
+            for plist in (list(g.pids), [int(p) for p in g.pids[::-1]] + [0]):
+                ev = pdfmi.xfxq2_f32 if f32 else pdfmi.xfxq2
+                s_ref = pdfmi.mc_chunk_sum(ev(m, plist, d1, dq), ev(m, plist, d2, dq),
+                                           pdfmi.alphas_q2(dq)).cpu().numpy()
+                s = pdfmi.mc_fused(m, plist, d1, d2, dq, f32=f32).cpu().numpy()
+                assert s.view(np.uint64)[0] == s_ref.view(np.uint64)[0], (f32, plist, s, s_ref)
     finally:
         pdfmi.unload(m)
 
