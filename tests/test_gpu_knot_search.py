@@ -180,13 +180,18 @@ def coord_sensitivity(g, x, q2, h=1e-9):
 
 
 def cell_L(g, k, ix, iq, x, q2):
-    """(1 + |ln x|) / Delta_x + (1 + |ln Q^2|) / Delta_Q of each point's own cells."""
+    """(1 + |ln x|) / Delta_x + (1 + |ln Q^2|) / Delta_Q of each point's own
+    cells, Delta the log of the ratio of the cell's knots (as the cell
+    parameter is formed): finite also for knots one ulp apart, where the
+    difference of the two rounded logs is zero."""
     L = np.zeros(len(x))
     for i in range(len(x)):
         if k[i] < 0:
             continue
-        tx, tq = np.log(g.xknots[k[i]]), np.log(g.q2knots[k[i]])
-        L[i] = (1 + abs(np.log(x[i]))) / (tx[ix[i] + 1] - tx[ix[i]]) + (1 + abs(np.log(q2[i]))) / (tq[iq[i] + 1] - tq[iq[i]])
+        tx, tq = g.xknots[k[i]], g.q2knots[k[i]]
+        dx = np.log(tx[ix[i] + 1] / tx[ix[i]])
+        dq = np.log(tq[iq[i] + 1] / tq[iq[i]])
+        L[i] = (1 + abs(np.log(x[i]))) / dx + (1 + abs(np.log(q2[i]))) / dq
     return L
 
 
