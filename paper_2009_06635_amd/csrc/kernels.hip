@@ -921,6 +921,8 @@ __global__ __launch_bounds__(kMcFusedBS) void k_mc_fused(MemberDev m, ReqCols rc
           }
           const T* g1 = grid + b1 + (st & 0xFFFF);
           const T* g2 = grid + b2 + (st & 0xFFFF);
+          // the stencils Q^2 row by Q^2 row (interp_stencil's steps): one
+          // row's reads of both lookups in flight at a time
           T f1[kGW], f2[kGW];
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
