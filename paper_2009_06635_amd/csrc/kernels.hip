@@ -737,10 +737,12 @@ hipError_t launch_mc_sum(const T* xf1, const T* xf2, int P, const double* as, in
 // request: a step reads one group and applies the terms of the next 1..kGW
 // requested flavours whose columns fall in it, in request order, so the sum
 // is still formed flavour by flavour in that order; a flavour absent from the
-// grid is a step of its own with no read.  Otherwise (and in FP64, where
-// column pairs measured slower: a pair's 16 reads per lookup do not fit in
-// flight beside the rest of the point's registers) the rows keep stride P
-// and each requested column is read on its own (kGW = 1).
+// grid is a step of its own with no read.  Otherwise the rows keep stride P
+// and each requested column is read on its own (kGW = 1), as in FP64: pairs
+// of FP64 columns measured no faster than single 8-byte reads (with rows of
+// 12 columns every stencil row starts on a 32-byte boundary and the reads of
+// one instruction use half of the banks; padding the x stride by 16 bytes
+// against that brought the pairs level with single reads, not below).
 constexpr int kMcFusedBS = 4 * kMcThreads;
 constexpr int kStepAbsent = -1;   // a step whose flavour is absent from the grid
 constexpr int kStepOrdered = 1 << 19;  // the step's terms are the group's columns 0, 1, ... in order
