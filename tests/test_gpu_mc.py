@@ -176,6 +176,7 @@ GROUP_REQUESTS = {
     "swapped_pairs": [-4, -5, -2, -3, 21, -1, 2, 1],
     "single": [3],
     "single_absent": [6],
+    "max_request": (PIDS * 5)[:64],  # the most flavours one call takes: every step slot in use
 }
 
 
