@@ -261,8 +261,9 @@ def test_chunk_sum_any_width(P, f32):
 
 def test_full_workload_fused_equals_unfused():
     """The benchmarked load: 100 chunks of 1e6 points (1e8 points), every
-    chunk sum of the fused kernel bit-identical to the unfused calls (FP64),
-    and the total within the summation bound of the oracle on three chunks."""
+    chunk sum of the fused kernel bit-identical to the unfused calls, FP64
+    and FP32 (whose fused kernel reads four flavours per LDS access), and the
+    FP64 total within the summation bound of the oracle on three chunks."""
     g = synth.config1_grid()
     qk, a = synth.config1_alphas()
     m = pdfmi.load_synth(g)
@@ -270,20 +271,23 @@ def test_full_workload_fused_equals_unfused():
     try:
         n = 1_000_000
         ws = pdfmi.mc_workspace(n, DEV)
-        f1 = torch.empty((n, len(PIDS)), dtype=torch.float64, device=DEV)
-        f2 = torch.empty_like(f1)
+        f = {dt: (torch.empty((n, len(PIDS)), dtype=dt, device=DEV), torch.empty((n, len(PIDS)), dtype=dt, device=DEV))
+             for dt in (torch.float64, torch.float32)}
         al = torch.empty(n, dtype=torch.float64, device=DEV)
-        unf = torch.empty(100, dtype=torch.float64, device=DEV)
-        fus = torch.empty(100, dtype=torch.float64, device=DEV)
+        unf = {k: torch.empty(100, dtype=torch.float64, device=DEV) for k in ("f64", "f32")}
+        fus = {k: torch.empty(100, dtype=torch.float64, device=DEV) for k in ("f64", "f32")}
         for c in range(100):
             x1, x2, q2 = (dev(v) for v in synth.config5_chunk(c))
-            pdfmi.xfxq2(m, PIDS, x1, q2, out=f1)
-            pdfmi.xfxq2(m, PIDS, x2, q2, out=f2)
             pdfmi.alphas_q2(q2, out=al)
-            pdfmi.mc_chunk_sum(f1, f2, al, workspace=ws, out=unf[c:c + 1])
-            pdfmi.mc_fused(m, PIDS, x1, x2, q2, workspace=ws, out=fus[c:c + 1])
-        assert torch.equal(unf.view(torch.int64), fus.view(torch.int64))
-        got = fus.cpu().numpy()
+            for key, dt, ev in (("f64", torch.float64, pdfmi.xfxq2), ("f32", torch.float32, pdfmi.xfxq2_f32)):
+                f1, f2 = f[dt]
+                ev(m, PIDS, x1, q2, out=f1)
+                ev(m, PIDS, x2, q2, out=f2)
+                pdfmi.mc_chunk_sum(f1, f2, al, workspace=ws, out=unf[key][c:c + 1])
+                pdfmi.mc_fused(m, PIDS, x1, x2, q2, f32=(key == "f32"), workspace=ws, out=fus[key][c:c + 1])
+        for key in ("f64", "f32"):
+            assert torch.equal(unf[key].view(torch.int64), fus[key].view(torch.int64)), key
+        got = fus["f64"].cpu().numpy()
         for c in (0, 57, 99):
             s, absum = oracle_chunk(g, qk, a, *synth.config5_chunk(c))
             assert abs(got[c] - s) <= 1e-11 * absum, c
