@@ -36,7 +36,8 @@ def check_f64(gpu, ora, scale, L, rtol=1e-12, c=4.0):
     gpu = np.asarray(gpu, np.float64)
     both_nan = np.isnan(gpu) & np.isnan(ora)
     same_inf = np.isinf(ora) & (gpu == ora)  # an extrapolation beyond the FP64 range, on both sides
-    diff = np.abs(gpu - ora)
+    with np.errstate(invalid="ignore"):  # inf - inf where both overflowed: taken by same_inf
+        diff = np.abs(gpu - ora)
     ok = both_nan | same_inf | (diff <= rtol * np.abs(ora) + c * EPS64 * scale * (1.0 + L))
     finite = np.isfinite(ora)
     lit = both_nan | same_inf | (diff <= rtol * np.abs(ora))
@@ -47,7 +48,8 @@ def check_f64(gpu, ora, scale, L, rtol=1e-12, c=4.0):
 def check_f32(gpu, ora, scale, rtol=1e-5, floor=1e-8, c=4.0):
     gpu = np.asarray(gpu, np.float64)
     both_nan = np.isnan(gpu) & np.isnan(ora)
-    diff = np.abs(gpu - ora)
+    with np.errstate(invalid="ignore"):  # inf - inf beyond the FP32 range: taken by `over` below
+        diff = np.abs(gpu - ora)
     small = np.abs(ora) <= floor
     # a value at or beyond the top of the FP32 range is the infinity of its sign in
     # FP32 arithmetic (round-to-nearest overflow), which no relative bound expresses
